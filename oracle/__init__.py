@@ -1,0 +1,176 @@
+"""FP64 CPU oracle for normalize (arXiv 2207.00257, Fig. 1, Sec. II-A, Sec. IV-C).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product path. It shares no code
+with the HIP library. The arithmetic lives in normalize_oracle.c (plain C,
+binary64); this module only loads it with ctypes and marshals numpy arrays.
+
+Functions (all return float64 arrays):
+  normalize(x)                 hoisted form: S = sum once, out = x / S
+  normalize_naive(x)           Fig. 1 as printed: every thread recomputes S
+  normalize_perblock(x, B)     shared-memory variant: one S per block of B
+  normalize_batched(x, offs)   each CSR row [offs[r], offs[r+1]) on its own
+  decode(x)                    exact widening of FP32 / BF16 / FP16 storage
+  round_bf16(y)                binary64 -> nearest bfloat16 (ties to even)
+
+Inputs: numpy float32 arrays, or uint16 arrays holding BF16 / FP16 bit
+patterns with dtype="bf16" / "f16".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "normalize_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+
+
+def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH) -> str:
+    """Compile the oracle with gcc: binary64 as written (no fast-math, no
+    contraction of a*b+c into fma)."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def _bind(lib):
+    i64, p, d = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+    lib.oracle_decode.argtypes = [p, ctypes.c_int, i64, p]
+    lib.oracle_sum.argtypes = [p, ctypes.c_int, i64]
+    lib.oracle_sum.restype = d
+    lib.oracle_normalize.argtypes = [p, ctypes.c_int, i64, p, p]
+    lib.oracle_normalize_naive.argtypes = [p, ctypes.c_int, i64, p]
+    lib.oracle_normalize_perblock.argtypes = [p, ctypes.c_int, i64, i64, p]
+    lib.oracle_normalize_batched.argtypes = [p, ctypes.c_int, p, i64, p, p]
+    lib.oracle_round_bf16.argtypes = [p, i64, p]
+    lib.oracle_round_bf16_one.argtypes = [d]
+    lib.oracle_round_bf16_one.restype = ctypes.c_uint16
+    for name in ("oracle_decode", "oracle_normalize", "oracle_normalize_naive",
+                 "oracle_normalize_perblock", "oracle_normalize_batched", "oracle_round_bf16"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+def _prep(x, dtype):
+    if dtype not in DTYPES:
+        raise ValueError("dtype must be one of %s" % list(DTYPES))
+    want = np.float32 if dtype == "f32" else np.uint16
+    x = np.ascontiguousarray(x)
+    if x.dtype != want:
+        raise TypeError("dtype %s needs a %s array, got %s" % (dtype, np.dtype(want), x.dtype))
+    return x.reshape(-1)
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments (status %d)" % rc)
+
+
+class Oracle:
+    """The oracle's entry points bound to one compiled copy of the C source."""
+
+    def __init__(self, lib_path: str):
+        self.lib = _bind(ctypes.CDLL(lib_path))
+
+    def decode(self, x, dtype="f32"):
+        x = _prep(x, dtype)
+        out = np.empty(x.size, np.float64)
+        _check(self.lib.oracle_decode(x.ctypes.data, DTYPES[dtype], x.size, out.ctypes.data))
+        return out
+
+    def sum(self, x, dtype="f32"):
+        x = _prep(x, dtype)
+        return float(self.lib.oracle_sum(x.ctypes.data, DTYPES[dtype], x.size))
+
+    def normalize(self, x, dtype="f32", return_sum=False):
+        x = _prep(x, dtype)
+        out = np.empty(x.size, np.float64)
+        s = ctypes.c_double(0.0)
+        _check(self.lib.oracle_normalize(x.ctypes.data, DTYPES[dtype], x.size, out.ctypes.data,
+                                         ctypes.byref(s)))
+        return (out, s.value) if return_sum else out
+
+    def normalize_naive(self, x, dtype="f32"):
+        x = _prep(x, dtype)
+        out = np.empty(x.size, np.float64)
+        _check(self.lib.oracle_normalize_naive(x.ctypes.data, DTYPES[dtype], x.size,
+                                               out.ctypes.data))
+        return out
+
+    def normalize_perblock(self, x, block, dtype="f32"):
+        x = _prep(x, dtype)
+        out = np.empty(x.size, np.float64)
+        _check(self.lib.oracle_normalize_perblock(x.ctypes.data, DTYPES[dtype], x.size, int(block),
+                                                  out.ctypes.data))
+        return out
+
+    def normalize_batched(self, x, offsets, dtype="f32", return_sums=False):
+        x = _prep(x, dtype)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64).reshape(-1)
+        if offs.size < 1:
+            raise ValueError("offsets needs rows + 1 >= 1 entries")
+        rows = offs.size - 1
+        if rows > 0 and offs[-1] > x.size:
+            raise ValueError("offsets run past the input")
+        out = np.full(x.size, np.nan, np.float64)
+        sums = np.empty(max(rows, 1), np.float64)
+        _check(self.lib.oracle_normalize_batched(x.ctypes.data, DTYPES[dtype], offs.ctypes.data,
+                                                 rows, out.ctypes.data, sums.ctypes.data))
+        return (out, sums[:rows]) if return_sums else out
+
+    def round_bf16(self, y):
+        y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
+        out = np.empty(y.size, np.uint16)
+        _check(self.lib.oracle_round_bf16(y.ctypes.data, y.size, out.ctypes.data))
+        return out
+
+    def round_bf16_one(self, v: float) -> int:
+        return int(self.lib.oracle_round_bf16_one(float(v)))
+
+
+_default = None
+
+
+def _get() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle(build())
+    return _default
+
+
+def decode(x, dtype="f32"):
+    return _get().decode(x, dtype)
+
+
+def sum_(x, dtype="f32"):
+    return _get().sum(x, dtype)
+
+
+def normalize(x, dtype="f32", return_sum=False):
+    return _get().normalize(x, dtype, return_sum)
+
+
+def normalize_naive(x, dtype="f32"):
+    return _get().normalize_naive(x, dtype)
+
+
+def normalize_perblock(x, block, dtype="f32"):
+    return _get().normalize_perblock(x, block, dtype)
+
+
+def normalize_batched(x, offsets, dtype="f32", return_sums=False):
+    return _get().normalize_batched(x, offsets, dtype, return_sums)
+
+
+def round_bf16(y):
+    return _get().round_bf16(y)

@@ -1,0 +1,56 @@
+"""Planted mistakes in copies of the oracle must each fail at least one pin.
+
+Each mutation is a plausible slip (a dropped term, a wrong index, a transposed
+operand, a wrong sign or bias, single-precision accumulation, a rounding rule)
+applied to a temporary copy of oracle/normalize_oracle.c, compiled with the
+same flags. The real oracle source is never modified.
+"""
+import os
+
+import pytest
+
+import oracle
+from oracle_pins import ALL_PINS
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "normalize_oracle.c")
+
+MUTATIONS = {
+    "dropped_first_term": ("for (int64_t j = begin; j < end; ++j)", "for (int64_t j = begin + 1; j < end; ++j)"),
+    "dropped_last_term": ("for (int64_t j = begin; j < end; ++j)", "for (int64_t j = begin; j < end - 1; ++j)"),
+    "reversed_index": ("for (int64_t i = 0; i < n; ++i) out[i] = load(in, dtype, i) / s;",
+                       "for (int64_t i = 0; i < n; ++i) out[i] = load(in, dtype, n - 1 - i) / s;"),
+    "transposed_divide": ("for (int64_t i = 0; i < n; ++i) out[i] = load(in, dtype, i) / s;",
+                          "for (int64_t i = 0; i < n; ++i) out[i] = s / load(in, dtype, i);"),
+    "float_accumulator": ("  double s = 0.0;\n  for (int64_t j", "  float s = 0.0f;\n  for (int64_t j"),
+    "bf16_lost_sign": ("    v = ldexp(128.0 + (double)f, e - 127 - 7);\n  }\n  return s ? -v : v;",
+                       "    v = ldexp(128.0 + (double)f, e - 127 - 7);\n  }\n  return v;"),
+    "bf16_wrong_bias": ("e - 127 - 7", "e - 126 - 7"),
+    "bf16_subnormal_scale": ("ldexp((double)f, -126 - 7)", "ldexp((double)f, -127 - 7)"),
+    "f16_subnormal_scale": ("ldexp((double)f, -14 - 10)", "ldexp((double)f, -15 - 10)"),
+    "round_ties_away": ("else kr = fmod(kf, 2.0) == 0.0 ? kf : kf + 1.0;", "else kr = kf + 1.0;"),
+    "round_truncates": ("if (rem > 0.5) kr = kf + 1.0;", "if (rem > 2.0) kr = kf + 1.0;"),
+    "batched_sum_from_zero": ("double s = e > b ? sum_seq(in, dtype, b, e) : 0.0;",
+                              "double s = e > b ? sum_seq(in, dtype, 0, e) : 0.0;"),
+    "naive_skips_last": ("if (tid < n) out[tid] = load(in, dtype, tid) / val;",
+                         "if (tid < n - 1) out[tid] = load(in, dtype, tid) / val;\n      else if (tid < n) out[tid] = 0.0;"),
+    "perblock_wrong_range": ("double shared_val = sum_seq(in, dtype, 0, n);",
+                             "double shared_val = sum_seq(in, dtype, b * block, n);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(tmp_path, name):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert old in src, "mutation site vanished from the oracle source: %s" % name
+    mutated = tmp_path / "mutated.c"
+    mutated.write_text(src.replace(old, new, 1))
+    lib = oracle.build(force=True, src=str(mutated), out=str(tmp_path / ("lib_%s.so" % name)))
+    orc = oracle.Oracle(lib)
+    failed = []
+    for pin in ALL_PINS:
+        try:
+            pin(orc)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, "planted mistake %r passed every pin" % name

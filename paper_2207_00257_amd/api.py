@@ -1,0 +1,107 @@
+"""Python binding of libnrm.so: argument marshalling only.
+
+Every step of normalize runs in the library's HIP kernels. torch provides the
+device memory (tensors) and the stream (the current stream of the tensor's
+device); this module passes their raw pointers through the C ABI.
+
+    normalize(out, inp)               out = inp / inp.sum(), FP32 or BF16/FP16
+    Context(...).normalize(out, inp)  with launch parameters and timing
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+from . import _lib as L
+
+_ACCUM = {"f32": L.NRM_ACC_F32, "kahan": L.NRM_ACC_KAHAN}
+
+
+def _dtype_code(t) -> int:
+    import torch
+
+    codes = {torch.float32: L.NRM_F32, torch.bfloat16: L.NRM_BF16, torch.float16: L.NRM_F16}
+    if t.dtype not in codes:
+        raise TypeError("unsupported dtype %s (float32, bfloat16, float16)" % t.dtype)
+    return codes[t.dtype]
+
+
+def _stream_of(t) -> int:
+    import torch
+
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _check_tensors(out, inp):
+    if not inp.is_cuda or not out.is_cuda:
+        raise ValueError("normalize needs device tensors (the library has no CPU path)")
+    if inp.device != out.device:
+        raise ValueError("in and out are on different devices")
+    if not inp.is_contiguous() or not out.is_contiguous():
+        raise ValueError("in and out must be contiguous")
+    if inp.numel() != out.numel():
+        raise ValueError("in and out differ in length")
+
+
+class Context:
+    """An nrm_ctx: owns device workspace and launch parameters."""
+
+    def __init__(self, device: int = -1, **params):
+        h = ctypes.c_void_p()
+        L.check(L.lib().nrm_create(ctypes.byref(h), int(device)), "nrm_create")
+        self.handle = h
+        if params:
+            self.set_params(**params)
+
+    def close(self) -> None:
+        if self.handle:
+            L.check(L.lib().nrm_destroy(self.handle), "nrm_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> dict:
+        p = L.NrmParams()
+        L.check(L.lib().nrm_get_params(self.handle, ctypes.byref(p)), "nrm_get_params")
+        return {f: getattr(p, f) for f, _ in L.NrmParams._fields_ if f != "reserved"}
+
+    def set_params(self, **kw) -> None:
+        cur = self.get_params()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise ValueError("unknown parameters %s" % sorted(unknown))
+        cur.update(kw)
+        p = L.NrmParams(**cur)
+        L.check(L.lib().nrm_set_params(self.handle, ctypes.byref(p)), "nrm_set_params")
+
+    def normalize(self, out, inp, accum: str = "f32", stream: Optional[int] = None):
+        return normalize(out, inp, accum=accum, ctx=self, stream=stream)
+
+    def set_timing(self, enable: bool) -> None:
+        L.check(L.lib().nrm_set_timing(self.handle, int(bool(enable))), "nrm_set_timing")
+
+    def kernel_times(self):
+        """(reduce_ms, map_ms, calls) summed over the calls recorded since timing was enabled."""
+        r, m, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        L.check(L.lib().nrm_kernel_times(self.handle, ctypes.byref(r), ctypes.byref(m), ctypes.byref(c)),
+                "nrm_kernel_times")
+        return r.value, m.value, c.value
+
+
+def normalize(out, inp, accum: str = "f32", ctx: Optional[Context] = None, stream: Optional[int] = None):
+    """out[i] = inp[i] / sum(inp) on the device, enqueued on the current stream.
+
+    inp: float32 / bfloat16 / float16 device tensor; out: same length, any of
+    those dtypes (out may be inp itself). accum: "f32" or "kahan"."""
+    _check_tensors(out, inp)
+    if accum not in _ACCUM:
+        raise ValueError("accum must be 'f32' or 'kahan'")
+    s = _stream_of(inp) if stream is None else stream
+    st = L.lib().nrm_normalize_ex(ctx.handle if ctx else None, out.data_ptr(), _dtype_code(out),
+                                  inp.data_ptr(), _dtype_code(inp), inp.numel(), _ACCUM[accum], s)
+    L.check(st, "nrm_normalize_ex")
+    return out

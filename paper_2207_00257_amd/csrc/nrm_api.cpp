@@ -1,0 +1,374 @@
+// C ABI of libnrm.so (declared in include/nrm.h): argument validation,
+// launch planning, contexts with their device workspace, and kernel timing.
+// All compute runs in the HIP kernels of nrm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nrm_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& what) {
+  g_last_error = what;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(NRM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kTimingRing = 1024;
+
+}  // namespace
+
+struct nrm_ctx {
+  int device = 0;
+  nrm_params params{};
+  // plain-path workspace
+  void* partials = nullptr;
+  int64_t partials_cap = 0;  // entries (each up to 8 bytes)
+  unsigned* ticket = nullptr;
+  float* sum = nullptr;      // 2 floats
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // 3 per recorded call
+  int64_t timed_calls = 0;
+};
+
+namespace {
+
+nrm_params default_params() {
+  nrm_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.block = 256;
+  p.unroll = 4;
+  p.map_unroll = 4;
+  p.grid = 2048;
+  p.map_grid = 2048;
+  p.layout = NRM_LAYOUT_CHUNK;
+  p.max_chain = 32;
+  p.reverse_map = 0;
+  p.nt_loads = 1;
+  return p;
+}
+
+int check_params(const nrm_params& p) {
+  if (p.block < 64 || p.block > 1024 || p.block % 64) return fail(NRM_EINVAL, "block must be 64..1024, a multiple of 64");
+  auto ok_u = [](int u) { return u == 1 || u == 2 || u == 4 || u == 8; };
+  if (!ok_u(p.unroll) || !ok_u(p.map_unroll)) return fail(NRM_EINVAL, "unroll and map_unroll must be 1, 2, 4 or 8");
+  if (p.grid < 1 || p.map_grid < 1) return fail(NRM_EINVAL, "grid and map_grid must be positive");
+  if (p.layout != NRM_LAYOUT_CHUNK && p.layout != NRM_LAYOUT_STRIDE) return fail(NRM_EINVAL, "unknown layout");
+  if (p.max_chain < 1 || p.max_chain > 64) return fail(NRM_EINVAL, "max_chain must be 1..64");
+  if (p.reverse_map != 0 && p.reverse_map != 1) return fail(NRM_EINVAL, "reverse_map must be 0 or 1");
+  if (p.nt_loads != 0 && p.nt_loads != 1) return fail(NRM_EINVAL, "nt_loads must be 0 or 1");
+  return NRM_OK;
+}
+
+// Fill zero fields with defaults.
+nrm_params resolve(const nrm_params& in) {
+  nrm_params d = default_params(), p = in;
+  if (!p.block) p.block = d.block;
+  if (!p.unroll) p.unroll = d.unroll;
+  if (!p.map_unroll) p.map_unroll = d.map_unroll;
+  if (!p.grid) p.grid = d.grid;
+  if (!p.map_grid) p.map_grid = d.map_grid;
+  if (!p.max_chain) p.max_chain = d.max_chain;
+  if (p.nt_loads == 2) p.nt_loads = d.nt_loads;
+  return p;
+}
+
+std::mutex g_default_mu;
+std::map<int, nrm_ctx*> g_default;
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    hipGetDevice(&prev_);
+    if (prev_ != dev) hipSetDevice(dev);
+    dev_ = dev;
+  }
+  ~DeviceGuard() {
+    if (prev_ != dev_) hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = 0, dev_ = 0;
+};
+
+int ensure_partials(nrm_ctx* c, int64_t entries) {
+  if (entries <= c->partials_cap) return NRM_OK;
+  int64_t cap = std::max<int64_t>(entries, 16384);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, (size_t)cap * 8);
+  if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+  if (c->partials) {
+    hipError_t e2 = hipDeviceSynchronize();  // the old buffer may still be in use
+    hipFree(c->partials);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipDeviceSynchronize");
+  }
+  c->partials = p;
+  c->partials_cap = cap;
+  return NRM_OK;
+}
+
+int default_ctx(nrm_ctx** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  auto it = g_default.find(dev);
+  if (it != g_default.end()) {
+    *out = it->second;
+    return NRM_OK;
+  }
+  nrm_ctx* c = nullptr;
+  int st = nrm_create(&c, dev);
+  if (st != NRM_OK) return st;
+  g_default[dev] = c;
+  *out = c;
+  return NRM_OK;
+}
+
+bool valid_dtype(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Blocks and per-block chunk for `nvec` vectors in steps of `step` vectors,
+// at most `max_blocks` blocks unless `max_iters` per block forces more.
+void split(int64_t nvec, int64_t step, int64_t max_blocks, int64_t max_iters, int64_t* blocks,
+           int64_t* chunk) {
+  int64_t iters = ceil_div(nvec, step);
+  if (iters == 0) {
+    *blocks = 1;
+    *chunk = step;
+    return;
+  }
+  int64_t b = std::min(max_blocks, iters);
+  if (max_iters > 0) b = std::max(b, ceil_div(iters, max_iters));
+  int64_t per = ceil_div(iters, b);
+  *blocks = ceil_div(iters, per);
+  *chunk = per * step;
+}
+
+int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_dt, int64_t n,
+               int acc, nrm::PlainPlan* p) {
+  const nrm_params& q = c->params;
+  const int si = nrm::dtype_size(in_dt), so = nrm::dtype_size(out_dt);
+  const uintptr_t ai = reinterpret_cast<uintptr_t>(in), ao = reinterpret_cast<uintptr_t>(out);
+  if (ai % si) return fail(NRM_EINVAL, "in is not aligned to its element size");
+  if (ao % so) return fail(NRM_EINVAL, "out is not aligned to its element size");
+  const int vec = nrm::dtype_vec(in_dt);
+  p->in = in;
+  p->out = out;
+  p->n = n;
+  p->in_dt = in_dt;
+  p->out_dt = out_dt;
+  p->acc = acc;
+  int64_t mis = (int64_t)(ai & 15);
+  p->head = std::min<int64_t>(mis ? (16 - mis) / si : 0, n);
+  p->nvec = (n - p->head) / vec;
+  p->tail_begin = p->head + p->nvec * vec;
+  const int64_t out_align = std::min(16, vec * so);
+  p->vector_map = ((ao + (uintptr_t)(p->head * so)) % (uintptr_t)out_align) == 0;
+  p->block = q.block;
+  p->unroll = q.unroll;
+  p->map_unroll = q.map_unroll;
+  p->layout = q.layout;
+  p->reverse_map = q.reverse_map;
+  p->nt_loads = q.nt_loads;
+  // Bound the additions per accumulator chain by max_chain: this fixes the
+  // height of the summation tree, hence the worst-case error of the sum.
+  const int64_t max_iters =
+      std::max<int64_t>(1, q.max_chain / nrm::adds_per_iteration(in_dt, acc, q.unroll));
+  split(p->nvec, (int64_t)q.block * q.unroll, q.grid, max_iters, &p->grid, &p->chunk);
+  split(p->nvec, (int64_t)q.block * q.map_unroll, q.map_grid, 0, &p->map_grid, &p->map_chunk);
+  if (p->grid > INT32_MAX || p->map_grid > INT32_MAX) return fail(NRM_EINVAL, "n too large for one launch");
+  return NRM_OK;
+}
+
+bool ranges_partially_overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
+  uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)abytes;
+  uintptr_t b0 = (uintptr_t)b, b1 = b0 + (uintptr_t)bbytes;
+  bool overlap = a0 < b1 && b0 < a1;
+  bool identical = a0 == b0 && abytes == bbytes;
+  return overlap && !identical;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nrm_status_string(int status) {
+  switch (status) {
+    case NRM_OK: return "ok";
+    case NRM_EINVAL: return "invalid argument";
+    case NRM_EOVERLAP: return "input and output overlap without being the same array";
+    case NRM_ENOMEM: return "workspace allocation failed";
+    case NRM_EHIP: return "HIP runtime error";
+    case NRM_EUNSUPPORTED: return "unsupported dtype or mode";
+    case NRM_EDEVICE: return "the device reported invalid data";
+    default: return "unknown status";
+  }
+}
+
+const char* nrm_last_error(void) { return g_last_error.c_str(); }
+
+int nrm_create(nrm_ctx** ctx, int device) {
+  if (!ctx) return fail(NRM_EINVAL, "ctx is NULL");
+  *ctx = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0) {
+    e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  }
+  if (device >= count) return fail(NRM_EINVAL, "no such device");
+  DeviceGuard g(device);
+  nrm_ctx* c = new nrm_ctx();
+  c->device = device;
+  c->params = default_params();
+  void* small = nullptr;
+  e = hipMalloc(&small, 256);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(NRM_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+  }
+  e = hipMemset(small, 0, 256);
+  if (e != hipSuccess) {
+    hipFree(small);
+    delete c;
+    return hip_fail(e, "hipMemset");
+  }
+  c->ticket = static_cast<unsigned*>(small);
+  c->sum = reinterpret_cast<float*>(static_cast<char*>(small) + 128);
+  int st = ensure_partials(c, 16384);
+  if (st != NRM_OK) {
+    hipFree(small);
+    delete c;
+    return st;
+  }
+  *ctx = c;
+  return NRM_OK;
+}
+
+int nrm_destroy(nrm_ctx* c) {
+  if (!c) return NRM_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    for (auto it = g_default.begin(); it != g_default.end(); ++it)
+      if (it->second == c) return fail(NRM_EINVAL, "the default context cannot be destroyed");
+  }
+  DeviceGuard g(c->device);
+  hipDeviceSynchronize();
+  for (hipEvent_t ev : c->events) hipEventDestroy(ev);
+  if (c->partials) hipFree(c->partials);
+  if (c->ticket) hipFree(c->ticket);
+  delete c;
+  return NRM_OK;
+}
+
+int nrm_set_params(nrm_ctx* c, const nrm_params* params) {
+  if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  nrm_params p = resolve(*params);
+  int st = check_params(p);
+  if (st != NRM_OK) return st;
+  c->params = p;
+  return NRM_OK;
+}
+
+int nrm_get_params(const nrm_ctx* c, nrm_params* params) {
+  if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  *params = c->params;
+  return NRM_OK;
+}
+
+int nrm_set_timing(nrm_ctx* c, int enable) {
+  if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  if (enable && c->events.empty()) {
+    DeviceGuard g(c->device);
+    c->events.resize(3 * kTimingRing);
+    for (auto& ev : c->events) {
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+  }
+  c->timing = enable != 0;
+  c->timed_calls = 0;
+  return NRM_OK;
+}
+
+int nrm_kernel_times(nrm_ctx* c, double* reduce_ms, double* map_ms, int64_t* calls) {
+  if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  double r = 0, m = 0;
+  int64_t k = std::min<int64_t>(c->timed_calls, kTimingRing);
+  for (int64_t i = 0; i < k; ++i) {
+    hipEvent_t* ev = &c->events[3 * i];
+    hipError_t e = hipEventSynchronize(ev[2]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float a = 0, b = 0;
+    e = hipEventElapsedTime(&a, ev[0], ev[1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    e = hipEventElapsedTime(&b, ev[1], ev[2]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    r += a;
+    m += b;
+  }
+  if (reduce_ms) *reduce_ms = r;
+  if (map_ms) *map_ms = m;
+  if (calls) *calls = k;
+  return NRM_OK;
+}
+
+int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype, int64_t n,
+                     int accum, void* stream) {
+  if (n < 0) return fail(NRM_EINVAL, "n < 0");
+  if (!valid_dtype(in_dtype) || !valid_dtype(out_dtype)) return fail(NRM_EINVAL, "unknown dtype");
+  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
+  if (n == 0) return NRM_OK;
+  if (!in || !out) return fail(NRM_EINVAL, "NULL data pointer with n > 0");
+  const int64_t si = nrm::dtype_size(in_dtype), so = nrm::dtype_size(out_dtype);
+  if (n > INT64_MAX / 8) return fail(NRM_EINVAL, "n too large");
+  if (ranges_partially_overlap(in, n * si, out, n * so))
+    return fail(NRM_EOVERLAP, "in and out overlap without being the same array");
+  if (!c) {
+    int st = default_ctx(&c);
+    if (st != NRM_OK) return st;
+  }
+  nrm::PlainPlan plan;
+  int st = plan_plain(c, out, out_dtype, in, in_dtype, n, accum, &plan);
+  if (st != NRM_OK) return st;
+  DeviceGuard g(c->device);
+  st = ensure_partials(c, plan.grid);
+  if (st != NRM_OK) return st;
+  nrm::PlainWorkspace ws{c->partials, c->ticket, c->sum};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t* ev = nullptr;
+  if (c->timing) {
+    ev = &c->events[3 * (c->timed_calls % kTimingRing)];
+    c->timed_calls++;
+    hipEventRecord(ev[0], s);
+  }
+  hipError_t e = nrm::launch_reduce(plan, ws, s);
+  if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  if (ev) hipEventRecord(ev[1], s);
+  e = nrm::launch_map(plan, ws, s);
+  if (e != hipSuccess) return hip_fail(e, "map kernel launch");
+  if (ev) hipEventRecord(ev[2], s);
+  return NRM_OK;
+}
+
+int normalize(float* out, const float* in, int64_t n) {
+  return nrm_normalize_ex(nullptr, out, NRM_F32, in, NRM_F32, n, NRM_ACC_F32, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+"""GPU parity of the plain normalize path against the FP64 oracle.
+
+Every call goes through the C ABI (libnrm.so via the ctypes binding). Inputs
+are seeded synthetic arrays from paper_2207_00257_amd.synth; expected values
+come from oracle/ only.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2207_00257_amd import _lib as L
+from paper_2207_00257_amd import api, synth
+from parity_util import (REL_F32, assert_f32_close, assert_within_ulp, bf16_bits_to_f64, ulp_bf16,
+                         ulp_f16)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def gpu(x: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def run_f32(x: np.ndarray, ctx=None, accum="f32") -> np.ndarray:
+    inp = gpu(x)
+    out = torch.empty_like(inp)
+    api.normalize(out, inp, accum=accum, ctx=ctx)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_plain_2p20_uniform_matches_oracle():
+    """n = 2^20 FP32, in ~ U[0.5, 1.5), seed 1."""
+    x = synth.uniform_f32(1 << 20, 1)
+    got = run_f32(x)
+    ref = oracle.normalize(x)
+    assert_f32_close(got, ref, what="n=2^20")
+
+
+def test_brute_force_naive_1024():
+    """n = 1024 against the naive per-thread-sum form of Fig. 1 (O(n^2))."""
+    x = synth.uniform_f32(1024, 2)
+    got = run_f32(x)
+    ref = oracle.normalize_naive(x)
+    assert_f32_close(got, ref, what="naive n=1024")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 255, 256, 257, 1000,
+                               1023, 1025, 4095, 4097, 65535, 65537, 262143, 1000003, 3000017])
+def test_sizes_and_ragged_tails(n):
+    x = synth.lognormal_f32(n, 10 + n % 97, 1.0)
+    assert_f32_close(run_f32(x), oracle.normalize(x), what="n=%d" % n)
+
+
+def test_single_element_is_exactly_one():
+    for v in (1.0, 3.5, 1e-30, 7e30):
+        assert run_f32(np.array([v], np.float32))[0] == 1.0
+
+
+@pytest.mark.parametrize("c", [1.0, 0.5, 2.0])
+def test_constant_input_exact_at_power_of_two(c):
+    """Constant c at n = 2^k: every partial is an exact multiple of c, so the
+    binary32 sum is exact and every output is exactly 2^-k."""
+    for k in list(range(0, 21)) + [24]:
+        n = 1 << k
+        got = run_f32(np.full(n, c, np.float32))
+        assert np.all(got == np.float32(2.0 ** -k)), (c, k)
+
+
+def test_power_of_two_scaling_is_bitwise_invariant():
+    x = synth.lognormal_f32(777777, 21, 1.0)
+    ref = run_f32(x)
+    for m in (-10, 3, 17):
+        y = (x * np.float32(2.0 ** m)).astype(np.float32)
+        assert np.array_equal(run_f32(y), ref), m
+
+
+def test_deterministic_repeat():
+    x = synth.uniform_f32(5_000_011, 22)
+    a = run_f32(x)
+    b = run_f32(x)
+    assert np.array_equal(a, b)
+
+
+def test_n_zero_writes_nothing():
+    out = torch.full((16,), 7.0, device=DEV)
+    inp = torch.ones(16, device=DEV)
+    st = L.lib().nrm_normalize_ex(None, out.data_ptr(), 0, inp.data_ptr(), 0, 0, 0, None)
+    torch.cuda.synchronize()
+    assert st == L.NRM_OK
+    assert torch.all(out == 7.0)
+
+
+def test_raw_north_star_entry_point():
+    """normalize(out, in, n) itself: FP32, default context, null stream."""
+    x = synth.uniform_f32(123457, 23)
+    inp = gpu(x)
+    out = torch.empty_like(inp)
+    torch.cuda.synchronize()
+    st = L.lib().normalize(out.data_ptr(), inp.data_ptr(), x.size)
+    torch.cuda.synchronize()
+    assert st == L.NRM_OK
+    assert_f32_close(out.cpu().numpy(), oracle.normalize(x), what="raw normalize")
+
+
+def test_in_place():
+    x = synth.lognormal_f32(1_000_001, 24, 1.0)
+    t = gpu(x)
+    api.normalize(t, t)
+    torch.cuda.synchronize()
+    assert_f32_close(t.cpu().numpy(), oracle.normalize(x), what="in place")
+
+
+@pytest.mark.parametrize("in_off,out_off", [(1, 1), (2, 2), (3, 3), (1, 0), (0, 3), (2, 1)])
+def test_misaligned_pointers(in_off, out_off):
+    """Element offsets inside larger buffers: unaligned heads, and outputs whose
+    alignment differs from the input's (element-wise map path)."""
+    n = 100_003
+    x = synth.lognormal_f32(n, 25, 1.0)
+    big_in = torch.zeros(n + 8, device=DEV)
+    big_in[in_off:in_off + n] = gpu(x)
+    big_out = torch.full((n + 8,), -1.0, device=DEV)
+    inp = big_in[in_off:in_off + n]
+    out = big_out[out_off:out_off + n]
+    api.normalize(out, inp)
+    torch.cuda.synchronize()
+    o = big_out.cpu().numpy()
+    assert_f32_close(o[out_off:out_off + n], oracle.normalize(x), what="offsets %d/%d" % (in_off, out_off))
+    assert np.all(o[:out_off] == -1.0) and np.all(o[out_off + n:] == -1.0), "wrote outside out"
+
+
+def test_rejects_element_misaligned_pointer():
+    inp = torch.ones(64, device=DEV)
+    out = torch.empty(64, device=DEV)
+    st = L.lib().nrm_normalize_ex(None, out.data_ptr(), 0, inp.data_ptr() + 1, 0, 10, 0, None)
+    assert st == L.NRM_EINVAL
+
+
+def test_mixed_signs_within_condition_scaled_bound():
+    n = 200_003
+    g = np.random.Generator(np.random.PCG64(26))
+    x = (g.standard_normal(n) + 0.05).astype(np.float32)
+    ref = oracle.normalize(x)
+    kappa = np.abs(x.astype(np.float64)).sum() / abs(x.astype(np.float64).sum())
+    assert_f32_close(run_f32(x), ref, tol=REL_F32 * kappa, what="mixed signs")
+
+
+PARAM_SETS = [
+    dict(block=64, unroll=1, map_unroll=1),
+    dict(block=128, unroll=2, map_unroll=8),
+    dict(block=512, unroll=8, map_unroll=2),
+    dict(block=1024, unroll=4, map_unroll=4, grid=300, map_grid=77),
+    dict(layout=1),
+    dict(layout=1, reverse_map=1, unroll=8),
+    dict(reverse_map=1),
+    dict(nt_loads=0, grid=1, map_grid=1),
+    dict(max_chain=1, grid=4),
+    dict(max_chain=64, grid=100000),
+]
+
+
+@pytest.mark.parametrize("params", PARAM_SETS, ids=lambda p: ",".join("%s=%s" % kv for kv in p.items()))
+def test_launch_parameters(params):
+    ctx = api.Context(**params)
+    for n, seed in ((1_000_003, 30), (4097, 31), (1 << 20, 32)):
+        x = synth.lognormal_f32(n, seed, 1.0)
+        assert_f32_close(run_f32(x, ctx), oracle.normalize(x), what="%s n=%d" % (params, n))
+    ctx.close()
+
+
+def test_kahan_f32():
+    x = synth.lognormal_f32(1 << 22, 33, 2.0)
+    ref = oracle.normalize(x)
+    assert_f32_close(run_f32(x, accum="kahan"), ref, what="kahan")
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+def test_bf16_in_bf16_out(accum):
+    bits = synth.lognormal_bf16((1 << 20) + 5, 40, 2.0)
+    inp = gpu(bits.view(np.int16)).view(torch.bfloat16)
+    out = torch.empty_like(inp)
+    api.normalize(out, inp, accum=accum)
+    torch.cuda.synchronize()
+    got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
+    ref = oracle.normalize(bits, "bf16")
+    assert_within_ulp(got, ref, ulp_bf16, what="bf16->bf16 " + accum)
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+def test_bf16_in_f32_out(accum):
+    bits = synth.lognormal_bf16((1 << 20) + 3, 41, 2.0)
+    inp = gpu(bits.view(np.int16)).view(torch.bfloat16)
+    out = torch.empty(inp.numel(), device=DEV)
+    api.normalize(out, inp, accum=accum)
+    torch.cuda.synchronize()
+    assert_f32_close(out.cpu().numpy(), oracle.normalize(bits, "bf16"), what="bf16->f32 " + accum)
+
+
+def test_f16_in_f32_and_f16_out():
+    x = synth.lognormal_f32(300_001, 42, 1.0)
+    bits = synth.f32_to_f16_bits(x)
+    inp = gpu(bits.view(np.int16)).view(torch.float16)
+    ref = oracle.normalize(bits, "f16")
+    out32 = torch.empty(inp.numel(), device=DEV)
+    api.normalize(out32, inp)
+    out16 = torch.empty_like(inp)
+    api.normalize(out16, inp)
+    torch.cuda.synchronize()
+    assert_f32_close(out32.cpu().numpy(), ref, what="f16->f32")
+    assert_within_ulp(out16.cpu().numpy().astype(np.float64), ref, ulp_f16, what="f16->f16")
+
+
+def test_f32_in_bf16_out():
+    x = synth.uniform_f32(1 << 20, 43)
+    inp = gpu(x)
+    out = torch.empty(x.size, dtype=torch.bfloat16, device=DEV)
+    api.normalize(out, inp)
+    torch.cuda.synchronize()
+    got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
+    assert_within_ulp(got, oracle.normalize(x), ulp_bf16, what="f32->bf16")
+
+
+def test_full_size_2p28_default_launch():
+    """n = 2^28 FP32, U[0.5, 1.5), seed 3, in the default launch configuration
+    (the one the benchmark times): every output against the oracle, and the
+    outputs sum to one."""
+    n = 1 << 28
+    x = synth.uniform_f32(n, 3)
+    inp = gpu(x)
+    out = torch.empty_like(inp)
+    api.normalize(out, inp)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    del inp, out
+    ref = oracle.normalize(x)
+    for b in range(0, n, 1 << 24):
+        assert_f32_close(got[b:b + (1 << 24)], ref[b:b + (1 << 24)], what="2^28 block %d" % b)
+    s = np.sum(got.astype(np.float64))
+    assert abs(s - 1.0) <= 4e-6 + n * 2.0 ** -53

@@ -36,9 +36,11 @@
  *  - Floating point: IEEE binary32 accumulation (or compensated binary32), a
  *    correctly rounded binary32 division, round-to-nearest-even conversions to
  *    BF16/FP16. No FP64 on the GPU. For non-negative inputs the relative error
- *    of every output against the exact quotient is at most gamma_h + u with
- *    h <= 64 summation levels (u = 2^-24), about 3.9e-6; compensated
- *    accumulation brings the sum's error to about 2u.
+ *    of every output against the exact quotient is at most gamma_h + u, where
+ *    h <= max_height + 26 is the height of the summation tree, u = 2^-24 and
+ *    gamma_h = h u / (1 - h u) (default max_height 36: h <= 62, bound 3.8e-6);
+ *    compensated accumulation brings the sum's error to a few u whatever the
+ *    size.
  */
 #ifndef NRM_H
 #define NRM_H
@@ -72,20 +74,28 @@ typedef enum { NRM_ACC_F32 = 0, NRM_ACC_KAHAN = 1 } nrm_accum;
  * strides over the input one block-iteration at a time. */
 typedef enum { NRM_LAYOUT_CHUNK = 0, NRM_LAYOUT_STRIDE = 1 } nrm_layout;
 
-/* Launch parameters of the plain path. Zero in a field means "library
- * default". Changing them changes the summation tree, hence the bits of the
- * result (within the stated error bound), never its definition. */
+/* Launch parameters of the plain path. Start from nrm_default_params() and
+ * change fields; nrm_set_params validates every field. Changing them changes
+ * the summation tree, hence the low bits of the result (always within the
+ * stated error bound), never its definition. */
 typedef struct {
-  int32_t block;       /* threads per block: 64..1024, multiple of 64 */
-  int32_t unroll;      /* reduce: 16-byte vectors per thread per iteration: 1, 2, 4 or 8 */
-  int32_t map_unroll;  /* map: 16-byte vectors per thread per iteration: 1, 2, 4 or 8 */
-  int32_t grid;        /* reduce blocks (upper bound; raised if chains would exceed max_chain) */
-  int32_t map_grid;    /* map blocks (upper bound) */
-  int32_t layout;      /* nrm_layout */
-  int32_t max_chain;   /* max additions per accumulator chain, 1..64 (bounds the error) */
-  int32_t reverse_map; /* 1: the map walks each chunk from its end (reuse of recently read lines) */
-  int32_t nt_loads;    /* 1: non-temporal hint on the map's loads (2 = library default) */
-  int32_t reserved[7];
+  /* reduce kernel */
+  int32_t block;        /* threads per block: 64..1024, multiple of 64 */
+  int32_t unroll;       /* 16-byte vectors per thread per iteration: 1, 2, 4 or 8 */
+  int32_t grid;         /* blocks (upper bound; raised when the height bound needs more) */
+  int32_t layout;       /* nrm_layout */
+  int32_t reduce_nt;    /* 1: non-temporal hint on the reduce's loads */
+  int32_t max_height;   /* bound on the additions along any path of one thread's summation
+                           tree, 24..48; the whole tree then has height <= max_height + 26
+                           (wavefront 6, block <= 4, grid combine <= 16) */
+  /* map kernel */
+  int32_t map_block;    /* threads per block: 64..1024, multiple of 64 */
+  int32_t map_unroll;   /* 16-byte vectors per thread per iteration: 1, 2, 4 or 8 */
+  int32_t map_grid;     /* blocks (upper bound) */
+  int32_t map_layout;   /* nrm_layout */
+  int32_t map_nt;       /* 1: non-temporal hint on the map's loads */
+  int32_t reverse_map;  /* 1: each block walks its share from the end (reuse of recently read lines) */
+  int32_t reserved[4];
 } nrm_params;
 
 typedef struct nrm_ctx nrm_ctx;
@@ -103,6 +113,9 @@ int normalize(float* out, const float* in, int64_t n);
 int nrm_create(nrm_ctx** ctx, int device);
 /* Free the context's workspace. Waits for the device to be idle first. */
 int nrm_destroy(nrm_ctx* ctx);
+/* The library's default launch parameters (tuned for MI355X). */
+int nrm_default_params(nrm_params* params);
+/* Replace the context's launch parameters; NRM_EINVAL if any field is out of range. */
 int nrm_set_params(nrm_ctx* ctx, const nrm_params* params);
 int nrm_get_params(const nrm_ctx* ctx, nrm_params* params);
 
@@ -125,7 +138,8 @@ const char* nrm_last_error(void);
 /* Kernel timing: while enabled, every plain call records HIP events around
  * its reduce and map kernels on the call's stream. nrm_kernel_times
  * synchronizes those events and returns the summed durations (ms) and the
- * number of calls recorded since the last reset (up to 4096 calls are kept). */
+ * number of calls recorded since timing was last enabled (the last 1024 calls
+ * are kept). */
 int nrm_set_timing(nrm_ctx* ctx, int enable);
 int nrm_kernel_times(nrm_ctx* ctx, double* reduce_ms, double* map_ms, int64_t* calls);
 

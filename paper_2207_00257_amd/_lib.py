@@ -22,14 +22,17 @@ class NrmParams(ctypes.Structure):
     _fields_ = [
         ("block", ctypes.c_int32),
         ("unroll", ctypes.c_int32),
-        ("map_unroll", ctypes.c_int32),
         ("grid", ctypes.c_int32),
-        ("map_grid", ctypes.c_int32),
         ("layout", ctypes.c_int32),
-        ("max_chain", ctypes.c_int32),
+        ("reduce_nt", ctypes.c_int32),
+        ("max_height", ctypes.c_int32),
+        ("map_block", ctypes.c_int32),
+        ("map_unroll", ctypes.c_int32),
+        ("map_grid", ctypes.c_int32),
+        ("map_layout", ctypes.c_int32),
+        ("map_nt", ctypes.c_int32),
         ("reverse_map", ctypes.c_int32),
-        ("nt_loads", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -48,6 +51,7 @@ def _declare(lib):
         "normalize": (i32, [p, p, i64]),
         "nrm_create": (i32, [ctypes.POINTER(p), i32]),
         "nrm_destroy": (i32, [p]),
+        "nrm_default_params": (i32, [ctypes.POINTER(NrmParams)]),
         "nrm_set_params": (i32, [p, ctypes.POINTER(NrmParams)]),
         "nrm_get_params": (i32, [p, ctypes.POINTER(NrmParams)]),
         "nrm_normalize_ex": (i32, [p, p, i32, p, i32, i64, i32, p]),

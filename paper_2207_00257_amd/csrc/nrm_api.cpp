@@ -46,44 +46,43 @@ struct nrm_ctx {
 
 namespace {
 
+// Defaults: the best shape found by the tuner (paper_2207_00257_amd/tune.py)
+// on MI355X for n = 2^28 FP32. The reduce streams with one 1024-thread block
+// per CU and non-temporal loads; the map runs many smaller blocks, both
+// striding over the whole input a block-iteration at a time.
 nrm_params default_params() {
   nrm_params p;
   std::memset(&p, 0, sizeof(p));
-  p.block = 256;
-  p.unroll = 4;
+  p.block = 1024;
+  p.unroll = 2;
+  p.grid = 256;
+  p.layout = NRM_LAYOUT_STRIDE;
+  p.reduce_nt = 1;
+  p.max_height = 36;
+  p.map_block = 512;
   p.map_unroll = 4;
-  p.grid = 2048;
-  p.map_grid = 2048;
-  p.layout = NRM_LAYOUT_CHUNK;
-  p.max_chain = 32;
-  p.reverse_map = 0;
-  p.nt_loads = 1;
+  p.map_grid = 8192;
+  p.map_layout = NRM_LAYOUT_STRIDE;
+  p.map_nt = 1;
+  p.reverse_map = 1;
   return p;
 }
 
 int check_params(const nrm_params& p) {
-  if (p.block < 64 || p.block > 1024 || p.block % 64) return fail(NRM_EINVAL, "block must be 64..1024, a multiple of 64");
+  auto ok_b = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
   auto ok_u = [](int u) { return u == 1 || u == 2 || u == 4 || u == 8; };
+  auto ok_l = [](int l) { return l == NRM_LAYOUT_CHUNK || l == NRM_LAYOUT_STRIDE; };
+  auto ok_f = [](int f) { return f == 0 || f == 1; };
+  if (!ok_b(p.block) || !ok_b(p.map_block)) return fail(NRM_EINVAL, "block sizes must be 64..1024, multiples of 64");
   if (!ok_u(p.unroll) || !ok_u(p.map_unroll)) return fail(NRM_EINVAL, "unroll and map_unroll must be 1, 2, 4 or 8");
   if (p.grid < 1 || p.map_grid < 1) return fail(NRM_EINVAL, "grid and map_grid must be positive");
-  if (p.layout != NRM_LAYOUT_CHUNK && p.layout != NRM_LAYOUT_STRIDE) return fail(NRM_EINVAL, "unknown layout");
-  if (p.max_chain < 1 || p.max_chain > 64) return fail(NRM_EINVAL, "max_chain must be 1..64");
-  if (p.reverse_map != 0 && p.reverse_map != 1) return fail(NRM_EINVAL, "reverse_map must be 0 or 1");
-  if (p.nt_loads != 0 && p.nt_loads != 1) return fail(NRM_EINVAL, "nt_loads must be 0 or 1");
+  if (!ok_l(p.layout) || !ok_l(p.map_layout)) return fail(NRM_EINVAL, "unknown layout");
+  if (p.max_height < 24 || p.max_height > 48) return fail(NRM_EINVAL, "max_height must be 24..48");
+  if (!ok_f(p.reduce_nt) || !ok_f(p.map_nt) || !ok_f(p.reverse_map))
+    return fail(NRM_EINVAL, "reduce_nt, map_nt and reverse_map must be 0 or 1");
+  for (int r : p.reserved)
+    if (r != 0) return fail(NRM_EINVAL, "reserved fields must be zero");
   return NRM_OK;
-}
-
-// Fill zero fields with defaults.
-nrm_params resolve(const nrm_params& in) {
-  nrm_params d = default_params(), p = in;
-  if (!p.block) p.block = d.block;
-  if (!p.unroll) p.unroll = d.unroll;
-  if (!p.map_unroll) p.map_unroll = d.map_unroll;
-  if (!p.grid) p.grid = d.grid;
-  if (!p.map_grid) p.map_grid = d.map_grid;
-  if (!p.max_chain) p.max_chain = d.max_chain;
-  if (p.nt_loads == 2) p.nt_loads = d.nt_loads;
-  return p;
 }
 
 std::mutex g_default_mu;
@@ -181,17 +180,25 @@ int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_d
   p->vector_map = ((ao + (uintptr_t)(p->head * so)) % (uintptr_t)out_align) == 0;
   p->block = q.block;
   p->unroll = q.unroll;
-  p->map_unroll = q.map_unroll;
   p->layout = q.layout;
+  p->reduce_nt = q.reduce_nt;
+  p->map_block = q.map_block;
+  p->map_unroll = q.map_unroll;
+  p->map_layout = q.map_layout;
+  p->map_nt = q.map_nt;
   p->reverse_map = q.reverse_map;
-  p->nt_loads = q.nt_loads;
-  // Bound the additions per accumulator chain by max_chain: this fixes the
-  // height of the summation tree, hence the worst-case error of the sum.
-  const int64_t max_iters =
-      std::max<int64_t>(1, q.max_chain / nrm::adds_per_iteration(in_dt, acc, q.unroll));
+  // Iterations per reduce block are bounded so that the height of a thread's
+  // summation tree stays within max_height (plain mode); compensated chains
+  // have no such bound (their error does not grow with the chain).
+  int64_t max_iters = 0;
+  if (acc == NRM_ACC_F32) {
+    max_iters = 1;
+    while (nrm::thread_tree_height(in_dt, acc, q.unroll, max_iters + 1) <= q.max_height) ++max_iters;
+  }
   split(p->nvec, (int64_t)q.block * q.unroll, q.grid, max_iters, &p->grid, &p->chunk);
-  split(p->nvec, (int64_t)q.block * q.map_unroll, q.map_grid, 0, &p->map_grid, &p->map_chunk);
-  if (p->grid > INT32_MAX || p->map_grid > INT32_MAX) return fail(NRM_EINVAL, "n too large for one launch");
+  split(p->nvec, (int64_t)q.map_block * q.map_unroll, q.map_grid, 0, &p->map_grid, &p->map_chunk);
+  if (p->grid > 65536) return fail(NRM_EINVAL, "n too large for these launch parameters (over 65536 reduce blocks)");
+  if (p->map_grid > INT32_MAX) return fail(NRM_EINVAL, "n too large for one launch");
   return NRM_OK;
 }
 
@@ -237,6 +244,11 @@ int nrm_create(nrm_ctx** ctx, int device) {
   nrm_ctx* c = new nrm_ctx();
   c->device = device;
   c->params = default_params();
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
+    c->params.grid = cus;           // one reduce block per CU
+    c->params.map_grid = 32 * cus;  // map: 32 blocks per CU
+  }
   void* small = nullptr;
   e = hipMalloc(&small, 256);
   if (e != hipSuccess) {
@@ -277,12 +289,17 @@ int nrm_destroy(nrm_ctx* c) {
   return NRM_OK;
 }
 
+int nrm_default_params(nrm_params* params) {
+  if (!params) return fail(NRM_EINVAL, "NULL argument");
+  *params = default_params();
+  return NRM_OK;
+}
+
 int nrm_set_params(nrm_ctx* c, const nrm_params* params) {
   if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
-  nrm_params p = resolve(*params);
-  int st = check_params(p);
+  int st = check_params(*params);
   if (st != NRM_OK) return st;
-  c->params = p;
+  c->params = *params;
   return NRM_OK;
 }
 

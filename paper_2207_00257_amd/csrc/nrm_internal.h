@@ -26,6 +26,20 @@ __host__ __device__ constexpr int accumulators(int dt, int acc, int unroll) {
 __host__ __device__ constexpr int adds_per_iteration(int dt, int acc, int unroll) {
   return unroll * (16 / (dt == NRM_F32 ? 4 : 2)) / accumulators(dt, acc, unroll);
 }
+// Plain binary32 mode: additions a chain receives before the thread sums its
+// chains into its running total and restarts them.
+constexpr int CHAIN_ADDS = 16;
+
+// Height (longest path of additions) of one thread's summation tree in plain
+// mode after `iters` loop iterations: a chain of CHAIN_ADDS (+1 for the head
+// or tail element), the pairwise merge of the chains, and one addition into
+// the running total per flush.
+inline int64_t thread_tree_height(int dt, int acc, int unroll, int64_t iters) {
+  int na = accumulators(dt, acc, unroll), lg = 0;
+  while ((1 << lg) < na) ++lg;
+  int flush = CHAIN_ADDS / adds_per_iteration(dt, acc, unroll);
+  return CHAIN_ADDS + 1 + lg + (iters + flush - 1) / flush;
+}
 
 // Plan of one plain normalize call, fully resolved on the host.
 struct PlainPlan {
@@ -37,16 +51,21 @@ struct PlainPlan {
   int64_t nvec;       // 16-byte input vectors in the aligned body
   int64_t tail_begin; // first element after the body
   bool vector_map;    // out is aligned like in, so the map can use vector stores
+  // reduce kernel
   int block;          // threads per block (multiple of 64, <= 1024)
   int unroll;         // 16-byte vectors per thread per iteration
-  int map_unroll;
-  int64_t grid;       // reduce blocks
-  int64_t chunk;      // reduce: vectors per block (multiple of block * unroll)
-  int64_t map_grid;
-  int64_t map_chunk;  // map: vectors per block (multiple of block * map_unroll)
+  int64_t grid;       // blocks
+  int64_t chunk;      // vectors per block (layout CHUNK; multiple of block * unroll)
   int layout;         // NRM_LAYOUT_*
+  int reduce_nt;      // non-temporal hint on loads
+  // map kernel
+  int map_block;
+  int map_unroll;
+  int64_t map_grid;
+  int64_t map_chunk;
+  int map_layout;
+  int map_nt;
   int reverse_map;
-  int nt_loads;       // non-temporal hint on the map's loads
 };
 
 // Device workspace of the plain path: per-block partials, the completion

@@ -290,18 +290,36 @@ struct ReduceArgs {
   float* sum;          // out: the hoisted invariant
 };
 
-constexpr int COMBINE_TILE = 1024;  // partials merged per LDS tree pass
+constexpr int COMBINE_TILE = 1024;     // partials merged per LDS tree pass
+constexpr int MAX_COMBINE_TILES = 64;  // at most 65536 blocks in a reduce launch
+
+// Pairwise sum of the thread's chains into acc[0] (fixed tree).
+template <int ACC, int NA>
+__device__ __forceinline__ void merge_chains(Acc<ACC> (&acc)[NA]) {
+#pragma unroll
+  for (int s = 1; s < NA; s <<= 1)
+#pragma unroll
+    for (int k = 0; k + s < NA; k += 2 * s) acc[k].merge(acc[k + s]);
+}
 
 template <int DT, int ACC, int U, bool NT>
 __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
   constexpr int VEC = Elem<DT>::VEC;
   constexpr int NA = accumulators(DT, ACC, U);
+  // Plain binary32: every FLUSH iterations (16 additions per chain) the
+  // chains are summed pairwise into a running total and restarted, so the
+  // height of the thread's summation tree grows by one per FLUSH iterations
+  // instead of one per iteration. Compensated chains need no flush.
+  constexpr int FLUSH = CHAIN_ADDS / adds_per_iteration(DT, ACC, U);
   __shared__ Acc<ACC> slots[MAX_WAVES];
   __shared__ int is_last;
 
   Acc<ACC> acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k].zero();
+  Acc<ACC> run;
+  run.zero();
+  int since_flush = 0;
 
   const int64_t B = blockDim.x;
   const int64_t step = B * U;
@@ -339,19 +357,25 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
         }
       }
     }
+    if constexpr (ACC == NRM_ACC_F32) {
+      if (++since_flush == FLUSH) {
+        since_flush = 0;
+        merge_chains<ACC, NA>(acc);
+        run.merge(acc[0]);
+#pragma unroll
+        for (int k = 0; k < NA; ++k) acc[k].zero();
+      }
+    }
   }
   // unaligned head and the tail shorter than a vector: block 0
   if (blockIdx.x == 0) {
     if ((int64_t)threadIdx.x < a.head) acc[0].add(load_one<DT>(a.in, threadIdx.x));
     if ((int64_t)threadIdx.x < a.n - a.tail_begin) acc[0].add(load_one<DT>(a.in, a.tail_begin + threadIdx.x));
   }
-  // the thread's chains, pairwise
-#pragma unroll
-  for (int s = 1; s < NA; s <<= 1)
-#pragma unroll
-    for (int k = 0; k + s < NA; k += 2 * s) acc[k].merge(acc[k + s]);
+  merge_chains<ACC, NA>(acc);
+  run.merge(acc[0]);
 
-  Acc<ACC> blk = block_reduce<ACC>(acc[0], slots);
+  Acc<ACC> blk = block_reduce<ACC>(run, slots);
 
   // publish the partial; the last block to arrive combines all of them
   Acc<ACC>* part = reinterpret_cast<Acc<ACC>*>(a.partials);
@@ -367,12 +391,13 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
 
   // Fixed-order combine: tiles of COMBINE_TILE partials are merged by a
   // halving tree in LDS (each level adds slot i + s into slot i, then a
-  // barrier); the tile results are merged left to right by thread 0.
+  // barrier); thread 0 then merges the tile results pairwise.
   __shared__ Acc<ACC> tree[COMBINE_TILE];
-  Acc<ACC> total;
-  total.zero();
+  __shared__ Acc<ACC> tiles[MAX_COMBINE_TILES];
   const int64_t G = gridDim.x;
-  for (int64_t t0 = 0; t0 < G; t0 += COMBINE_TILE) {
+  const int ntiles = (int)((G + COMBINE_TILE - 1) / COMBINE_TILE);
+  for (int t = 0; t < ntiles; ++t) {
+    const int64_t t0 = (int64_t)t * COMBINE_TILE;
     for (int i = threadIdx.x; i < COMBINE_TILE; i += blockDim.x) {
       if (t0 + i < G) fetch(part, t0 + i, tree[i]);
       else tree[i].zero();
@@ -382,11 +407,15 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
       for (int i = threadIdx.x; i < s; i += blockDim.x) tree[i].merge(tree[i + s]);
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
-      if (t0 == 0) total = tree[0];
-      else total.merge(tree[0]);
-    }
+    if (threadIdx.x == 0) tiles[t] = tree[0];
     __syncthreads();
+  }
+  Acc<ACC> total;
+  total.zero();
+  if (threadIdx.x == 0) {
+    for (int s = 1; s < ntiles; s <<= 1)
+      for (int i = 0; i + s < ntiles; i += 2 * s) tiles[i].merge(tiles[i + s]);
+    total = tiles[0];
   }
   if (threadIdx.x == 0) {
     a.sum[0] = total.value();
@@ -476,7 +505,7 @@ __global__ void __launch_bounds__(256) map_scalar_kernel(const char* in, char* o
 
 template <int DT, int ACC, int U>
 hipError_t reduce_u(const PlainPlan& p, const ReduceArgs& a, hipStream_t s) {
-  if (p.nt_loads)
+  if (p.reduce_nt)
     hipLaunchKernelGGL((reduce_kernel<DT, ACC, U, true>), dim3(p.grid), dim3(p.block), 0, s, a);
   else
     hipLaunchKernelGGL((reduce_kernel<DT, ACC, U, false>), dim3(p.grid), dim3(p.block), 0, s, a);
@@ -501,10 +530,10 @@ hipError_t reduce_dt(const PlainPlan& p, const ReduceArgs& a, hipStream_t s) {
 
 template <int DTI, int DTO, int U>
 hipError_t map_u(const PlainPlan& p, const MapArgs& a, hipStream_t s) {
-  if (p.nt_loads)
-    hipLaunchKernelGGL((map_kernel<DTI, DTO, U, true>), dim3(p.map_grid), dim3(p.block), 0, s, a);
+  if (p.map_nt)
+    hipLaunchKernelGGL((map_kernel<DTI, DTO, U, true>), dim3(p.map_grid), dim3(p.map_block), 0, s, a);
   else
-    hipLaunchKernelGGL((map_kernel<DTI, DTO, U, false>), dim3(p.map_grid), dim3(p.block), 0, s, a);
+    hipLaunchKernelGGL((map_kernel<DTI, DTO, U, false>), dim3(p.map_grid), dim3(p.map_block), 0, s, a);
   return hipGetLastError();
 }
 
@@ -568,7 +597,7 @@ hipError_t launch_map(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t 
   a.tail_begin = p.tail_begin;
   a.n = p.n;
   a.chunk = p.map_chunk;
-  a.layout = p.layout;
+  a.layout = p.map_layout;
   a.reverse = p.reverse_map;
   a.sum = ws.sum;
   switch (p.in_dt) {

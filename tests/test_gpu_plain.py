@@ -4,6 +4,8 @@ Every call goes through the C ABI (libnrm.so via the ctypes binding). Inputs
 are seeded synthetic arrays from paper_2207_00257_amd.synth; expected values
 come from oracle/ only.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -148,16 +150,18 @@ def test_mixed_signs_within_condition_scaled_bound():
 
 
 PARAM_SETS = [
-    dict(block=64, unroll=1, map_unroll=1),
+    dict(block=64, unroll=1, map_block=64, map_unroll=1),
     dict(block=128, unroll=2, map_unroll=8),
-    dict(block=512, unroll=8, map_unroll=2),
+    dict(block=512, unroll=8, map_block=1024, map_unroll=2),
     dict(block=1024, unroll=4, map_unroll=4, grid=300, map_grid=77),
-    dict(layout=1),
-    dict(layout=1, reverse_map=1, unroll=8),
+    dict(layout=1, map_layout=1),
+    dict(layout=1, map_layout=1, reverse_map=1, unroll=8),
     dict(reverse_map=1),
-    dict(nt_loads=0, grid=1, map_grid=1),
-    dict(max_chain=1, grid=4),
-    dict(max_chain=64, grid=100000),
+    dict(reduce_nt=0, map_nt=0, grid=1, map_grid=1),
+    dict(max_height=24, grid=4),
+    dict(max_height=48, grid=65536, map_grid=65536),
+    dict(layout=1, grid=8, unroll=8, block=1024, max_height=48),
+    dict(layout=0, grid=3, unroll=1, block=64, max_height=48),
 ]
 
 
@@ -239,3 +243,37 @@ def test_full_size_2p28_default_launch():
         assert_f32_close(got[b:b + (1 << 24)], ref[b:b + (1 << 24)], what="2^28 block %d" % b)
     s = np.sum(got.astype(np.float64))
     assert abs(s - 1.0) <= 4e-6 + n * 2.0 ** -53
+
+
+def test_parameter_validation():
+    ctx = api.Context()
+    good = ctx.get_params()
+    for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(grid=0),
+                dict(layout=2), dict(max_height=23), dict(max_height=49), dict(reverse_map=2),
+                dict(map_nt=-1)):
+        with pytest.raises(L.NrmError):
+            ctx.set_params(**bad)
+        assert ctx.get_params() == good, bad
+    p = L.NrmParams()
+    assert L.lib().nrm_default_params(ctypes.byref(p)) == L.NRM_OK
+    assert {f: getattr(p, f) for f, _ in L.NrmParams._fields_ if f != "reserved"} == good
+    p.reserved[0] = 1
+    assert L.lib().nrm_set_params(ctx.handle, ctypes.byref(p)) == L.NRM_EINVAL
+    ctx.close()
+
+
+def test_too_many_blocks_is_rejected():
+    """The combine handles at most 65536 reduce blocks; a launch shape that
+    would need more is an argument error, not a wrong result."""
+    # 64 threads x 1 vector x 80 iterations per block (the most max_height
+    # 24 allows) x 65536 blocks covers 1,342,177,280 elements; use more. The
+    # buffers are real allocations, so even a launch would stay in bounds.
+    n = 1_400_000_000
+    ctx = api.Context(block=64, unroll=1, max_height=24, grid=65536)
+    x = torch.empty(n, device=DEV)
+    out = torch.empty_like(x)
+    with pytest.raises(L.NrmError):
+        api.normalize(out, x, ctx=ctx)
+    ctx.close()
+    del x, out
+    torch.cuda.empty_cache()

@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--params", default=None,
                     help="JSON file of tuned launch parameters (default: the committed tuning cache "
                          "if it has an entry for this device and size, else the library defaults)")
+    ap.add_argument("--workload", default="plain", choices=["plain", "ragged", "serve"],
+                    help="plain: n=2^log2n FP32 (the headline); ragged: 4096 rows, lengths log-uniform "
+                         "in [32, 2^20], LogNormal(0,1) FP32, one graph-replayed batched call per step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of the same size instead (torch copy_: reads and "
                          "writes 4n bytes each); used to scale HBM counter readings")
@@ -94,6 +97,11 @@ def main():
         print("bench.py measures one GPU only: the normalize hot path here is a single-GPU build "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "ragged":
+        return bench_ragged(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch
@@ -194,6 +202,178 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x)
+    print(json.dumps(line), flush=True)
+
+
+def bench_ragged(args):
+    """Ragged batched workload: one step = one batched call over 4096 rows
+    (planner + phase 1 + phase 2, replayed from a captured hipGraph). Also
+    times the same rows as one plain normalize call per row (two kernel
+    launches each) for comparison."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2207_00257_amd import _lib as L
+    from paper_2207_00257_amd import api, synth, tune
+
+    rows = 4096
+    x, offs = synth.ragged_batch(rows, 4)
+    total = int(offs[-1])
+    dev = torch.device("cuda:0")
+    inp = torch.from_numpy(x).to(dev)
+    out = torch.empty_like(inp)
+    offs_d = torch.from_numpy(offs).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = api.Context()
+    bp = tune.load_batch_params(args.params) or {}
+    bp["graph"] = 1
+    ctx.set_batch_params(**bp)
+    ctx.batch_reserve(rows, total)
+    for _ in range(args.warmup):
+        api.normalize_batched(out, inp, offs_d, ctx=ctx)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        api.normalize_batched(out, inp, offs_d, ctx=ctx)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    if ctx.device_error() != L.NRM_OK:
+        raise RuntimeError("device reported invalid rows")
+    # spot check: 64 rows against the definition
+    pick = np.random.Generator(np.random.PCG64(1)).integers(0, rows, 64)
+    o = out.cpu().numpy()
+    worst = 0.0
+    for r in pick:
+        b, e = int(offs[r]), int(offs[r + 1])
+        ref = x[b:e].astype(np.float64) / np.sum(x[b:e].astype(np.float64))
+        worst = max(worst, float(np.max(np.abs(o[b:e] - ref) / ref)))
+    # one plain call per row, from the host, on the same stream
+    pctx = api.Context()
+    lib = L.lib()
+    s = stream.cuda_stream
+    ip, op = inp.data_ptr(), out.data_ptr()
+    bounds = [(int(offs[r]), int(offs[r + 1] - offs[r])) for r in range(rows)]
+
+    def per_row():
+        for b, n in bounds:
+            st = lib.nrm_normalize_ex(pctx.handle, op + 4 * b, 0, ip + 4 * b, 0, n, 0, s)
+            if st:
+                raise RuntimeError("per-row call failed: %d" % st)
+
+    per_row()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    per_row()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per_row_ms = e0.elapsed_time(e1)
+    gbs = 12.0 * total / (ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s",
+        "pct_of_peak": round(100.0 * gbs / PEAK_HBM_GBS, 2),
+        "elements_per_s": round(total / (ms * 1e-3), 1), "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ragged batched normalize: 4096 rows, lengths log-uniform in [32, 2^20] "
+                               "(seed 4), LogNormal(0,1) FP32, int64 CSR offsets, hipGraph replay; "
+                               "model 12 B/element", "rows": rows, "elements": total,
+                   "batch_params": ctx.get_batch_params()},
+        "per_row_launch": {"ms": round(per_row_ms, 4), "GBps": round(12.0 * total / (per_row_ms * 1e-3) / 1e9, 2),
+                           "speedup_of_batched": round(per_row_ms / ms, 3)},
+        "sample_max_rel_err": worst,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
+    """Serving workload: an open-loop Poisson trace (20k req/s; n log-uniform
+    in [2^8, 2^24]; 70% FP32 / 30% BF16 requests, BF16 in and out) replayed
+    into the continuous-batching server with a 64 GiB HBM budget, and into
+    the same server in per-request mode (one plain call per request).
+    Latency runs from each request's scheduled arrival to the observed
+    completion; statistics exclude the first warm_s seconds."""
+    import numpy as np
+    import torch
+
+    from paper_2207_00257_amd import serve, tune
+    import oracle
+
+    torch.cuda.init()
+    trace = serve.make_trace(rate, warm_s + measure_s, seed=6)
+    k = trace["n"].size
+    pool = serve.InputPool(1 << 24, 7)
+    offs = pool.offsets(trace["n"], 8)
+    ptrs = pool.pointers(trace["in_dt"], offs)
+    ids = np.arange(k)
+    bp = tune.load_batch_params(args.params)
+    warm_ns = int(warm_s * 1e9)
+
+    def run(batching, budget=64 << 30, tr=trace, pt=ptrs, n_req=None, warm_ns=warm_ns):
+        n_req = tr["n"].size if n_req is None else n_req
+        srv = serve.Server(slots=4, budget_bytes=budget, batching=batching, batch_params=bp)
+        t0 = srv.replay(np.arange(n_req), pt[:n_req], tr["n"][:n_req], tr["in_dt"][:n_req], tr["out_dt"][:n_req],
+                        tr["t_ns"][:n_req])
+        comps = srv.wait_all(n_req, timeout_s=600)
+        st = srv.stats()
+        srv.close()
+        meas = [c for c in comps if c[2] - t0 >= warm_ns]
+        out = serve.latency_stats(meas)
+        out["batches"] = st["batches"]
+        out["launches"] = st["launches"]
+        return out
+
+    batched = run(True)
+    per_req = run(False)
+    stress = run(True, budget=256 << 20)
+    sweep = []
+    for r in (50000.0, 100000.0, 200000.0):
+        tr = serve.make_trace(r, 1.2, seed=9)
+        pt = pool.pointers(tr["in_dt"], pool.offsets(tr["n"], 10))
+        res_b = run(True, tr=tr, pt=pt, warm_ns=int(0.2e9))
+        res_p = run(False, tr=tr, pt=pt, warm_ns=int(0.2e9))
+        sweep.append({"offered_req_per_s": r, "batched": res_b, "per_request": res_p})
+    # results of a sample of requests, held and checked against the oracle
+    srv = serve.Server(slots=4, hold_outputs=True, batch_params=bp)
+    sel = np.arange(0, k, max(1, k // 64))[:64]
+    srv.submit(sel, ptrs[sel], trace["n"][sel], trace["in_dt"][sel], trace["out_dt"][sel])
+    worst, worst_bf16 = 0.0, 0.0
+    import ctypes
+    paths = sorted({ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln})
+    hip = ctypes.CDLL(paths[0])
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    for c in srv.wait_all(len(sel)):
+        i = c[0]
+        n, dt, o = int(trace["n"][i]), int(trace["in_dt"][i]), int(offs[i])
+        if dt == 0:
+            host = np.empty(n, np.float32)
+            hip.hipMemcpy(host.ctypes.data, c[1], 4 * n, 2)
+            ref = oracle.normalize(pool.host_f32[o:o + n])
+            worst = max(worst, float(np.max(np.abs(host - ref) / ref)))
+        else:
+            bits = np.empty(n, np.uint16)
+            hip.hipMemcpy(bits.ctypes.data, c[1], 2 * n, 2)
+            got = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+            ref = oracle.normalize(pool.host_bf16[o:o + n], "bf16")
+            ulp = np.exp2(np.floor(np.log2(ref)) - 7)
+            worst_bf16 = max(worst_bf16, float(np.max(np.abs(got - ref) / ulp)))
+        srv.release(i)
+    srv.close()
+    line = {
+        "metric": METRIC, "value": round(batched["req_per_s"], 1), "unit": "req/s",
+        "p50_ms": round(batched["p50_ms"], 4), "p99_ms": round(batched["p99_ms"], 4),
+        "n_gpus": 1, "steps": None, "warmup": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": "serving: Poisson %.0f req/s for %.0f s (+%.0f s warm-up), n log-uniform in "
+                               "[2^8, 2^24], 70%% FP32 / 30%% BF16 (BF16 in and out), inputs device-resident, "
+                               "64 GiB HBM admission budget, 4 slots, open-loop replay, latency from scheduled "
+                               "arrival" % (rate, measure_s, warm_s), "requests": int(k)},
+        "batched": batched, "per_request_launch": per_req, "budget_256MiB": stress, "rate_sweep": sweep,
+        "sample_max_rel_err_f32": worst, "sample_max_err_bf16_ulps": worst_bf16,
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -95,8 +95,37 @@ typedef struct {
   int32_t map_layout;   /* nrm_layout */
   int32_t map_nt;       /* 1: non-temporal hint on the map's loads */
   int32_t reverse_map;  /* 1: each block walks its share from the end (reuse of recently read lines) */
-  int32_t reserved[4];
+  int32_t reduce_keep_mib; /* 0..4096: the reduce reads the last this many MiB of the input with a
+                              temporal hint (the rest non-temporal), so that a reverse map may find
+                              them in the last-level cache */
+  int32_t reserved[3];
 } nrm_params;
+
+/* Launch parameters of the ragged batched path. Start from
+ * nrm_default_batch_params(). A row's result depends on these, on its length,
+ * dtypes and start alignment modulo 16 bytes, never on the other rows. */
+typedef struct {
+  int32_t block;       /* threads per block: 64..1024, multiple of 64 */
+  int32_t unroll;      /* tile sums: 16-byte vectors per thread per iteration: 1, 2, 4, 8 */
+  int32_t map_unroll;  /* tile divides: 16-byte vectors per thread per iteration: 1, 2, 4, 8 */
+  int32_t grid;        /* persistent blocks of both phases */
+  int32_t tile_log2;   /* a long row is cut into tiles of 2^tile_log2 elements: 10..22 */
+  int32_t short_regs;  /* 16-byte vectors per thread held in registers by a single-pass row:
+                          1, 2, 4 or 8; rows with n <= block * short_regs * 4 take one pass
+                          (one read, one write) */
+  int32_t graph;       /* 1: capture the launch sequence once in a hipGraph and replay it */
+  int32_t reserved[5];
+} nrm_batch_params;
+
+/* One row of a batch given as a table: `in` and `out` are device arrays of
+ * n elements of in_dtype / out_dtype; the row is normalized on its own. */
+typedef struct {
+  const void* in;
+  void* out;
+  int64_t n;
+  int32_t in_dtype;
+  int32_t out_dtype;
+} nrm_row;
 
 typedef struct nrm_ctx nrm_ctx;
 
@@ -105,6 +134,15 @@ typedef struct nrm_ctx nrm_ctx;
 /* out[i] = in[i] / sum(in[0..n)) for i in [0, n). Fig. 1 semantics with the
  * sum hoisted (Sec. IV-C). in, out: device arrays of n floats. */
 int normalize(float* out, const float* in, int64_t n);
+
+/* Ragged batched, CSR form: row r in [0, rows) is the slice
+ * [offsets[r], offsets[r+1]) of both `in` and `out`, normalized on its own.
+ * offsets: DEVICE array of rows + 1 int64, offsets[0] >= 0, non-decreasing;
+ * empty rows are allowed. FP32, default context, null stream. The library
+ * reads offsets[rows] back to the host (synchronizing the null stream) to
+ * size its workspace and to bound every row; rows that violate the rules are
+ * skipped and reported by nrm_get_device_error. */
+int normalize_batched(float* out, const float* in, const int64_t* offsets, int64_t rows);
 
 /* ---- contexts ------------------------------------------------------------ */
 
@@ -128,6 +166,107 @@ int nrm_get_params(const nrm_ctx* ctx, nrm_params* params);
 int nrm_normalize_ex(nrm_ctx* ctx, void* out, int out_dtype, const void* in, int in_dtype,
                      int64_t n, int accum, void* stream);
 
+/* ---- extended batched forms ---------------------------------------------- */
+
+/* CSR form with dtypes, accumulation, context and stream. `capacity` is the
+ * number of elements `in` and `out` hold: every row must lie inside
+ * [0, capacity), which the device checks (rows outside are skipped and
+ * flagged). capacity < 0: read offsets[rows] back and use it (synchronizes
+ * `stream`). The workspace is sized for rows and capacity. */
+int nrm_normalize_batched_ex(nrm_ctx* ctx, void* out, int out_dtype, const void* in, int in_dtype,
+                             const int64_t* offsets, int64_t rows, int64_t capacity, int accum,
+                             void* stream);
+
+/* Table form: `rows` is a HOST array of nrows descriptors (device data
+ * pointers), copied to the device through the context's pinned staging
+ * memory; rows may mix dtypes. Rows are validated on the host. The staging
+ * buffer is reused only after the previous call's copy has executed. */
+int nrm_normalize_rows(nrm_ctx* ctx, const nrm_row* rows, int64_t nrows, int accum, void* stream);
+
+/* Reserve batched workspace for up to max_rows rows and max_elems elements
+ * in total (optional: calls grow it on demand, which synchronizes the
+ * device; a captured graph needs a fixed workspace). */
+int nrm_batch_reserve(nrm_ctx* ctx, int64_t max_rows, int64_t max_elems);
+
+int nrm_default_batch_params(nrm_batch_params* params);
+int nrm_set_batch_params(nrm_ctx* ctx, const nrm_batch_params* params);
+int nrm_get_batch_params(const nrm_ctx* ctx, nrm_batch_params* params);
+
+/* Synchronize `stream`, then return NRM_EDEVICE if a batched call on this
+ * context found invalid rows or ran out of workspace since the last check
+ * (and clear the flag), else NRM_OK. nrm_last_error() names the cause. */
+int nrm_get_device_error(nrm_ctx* ctx, void* stream);
+
+/* ---- continuous-batching server --------------------------------------------- */
+
+/* A normalize request: `in` is a device array of n elements of in_dtype that
+ * stays valid until the request completes; the output is allocated by the
+ * server. t_arrival_ns: for nrm_server_submit, the arrival time on the
+ * steady clock in ns (0: now); for nrm_server_replay, the offset of the
+ * scheduled arrival from the start of the replay. */
+typedef struct {
+  int64_t id;
+  const void* in;
+  int64_t n;
+  int32_t in_dtype;
+  int32_t out_dtype;
+  int64_t t_arrival_ns;
+} nrm_request;
+
+typedef struct {
+  int64_t id;
+  void* out;             /* device output (valid until released when hold_outputs) */
+  int64_t t_arrival_ns;  /* scheduled arrival (steady clock, ns) */
+  int64_t t_launch_ns;   /* when its batch was launched */
+  int64_t t_done_ns;     /* when its completion was observed */
+  int32_t status;
+  int32_t pad;
+} nrm_completion;
+
+typedef struct {
+  int32_t slots;             /* concurrent batches (each its own stream, workspace, graph): 1..64 */
+  int32_t batching;          /* 1: one ragged batched launch per admitted group; 0: one plain call per request */
+  int32_t graph;             /* 1: batched launches replay a captured hipGraph */
+  int32_t accum;             /* nrm_accum */
+  int32_t hold_outputs;      /* 1: outputs (and their budget) stay until nrm_server_release */
+  int32_t use_batch_params;  /* 1: use batch_params for the slots, else the library defaults */
+  int64_t budget_bytes;      /* HBM admission budget: input + output bytes of admitted requests */
+  int64_t arena_bytes;       /* device arena for outputs (0: two thirds of the budget) */
+  int64_t max_batch_rows;    /* requests per batch */
+  int64_t max_batch_elems;   /* elements per batch (a single larger request still runs alone) */
+  nrm_batch_params batch_params;
+} nrm_server_config;
+
+typedef struct {
+  int64_t in_flight;   /* submitted and not completed */
+  int64_t queued;      /* waiting for admission */
+  int64_t held;        /* completed, output not released */
+  int64_t budget_used; /* bytes */
+  int64_t batches;
+  int64_t launches;    /* library calls made (batched calls or plain calls) */
+  int64_t replaying;
+} nrm_server_counters;
+
+typedef struct nrm_server nrm_server;
+
+int nrm_server_default_config(nrm_server_config* cfg);
+/* Start a server on `device` (-1: current): allocates the output arena and
+ * one context, stream and event per slot, and starts the scheduler thread. */
+int nrm_server_create(nrm_server** server, int device, const nrm_server_config* cfg);
+/* Queue requests now (thread-safe). A request larger than the budget is
+ * NRM_EINVAL; otherwise it waits until memory and a slot free up. */
+int nrm_server_submit(nrm_server* server, const nrm_request* reqs, int64_t count);
+/* Submit a trace from a background thread at its scheduled times (open
+ * loop; requests sorted by t_arrival_ns). *t0_ns receives the start time. */
+int nrm_server_replay(nrm_server* server, const nrm_request* reqs, int64_t count, int64_t* t0_ns);
+/* Move up to max completions into out; *count receives how many. */
+int nrm_server_poll(nrm_server* server, nrm_completion* out, int64_t max, int64_t* count);
+/* Release a held output (hold_outputs = 1). */
+int nrm_server_release(nrm_server* server, int64_t id);
+int nrm_server_stats(nrm_server* server, nrm_server_counters* counters);
+/* Stop accepting replays, finish all queued and in-flight work, free everything. */
+int nrm_server_destroy(nrm_server* server);
+
 /* ---- diagnostics and measurement ------------------------------------------ */
 
 /* Static text for a status code. */
@@ -136,12 +275,16 @@ const char* nrm_status_string(int status);
 const char* nrm_last_error(void);
 
 /* Kernel timing: while enabled, every plain call records HIP events around
- * its reduce and map kernels on the call's stream. nrm_kernel_times
+ * its reduce and map kernels on the call's stream (batched calls: around the
+ * whole call). nrm_kernel_times
  * synchronizes those events and returns the summed durations (ms) and the
  * number of calls recorded since timing was last enabled (the last 1024 calls
  * are kept). */
 int nrm_set_timing(nrm_ctx* ctx, int enable);
 int nrm_kernel_times(nrm_ctx* ctx, double* reduce_ms, double* map_ms, int64_t* calls);
+/* The same for batched calls: summed duration of each call's whole launch
+ * sequence (staging copy, planner, both phases), and the number of calls. */
+int nrm_batch_times(nrm_ctx* ctx, double* total_ms, int64_t* calls);
 
 #ifdef __cplusplus
 }

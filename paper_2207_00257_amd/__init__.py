@@ -8,7 +8,7 @@ is not built).
 
 
 def __getattr__(name):
-    if name in ("normalize", "Context"):
+    if name in ("normalize", "normalize_batched", "normalize_rows", "device_error", "Context"):
         from . import api
 
         return getattr(api, name)

@@ -32,8 +32,76 @@ class NrmParams(ctypes.Structure):
         ("map_layout", ctypes.c_int32),
         ("map_nt", ctypes.c_int32),
         ("reverse_map", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("reduce_keep_mib", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
+
+
+class NrmBatchParams(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32),
+        ("unroll", ctypes.c_int32),
+        ("map_unroll", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("tile_log2", ctypes.c_int32),
+        ("short_regs", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
+class NrmRow(ctypes.Structure):
+    _fields_ = [
+        ("in_", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("in_dtype", ctypes.c_int32),
+        ("out_dtype", ctypes.c_int32),
+    ]
+
+
+class NrmRequest(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("in_", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("in_dtype", ctypes.c_int32),
+        ("out_dtype", ctypes.c_int32),
+        ("t_arrival_ns", ctypes.c_int64),
+    ]
+
+
+class NrmCompletion(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("out", ctypes.c_void_p),
+        ("t_arrival_ns", ctypes.c_int64),
+        ("t_launch_ns", ctypes.c_int64),
+        ("t_done_ns", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+
+class NrmServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int32),
+        ("batching", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
+        ("accum", ctypes.c_int32),
+        ("hold_outputs", ctypes.c_int32),
+        ("use_batch_params", ctypes.c_int32),
+        ("budget_bytes", ctypes.c_int64),
+        ("arena_bytes", ctypes.c_int64),
+        ("max_batch_rows", ctypes.c_int64),
+        ("max_batch_elems", ctypes.c_int64),
+        ("batch_params", NrmBatchParams),
+    ]
+
+
+class NrmServerCounters(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("in_flight", "queued", "held", "budget_used", "batches", "launches", "replaying")]
 
 
 class NrmError(RuntimeError):
@@ -60,6 +128,23 @@ def _declare(lib):
         "nrm_set_timing": (i32, [p, i32]),
         "nrm_kernel_times": (i32, [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64)]),
+        "nrm_batch_times": (i32, [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+        "normalize_batched": (i32, [p, p, p, i64]),
+        "nrm_normalize_batched_ex": (i32, [p, p, i32, p, i32, p, i64, i64, i32, p]),
+        "nrm_normalize_rows": (i32, [p, ctypes.POINTER(NrmRow), i64, i32, p]),
+        "nrm_batch_reserve": (i32, [p, i64, i64]),
+        "nrm_default_batch_params": (i32, [ctypes.POINTER(NrmBatchParams)]),
+        "nrm_set_batch_params": (i32, [p, ctypes.POINTER(NrmBatchParams)]),
+        "nrm_get_batch_params": (i32, [p, ctypes.POINTER(NrmBatchParams)]),
+        "nrm_get_device_error": (i32, [p, p]),
+        "nrm_server_default_config": (i32, [ctypes.POINTER(NrmServerConfig)]),
+        "nrm_server_create": (i32, [ctypes.POINTER(p), i32, ctypes.POINTER(NrmServerConfig)]),
+        "nrm_server_submit": (i32, [p, ctypes.POINTER(NrmRequest), i64]),
+        "nrm_server_replay": (i32, [p, ctypes.POINTER(NrmRequest), i64, ctypes.POINTER(ctypes.c_int64)]),
+        "nrm_server_poll": (i32, [p, ctypes.POINTER(NrmCompletion), i64, ctypes.POINTER(ctypes.c_int64)]),
+        "nrm_server_release": (i32, [p, i64]),
+        "nrm_server_stats": (i32, [p, ctypes.POINTER(NrmServerCounters)]),
+        "nrm_server_destroy": (i32, [p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -81,6 +81,40 @@ class Context:
     def normalize(self, out, inp, accum: str = "f32", stream: Optional[int] = None):
         return normalize(out, inp, accum=accum, ctx=self, stream=stream)
 
+    def normalize_batched(self, out, inp, offsets, accum: str = "f32", stream: Optional[int] = None):
+        return normalize_batched(out, inp, offsets, accum=accum, ctx=self, stream=stream)
+
+    def normalize_rows(self, pairs, accum: str = "f32", stream: Optional[int] = None):
+        return normalize_rows(pairs, accum=accum, ctx=self, stream=stream)
+
+    def get_batch_params(self) -> dict:
+        p = L.NrmBatchParams()
+        L.check(L.lib().nrm_get_batch_params(self.handle, ctypes.byref(p)), "nrm_get_batch_params")
+        return {f: getattr(p, f) for f, _ in L.NrmBatchParams._fields_ if f != "reserved"}
+
+    def set_batch_params(self, **kw) -> None:
+        cur = self.get_batch_params()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise ValueError("unknown batch parameters %s" % sorted(unknown))
+        cur.update(kw)
+        p = L.NrmBatchParams(**cur)
+        L.check(L.lib().nrm_set_batch_params(self.handle, ctypes.byref(p)), "nrm_set_batch_params")
+
+    def batch_reserve(self, max_rows: int, max_elems: int) -> None:
+        L.check(L.lib().nrm_batch_reserve(self.handle, int(max_rows), int(max_elems)), "nrm_batch_reserve")
+
+    def device_error(self, stream: Optional[int] = None) -> int:
+        """Synchronize and return the status of the device-side row checks
+        (NRM_OK or NRM_EDEVICE), clearing the flag."""
+        return device_error(self, stream)
+
+    def batch_times(self):
+        """(total_ms, calls) summed over the batched calls recorded since timing was enabled."""
+        t, c = ctypes.c_double(), ctypes.c_int64()
+        L.check(L.lib().nrm_batch_times(self.handle, ctypes.byref(t), ctypes.byref(c)), "nrm_batch_times")
+        return t.value, c.value
+
     def set_timing(self, enable: bool) -> None:
         L.check(L.lib().nrm_set_timing(self.handle, int(bool(enable))), "nrm_set_timing")
 
@@ -105,3 +139,62 @@ def normalize(out, inp, accum: str = "f32", ctx: Optional[Context] = None, strea
                                   inp.data_ptr(), _dtype_code(inp), inp.numel(), _ACCUM[accum], s)
     L.check(st, "nrm_normalize_ex")
     return out
+
+
+def normalize_batched(out, inp, offsets, accum: str = "f32", ctx: Optional[Context] = None,
+                      stream: Optional[int] = None):
+    """Ragged batched normalize, CSR form: row r is inp[offsets[r]:offsets[r+1]]
+    (and the same slice of out), normalized on its own. offsets: int64 device
+    tensor of rows + 1 entries. The device checks every row against the
+    tensors' length; see device_error()."""
+    import torch
+
+    _check_tensors(out, inp)
+    if accum not in _ACCUM:
+        raise ValueError("accum must be 'f32' or 'kahan'")
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous int64 device tensor")
+    if offsets.device != inp.device:
+        raise ValueError("offsets is on another device")
+    rows = offsets.numel() - 1
+    if rows < 0:
+        raise ValueError("offsets needs rows + 1 >= 1 entries")
+    s = _stream_of(inp) if stream is None else stream
+    st = L.lib().nrm_normalize_batched_ex(ctx.handle if ctx else None, out.data_ptr(), _dtype_code(out),
+                                          inp.data_ptr(), _dtype_code(inp), offsets.data_ptr(), rows,
+                                          inp.numel(), _ACCUM[accum], s)
+    L.check(st, "nrm_normalize_batched_ex")
+    return out
+
+
+def normalize_rows(pairs, accum: str = "f32", ctx: Optional[Context] = None, stream: Optional[int] = None):
+    """Batched normalize of independent rows: pairs is a sequence of
+    (out, inp) device tensors (each pair contiguous, same length; dtypes may
+    differ between rows). One launch sequence for the whole batch."""
+    if accum not in _ACCUM:
+        raise ValueError("accum must be 'f32' or 'kahan'")
+    pairs = list(pairs)
+    table = (L.NrmRow * max(1, len(pairs)))()
+    dev = None
+    for i, (out, inp) in enumerate(pairs):
+        _check_tensors(out, inp)
+        dev = inp.device if dev is None else dev
+        if inp.device != dev:
+            raise ValueError("rows on different devices")
+        table[i].in_ = inp.data_ptr()
+        table[i].out = out.data_ptr()
+        table[i].n = inp.numel()
+        table[i].in_dtype = _dtype_code(inp)
+        table[i].out_dtype = _dtype_code(out)
+    if not pairs:
+        return
+    s = _stream_of(pairs[0][1]) if stream is None else stream
+    st = L.lib().nrm_normalize_rows(ctx.handle if ctx else None, table, len(pairs), _ACCUM[accum], s)
+    L.check(st, "nrm_normalize_rows")
+
+
+def device_error(ctx: Optional[Context] = None, stream: Optional[int] = None) -> int:
+    import torch
+
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    return L.lib().nrm_get_device_error(ctx.handle if ctx else None, s)

@@ -11,38 +11,20 @@
 #include <string>
 #include <vector>
 
-#include "nrm_internal.h"
+#include "nrm_ctx.h"
 
-namespace {
+using nrm::fail;
+using nrm::hip_fail;
+using nrm::kTimingRing;
+using nrm::DeviceGuard;
 
-thread_local std::string g_last_error;
-
-int fail(int status, const std::string& what) {
-  g_last_error = what;
-  return status;
+namespace nrm {
+std::string& last_error() {
+  thread_local std::string msg;
+  return msg;
 }
+}  // namespace nrm
 
-int hip_fail(hipError_t e, const char* where) {
-  return fail(NRM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
-}
-
-constexpr int kTimingRing = 1024;
-
-}  // namespace
-
-struct nrm_ctx {
-  int device = 0;
-  nrm_params params{};
-  // plain-path workspace
-  void* partials = nullptr;
-  int64_t partials_cap = 0;  // entries (each up to 8 bytes)
-  unsigned* ticket = nullptr;
-  float* sum = nullptr;      // 2 floats
-  // kernel timing
-  bool timing = false;
-  std::vector<hipEvent_t> events;  // 3 per recorded call
-  int64_t timed_calls = 0;
-};
 
 namespace {
 
@@ -80,6 +62,7 @@ int check_params(const nrm_params& p) {
   if (p.max_height < 24 || p.max_height > 48) return fail(NRM_EINVAL, "max_height must be 24..48");
   if (!ok_f(p.reduce_nt) || !ok_f(p.map_nt) || !ok_f(p.reverse_map))
     return fail(NRM_EINVAL, "reduce_nt, map_nt and reverse_map must be 0 or 1");
+  if (p.reduce_keep_mib < 0 || p.reduce_keep_mib > 4096) return fail(NRM_EINVAL, "reduce_keep_mib must be 0..4096");
   for (int r : p.reserved)
     if (r != 0) return fail(NRM_EINVAL, "reserved fields must be zero");
   return NRM_OK;
@@ -88,37 +71,9 @@ int check_params(const nrm_params& p) {
 std::mutex g_default_mu;
 std::map<int, nrm_ctx*> g_default;
 
-class DeviceGuard {
- public:
-  explicit DeviceGuard(int dev) {
-    hipGetDevice(&prev_);
-    if (prev_ != dev) hipSetDevice(dev);
-    dev_ = dev;
-  }
-  ~DeviceGuard() {
-    if (prev_ != dev_) hipSetDevice(prev_);
-  }
+}  // namespace
 
- private:
-  int prev_ = 0, dev_ = 0;
-};
-
-int ensure_partials(nrm_ctx* c, int64_t entries) {
-  if (entries <= c->partials_cap) return NRM_OK;
-  int64_t cap = std::max<int64_t>(entries, 16384);
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, (size_t)cap * 8);
-  if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
-  if (c->partials) {
-    hipError_t e2 = hipDeviceSynchronize();  // the old buffer may still be in use
-    hipFree(c->partials);
-    if (e2 != hipSuccess) return hip_fail(e2, "hipDeviceSynchronize");
-  }
-  c->partials = p;
-  c->partials_cap = cap;
-  return NRM_OK;
-}
-
+namespace nrm {
 int default_ctx(nrm_ctx** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -136,6 +91,27 @@ int default_ctx(nrm_ctx** out) {
   *out = c;
   return NRM_OK;
 }
+}  // namespace nrm
+
+namespace {
+
+
+int ensure_partials(nrm_ctx* c, int64_t entries) {
+  if (entries <= c->partials_cap) return NRM_OK;
+  int64_t cap = std::max<int64_t>(entries, 16384);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, (size_t)cap * 8);
+  if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+  if (c->partials) {
+    hipError_t e2 = hipDeviceSynchronize();  // the old buffer may still be in use
+    hipFree(c->partials);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipDeviceSynchronize");
+  }
+  c->partials = p;
+  c->partials_cap = cap;
+  return NRM_OK;
+}
+
 
 bool valid_dtype(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
 
@@ -187,6 +163,7 @@ int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_d
   p->map_layout = q.map_layout;
   p->map_nt = q.map_nt;
   p->reverse_map = q.reverse_map;
+  p->keep_from = std::max<int64_t>(0, p->nvec - ((int64_t)q.reduce_keep_mib << 20) / 16);
   // Iterations per reduce block are bounded so that the height of a thread's
   // summation tree stays within max_height (plain mode); compensated chains
   // have no such bound (their error does not grow with the chain).
@@ -227,7 +204,7 @@ const char* nrm_status_string(int status) {
   }
 }
 
-const char* nrm_last_error(void) { return g_last_error.c_str(); }
+const char* nrm_last_error(void) { return nrm::last_error().c_str(); }
 
 int nrm_create(nrm_ctx** ctx, int device) {
   if (!ctx) return fail(NRM_EINVAL, "ctx is NULL");
@@ -244,6 +221,7 @@ int nrm_create(nrm_ctx** ctx, int device) {
   nrm_ctx* c = new nrm_ctx();
   c->device = device;
   c->params = default_params();
+  nrm_default_batch_params(&c->bparams);
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
     c->params.grid = cus;           // one reduce block per CU
@@ -283,6 +261,7 @@ int nrm_destroy(nrm_ctx* c) {
   DeviceGuard g(c->device);
   hipDeviceSynchronize();
   for (hipEvent_t ev : c->events) hipEventDestroy(ev);
+  nrm::batch_free(c);
   if (c->partials) hipFree(c->partials);
   if (c->ticket) hipFree(c->ticket);
   delete c;
@@ -318,9 +297,15 @@ int nrm_set_timing(nrm_ctx* c, int enable) {
       hipError_t e = hipEventCreate(&ev);
       if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
+    c->batch.events.resize(2 * kTimingRing);
+    for (auto& ev : c->batch.events) {
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
   }
   c->timing = enable != 0;
   c->timed_calls = 0;
+  c->batch.timed_calls = 0;
   return NRM_OK;
 }
 
@@ -358,7 +343,7 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
   if (ranges_partially_overlap(in, n * si, out, n * so))
     return fail(NRM_EOVERLAP, "in and out overlap without being the same array");
   if (!c) {
-    int st = default_ctx(&c);
+    int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
   nrm::PlainPlan plan;

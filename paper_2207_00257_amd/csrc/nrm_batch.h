@@ -1,0 +1,79 @@
+// Internal interface of the ragged batched path: the device-side header and
+// row table a batch is described by, the workspace pointers the kernels use,
+// and the launch plan. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nrm.h"
+
+namespace nrm {
+
+// One row as the kernels see it (same layout as the public nrm_row).
+struct RowDesc {
+  const char* in;
+  char* out;
+  int64_t n;
+  int32_t in_dt;
+  int32_t out_dt;
+};
+static_assert(sizeof(RowDesc) == sizeof(nrm_row), "RowDesc must match nrm_row");
+
+enum { BATCH_CSR = 0, BATCH_TABLE = 1 };
+
+// Per-call inputs, written to device memory before the launches so that a
+// captured graph can replay with new contents.
+struct BatchHeader {
+  int64_t nrows;
+  int32_t mode;            // BATCH_CSR or BATCH_TABLE
+  int32_t csr_in_dt, csr_out_dt;
+  int32_t pad;
+  const int64_t* offsets;  // CSR: rows + 1 offsets (device)
+  const char* csr_in;
+  char* csr_out;
+  int64_t capacity;        // CSR: elements addressable through csr_in / csr_out
+  const RowDesc* table;    // TABLE: device row table
+};
+
+// Device error bits (OR-ed by the planner, read by nrm_get_device_error).
+enum {
+  NRM_DEVERR_OFFSETS = 1,   // CSR offsets negative, decreasing or past capacity
+  NRM_DEVERR_ROW = 2,       // a table row with n < 0, bad dtype, NULL pointer, or too many tiles
+  NRM_DEVERR_CAPACITY = 4,  // more rows or work items than the workspace holds
+};
+
+constexpr int64_t MAX_ROW_TILES = 65536;  // partials the per-row combine merges
+
+// One work item: a tile of a long row, or a whole short row (tile 0).
+struct Item {
+  int32_t row;
+  int32_t tile;
+};
+
+// Kernel arguments: workspace pointers, fixed for a context's workspace.
+struct BatchArgs {
+  const BatchHeader* hdr;
+  RowDesc* rows;         // resolved rows [cap_rows]
+  Item* items;           // [cap_items]: the long rows' tiles first, then the short rows
+  int64_t* n_items;      // [2]: all items, items that are tiles of long rows
+  int* error;            // [1]
+  void* partials;        // [cap_items] x 8 bytes
+  int64_t cap_rows;
+  int64_t cap_items;
+  int64_t tile;          // elements per tile of a long row
+  int64_t short_max;     // rows with n <= short_max take one pass
+};
+
+struct BatchPlan {
+  int acc;
+  int block;
+  int unroll;       // tile reduce: vectors per thread per iteration
+  int map_unroll;   // tile map
+  int short_regs;   // vectors per thread held for a single-pass row
+  int64_t grid;     // persistent blocks
+};
+
+hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s);
+
+}  // namespace nrm

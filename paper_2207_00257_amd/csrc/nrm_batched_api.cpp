@@ -1,0 +1,445 @@
+// C ABI of the ragged batched path (include/nrm.h): workspace and pinned
+// staging management, host validation, the launch sequence (planner, phase 1,
+// phase 2) and its optional capture in a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "nrm_ctx.h"
+
+using nrm::BatchArgs;
+using nrm::BatchHeader;
+using nrm::BatchPlan;
+using nrm::BatchWorkspace;
+using nrm::DeviceGuard;
+using nrm::RowDesc;
+using nrm::fail;
+using nrm::hip_fail;
+
+namespace {
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t align_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+nrm_batch_params default_batch_params() {
+  nrm_batch_params p;
+  std::memset(&p, 0, sizeof(p));
+  // the tuner's best on MI355X for the 4096-row ragged workload
+  p.block = 1024;
+  p.unroll = 2;
+  p.map_unroll = 2;
+  p.grid = 1024;
+  p.tile_log2 = 15;
+  p.short_regs = 2;
+  p.graph = 0;
+  return p;
+}
+
+int check_batch_params(const nrm_batch_params& p) {
+  auto ok_u = [](int u) { return u == 1 || u == 2 || u == 4 || u == 8; };
+  if (p.block < 64 || p.block > 1024 || p.block % 64) return fail(NRM_EINVAL, "block must be 64..1024, a multiple of 64");
+  if (!ok_u(p.unroll) || !ok_u(p.map_unroll) || !ok_u(p.short_regs))
+    return fail(NRM_EINVAL, "unroll, map_unroll and short_regs must be 1, 2, 4 or 8");
+  if (p.grid < 1 || p.grid > (1 << 20)) return fail(NRM_EINVAL, "grid must be 1..2^20");
+  if (p.tile_log2 < 10 || p.tile_log2 > 22) return fail(NRM_EINVAL, "tile_log2 must be 10..22");
+  if (p.graph != 0 && p.graph != 1) return fail(NRM_EINVAL, "graph must be 0 or 1");
+  for (int r : p.reserved)
+    if (r != 0) return fail(NRM_EINVAL, "reserved fields must be zero");
+  // a tile's per-thread summation tree must stay within the plain path's
+  // height bound (36) for every input dtype: 4-byte elements give the most
+  // iterations, 2-byte elements the most additions per iteration
+  const int64_t tile = int64_t(1) << p.tile_log2;
+  for (int dt : {NRM_F32, NRM_BF16}) {
+    int64_t iters = ceil_div(tile, (int64_t)p.block * p.unroll * nrm::dtype_vec(dt));
+    if (nrm::thread_tree_height(dt, NRM_ACC_F32, p.unroll, iters) > 36)
+      return fail(NRM_EINVAL, "tile too long for block * unroll: a thread's summation tree would exceed height 36");
+  }
+  return NRM_OK;
+}
+
+int64_t short_max_of(const nrm_batch_params& p) { return (int64_t)p.block * p.short_regs * 4; }
+
+void destroy_graph(BatchWorkspace& w) {
+  if (w.graph) hipGraphExecDestroy(w.graph);
+  w.graph = nullptr;
+  w.graph_acc = -1;
+}
+
+// Layout of the single device allocation.
+struct Layout {
+  size_t hdr, table, rows, items, small, partials, total;
+};
+
+Layout layout_for(int64_t cap_rows, int64_t cap_items) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = (size_t)align_up((int64_t)(off + bytes), 256);
+    return at;
+  };
+  L.hdr = take(sizeof(BatchHeader));
+  L.table = take(sizeof(RowDesc) * cap_rows);
+  L.rows = take(sizeof(RowDesc) * cap_rows);
+  L.items = take(sizeof(nrm::Item) * cap_items);
+  L.small = take(64);  // n_items (2 x 8 bytes) + error (4 bytes)
+  L.partials = take(8 * cap_items);
+  L.total = off;
+  return L;
+}
+
+int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
+  BatchWorkspace& w = c->batch;
+  if (rows <= w.cap_rows && items <= w.cap_items && w.dev) return NRM_OK;
+  int64_t cap_rows = std::max<int64_t>({rows, w.cap_rows, 64});
+  int64_t cap_items = std::max<int64_t>({items, w.cap_items, 1024});
+  Layout L = layout_for(cap_rows, cap_items);
+  // the old buffers may still be in use by enqueued work
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  destroy_graph(w);
+  void* dev = nullptr;
+  e = hipMalloc(&dev, L.total);
+  if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("batched workspace hipMalloc: ") + hipGetErrorString(e));
+  void* host = nullptr;
+  e = hipHostMalloc(&host, L.table + sizeof(RowDesc) * cap_rows, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    hipFree(dev);
+    return fail(NRM_ENOMEM, std::string("pinned staging hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  int err_word = 0;
+  if (w.dev) {
+    hipMemcpy(&err_word, w.error, sizeof(int), hipMemcpyDeviceToHost);  // keep a pending device error
+    hipFree(w.dev);
+  }
+  if (w.host) hipHostFree(w.host);
+  char* d = static_cast<char*>(dev);
+  w.dev = dev;
+  w.host = host;
+  w.hdr = reinterpret_cast<BatchHeader*>(d + L.hdr);
+  w.table = reinterpret_cast<RowDesc*>(d + L.table);
+  w.rows = reinterpret_cast<RowDesc*>(d + L.rows);
+  w.items = reinterpret_cast<nrm::Item*>(d + L.items);
+  w.n_items = reinterpret_cast<int64_t*>(d + L.small);
+  w.error = reinterpret_cast<int*>(d + L.small + 16);
+  w.partials = d + L.partials;
+  w.cap_rows = cap_rows;
+  w.cap_items = cap_items;
+  w.staged_pending = false;
+  e = hipMemset(d + L.small, 0, 64);
+  if (e == hipSuccess && err_word) e = hipMemcpy(w.error, &err_word, sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemset");
+  if (!w.staged) {
+    e = hipEventCreateWithFlags(&w.staged, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  }
+  return NRM_OK;
+}
+
+// Items a batch of `rows` rows and at most `elems` elements can need.
+int64_t items_bound(const nrm_batch_params& p, int64_t rows, int64_t elems) {
+  return rows + ceil_div(std::max<int64_t>(elems, 0), int64_t(1) << p.tile_log2);
+}
+
+BatchArgs args_of(const nrm_ctx* c) {
+  const BatchWorkspace& w = c->batch;
+  BatchArgs a;
+  a.hdr = w.hdr;
+  a.rows = w.rows;
+  a.items = w.items;
+  a.n_items = w.n_items;
+  a.error = w.error;
+  a.partials = w.partials;
+  a.cap_rows = w.cap_rows;
+  a.cap_items = w.cap_items;
+  a.tile = int64_t(1) << c->bparams.tile_log2;
+  a.short_max = short_max_of(c->bparams);
+  return a;
+}
+
+BatchPlan plan_of(const nrm_ctx* c, int acc) {
+  BatchPlan p;
+  p.acc = acc;
+  p.block = c->bparams.block;
+  p.unroll = c->bparams.unroll;
+  p.map_unroll = c->bparams.map_unroll;
+  p.short_regs = c->bparams.short_regs;
+  p.grid = c->bparams.grid;
+  return p;
+}
+
+// Bytes of staging copied per call: the header, plus the table in table mode.
+// A captured graph always copies the header and a full-capacity table.
+size_t staged_bytes(const BatchWorkspace& w, int64_t table_rows) {
+  return (size_t)(reinterpret_cast<char*>(w.table) - reinterpret_cast<char*>(w.hdr)) +
+         sizeof(RowDesc) * (size_t)table_rows;
+}
+
+int capture_graph(nrm_ctx* c, int acc) {
+  BatchWorkspace& w = c->batch;
+  destroy_graph(w);
+  hipError_t e;
+  if (!w.capture_stream) {
+    e = hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  }
+  e = hipStreamBeginCapture(w.capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t e1 = hipMemcpyAsync(w.hdr, w.host, staged_bytes(w, w.cap_rows), hipMemcpyHostToDevice,
+                                 w.capture_stream);
+  hipError_t e2 = e1 == hipSuccess ? nrm::launch_batch(plan_of(c, acc), args_of(c), w.capture_stream) : e1;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(w.capture_stream, &graph);
+  if (e1 != hipSuccess) return hip_fail(e1, "hipMemcpyAsync (capture)");
+  if (e2 != hipSuccess) return hip_fail(e2, "batched launch (capture)");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&w.graph, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    w.graph = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  w.graph_acc = acc;
+  return NRM_OK;
+}
+
+// Stage the header (and table), then run the three kernels on `s`.
+int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nrows, int acc,
+              hipStream_t s) {
+  BatchWorkspace& w = c->batch;
+  hipError_t e;
+  if (w.staged_pending) {  // the previous call's copy must have read the staging buffer
+    e = hipEventSynchronize(w.staged);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    w.staged_pending = false;
+  }
+  BatchHeader hd = h;
+  hd.table = w.table;
+  std::memcpy(w.host, &hd, sizeof(hd));
+  char* host_table = static_cast<char*>(w.host) + (reinterpret_cast<char*>(w.table) - reinterpret_cast<char*>(w.hdr));
+  if (table) std::memcpy(host_table, table, sizeof(RowDesc) * (size_t)nrows);
+  hipEvent_t* ev = nullptr;
+  if (c->timing) {
+    ev = &w.events[2 * (w.timed_calls % nrm::kTimingRing)];
+    w.timed_calls++;
+    hipEventRecord(ev[0], s);
+  }
+  if (c->bparams.graph) {
+    if (!w.graph || w.graph_acc != acc) {
+      int st = capture_graph(c, acc);
+      if (st != NRM_OK) return st;
+    }
+    e = hipGraphLaunch(w.graph, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  } else {
+    e = hipMemcpyAsync(w.hdr, w.host, staged_bytes(w, table ? nrows : 0), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = nrm::launch_batch(plan_of(c, acc), args_of(c), s);
+    if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
+  }
+  if (ev) hipEventRecord(ev[1], s);
+  e = hipEventRecord(w.staged, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  w.staged_pending = true;
+  return NRM_OK;
+}
+
+bool valid_dtype(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
+
+}  // namespace
+
+namespace nrm {
+void batch_free(nrm_ctx* c) {
+  BatchWorkspace& w = c->batch;
+  destroy_graph(w);
+  if (w.capture_stream) hipStreamDestroy(w.capture_stream);
+  if (w.staged) hipEventDestroy(w.staged);
+  for (hipEvent_t ev : w.events) hipEventDestroy(ev);
+  if (w.dev) hipFree(w.dev);
+  if (w.host) hipHostFree(w.host);
+  w = BatchWorkspace();
+}
+}  // namespace nrm
+
+extern "C" {
+
+int nrm_default_batch_params(nrm_batch_params* params) {
+  if (!params) return fail(NRM_EINVAL, "NULL argument");
+  *params = default_batch_params();
+  return NRM_OK;
+}
+
+int nrm_set_batch_params(nrm_ctx* c, const nrm_batch_params* params) {
+  if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  int st = check_batch_params(*params);
+  if (st != NRM_OK) return st;
+  if (std::memcmp(params, &c->bparams, sizeof(*params)) != 0) {
+    DeviceGuard g(c->device);
+    if (c->batch.graph) {
+      hipDeviceSynchronize();
+      destroy_graph(c->batch);
+    }
+    c->bparams = *params;
+  }
+  return NRM_OK;
+}
+
+int nrm_get_batch_params(const nrm_ctx* c, nrm_batch_params* params) {
+  if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  *params = c->bparams;
+  return NRM_OK;
+}
+
+int nrm_batch_reserve(nrm_ctx* c, int64_t max_rows, int64_t max_elems) {
+  if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  if (max_rows < 0 || max_elems < 0) return fail(NRM_EINVAL, "negative reservation");
+  if (max_rows > INT32_MAX) return fail(NRM_EINVAL, "more than 2^31 - 1 rows");
+  DeviceGuard g(c->device);
+  return reserve(c, max_rows, items_bound(c->bparams, max_rows, max_elems));
+}
+
+namespace {
+int check_csr_buffers(const void* out, int out_dtype, const void* in, int in_dtype, int64_t capacity) {
+  const int64_t si = nrm::dtype_size(in_dtype), so = nrm::dtype_size(out_dtype);
+  if (!in || !out) return fail(NRM_EINVAL, "NULL data pointer");
+  if (capacity > INT64_MAX / 8) return fail(NRM_EINVAL, "capacity too large");
+  if ((reinterpret_cast<uintptr_t>(in) % si) || (reinterpret_cast<uintptr_t>(out) % so))
+    return fail(NRM_EINVAL, "in or out is not aligned to its element size");
+  uintptr_t a0 = (uintptr_t)in, a1 = a0 + (uintptr_t)(capacity * si);
+  uintptr_t b0 = (uintptr_t)out, b1 = b0 + (uintptr_t)(capacity * so);
+  if (a0 < b1 && b0 < a1 && !(a0 == b0 && si == so))
+    return fail(NRM_EOVERLAP, "in and out overlap without being the same array");
+  return NRM_OK;
+}
+}  // namespace
+
+int nrm_normalize_batched_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype,
+                             const int64_t* offsets, int64_t rows, int64_t capacity, int accum,
+                             void* stream) {
+  if (rows < 0) return fail(NRM_EINVAL, "rows < 0");
+  if (!valid_dtype(in_dtype) || !valid_dtype(out_dtype)) return fail(NRM_EINVAL, "unknown dtype");
+  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
+  if (rows == 0) return NRM_OK;
+  if (rows > INT32_MAX) return fail(NRM_EINVAL, "more than 2^31 - 1 rows");
+  if (!offsets) return fail(NRM_EINVAL, "offsets is NULL");
+  if (capacity == 0) return NRM_OK;  // every row is empty (or invalid)
+  if (capacity > 0) {
+    int st = check_csr_buffers(out, out_dtype, in, in_dtype, capacity);
+    if (st != NRM_OK) return st;
+  }
+  if (!c) {
+    int st = nrm::default_ctx(&c);
+    if (st != NRM_OK) return st;
+  }
+  DeviceGuard g(c->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (capacity < 0) {
+    int64_t last = 0;
+    hipError_t e = hipMemcpyAsync(&last, offsets + rows, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading offsets[rows]");
+    if (last <= 0) return NRM_OK;
+    capacity = last;
+    int st = check_csr_buffers(out, out_dtype, in, in_dtype, capacity);
+    if (st != NRM_OK) return st;
+  }
+  int st = reserve(c, rows, items_bound(c->bparams, rows, capacity));
+  if (st != NRM_OK) return st;
+  BatchHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.nrows = rows;
+  h.mode = nrm::BATCH_CSR;
+  h.csr_in_dt = in_dtype;
+  h.csr_out_dt = out_dtype;
+  h.offsets = offsets;
+  h.csr_in = static_cast<const char*>(in);
+  h.csr_out = static_cast<char*>(out);
+  h.capacity = capacity;
+  return run_batch(c, h, nullptr, rows, accum, s);
+}
+
+int normalize_batched(float* out, const float* in, const int64_t* offsets, int64_t rows) {
+  return nrm_normalize_batched_ex(nullptr, out, NRM_F32, in, NRM_F32, offsets, rows, -1, NRM_ACC_F32, nullptr);
+}
+
+int nrm_normalize_rows(nrm_ctx* c, const nrm_row* rows, int64_t nrows, int accum, void* stream) {
+  if (nrows < 0) return fail(NRM_EINVAL, "nrows < 0");
+  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
+  if (nrows == 0) return NRM_OK;
+  if (nrows > INT32_MAX) return fail(NRM_EINVAL, "more than 2^31 - 1 rows");
+  if (!rows) return fail(NRM_EINVAL, "rows is NULL");
+  int64_t total = 0, longest = 0;
+  for (int64_t r = 0; r < nrows; ++r) {
+    const nrm_row& d = rows[r];
+    if (d.n < 0) return fail(NRM_EINVAL, "row with n < 0");
+    if (!valid_dtype(d.in_dtype) || !valid_dtype(d.out_dtype)) return fail(NRM_EINVAL, "row with unknown dtype");
+    if (d.n == 0) continue;
+    if (!d.in || !d.out) return fail(NRM_EINVAL, "row with NULL data pointer");
+    const int64_t si = nrm::dtype_size(d.in_dtype), so = nrm::dtype_size(d.out_dtype);
+    if ((reinterpret_cast<uintptr_t>(d.in) % si) || (reinterpret_cast<uintptr_t>(d.out) % so))
+      return fail(NRM_EINVAL, "row pointer not aligned to its element size");
+    uintptr_t a0 = (uintptr_t)d.in, a1 = a0 + (uintptr_t)(d.n * si);
+    uintptr_t b0 = (uintptr_t)d.out, b1 = b0 + (uintptr_t)(d.n * so);
+    if (a0 < b1 && b0 < a1 && !(a0 == b0 && si == so))
+      return fail(NRM_EOVERLAP, "a row's in and out overlap without being the same array");
+    total += d.n;
+    longest = std::max(longest, d.n);
+  }
+  if (!c) {
+    int st = nrm::default_ctx(&c);
+    if (st != NRM_OK) return st;
+  }
+  if (longest > (int64_t(1) << c->bparams.tile_log2) * nrm::MAX_ROW_TILES)
+    return fail(NRM_EINVAL, "row too long for the batched path's tile size");
+  DeviceGuard g(c->device);
+  int st = reserve(c, nrows, items_bound(c->bparams, nrows, total));
+  if (st != NRM_OK) return st;
+  BatchHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.nrows = nrows;
+  h.mode = nrm::BATCH_TABLE;
+  return run_batch(c, h, rows, nrows, accum, static_cast<hipStream_t>(stream));
+}
+
+int nrm_get_device_error(nrm_ctx* c, void* stream) {
+  if (!c) {
+    int st = nrm::default_ctx(&c);
+    if (st != NRM_OK) return st;
+  }
+  DeviceGuard g(c->device);
+  if (!c->batch.dev) return NRM_OK;
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  int word = 0;
+  e = hipMemcpy(&word, c->batch.error, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading the device error flag");
+  if (!word) return NRM_OK;
+  e = hipMemset(c->batch.error, 0, sizeof(int));
+  if (e != hipSuccess) return hip_fail(e, "clearing the device error flag");
+  std::string why;
+  if (word & nrm::NRM_DEVERR_OFFSETS) why += "CSR offsets negative, decreasing or past capacity; ";
+  if (word & nrm::NRM_DEVERR_ROW) why += "invalid table row or row with too many tiles; ";
+  if (word & nrm::NRM_DEVERR_CAPACITY) why += "batch larger than the workspace; ";
+  return fail(NRM_EDEVICE, why + "those rows were skipped");
+}
+
+int nrm_batch_times(nrm_ctx* c, double* total_ms, int64_t* calls) {
+  if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  BatchWorkspace& w = c->batch;
+  double t = 0;
+  int64_t k = std::min<int64_t>(w.timed_calls, nrm::kTimingRing);
+  for (int64_t i = 0; i < k; ++i) {
+    hipError_t e = hipEventSynchronize(w.events[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, w.events[2 * i], w.events[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    t += ms;
+  }
+  if (total_ms) *total_ms = t;
+  if (calls) *calls = k;
+  return NRM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// The context object behind nrm_ctx* and host-side helpers shared by the
+// C ABI's translation units. Private to libnrm.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "nrm_batch.h"
+#include "nrm_internal.h"
+
+namespace nrm {
+
+std::string& last_error();
+
+inline int fail(int status, const std::string& what) {
+  last_error() = what;
+  return status;
+}
+
+inline int hip_fail(hipError_t e, const char* where) {
+  return fail(NRM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kTimingRing = 1024;
+
+// Makes `dev` current for the guard's lifetime.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    hipGetDevice(&prev_);
+    if (prev_ != dev) hipSetDevice(dev);
+    dev_ = dev;
+  }
+  ~DeviceGuard() {
+    if (prev_ != dev_) hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = 0, dev_ = 0;
+};
+
+
+// Device workspace and host staging of the batched path.
+struct BatchWorkspace {
+  int64_t cap_rows = 0;
+  int64_t cap_items = 0;
+  void* dev = nullptr;         // one allocation, carved into the pointers below
+  BatchHeader* hdr = nullptr;  // followed by the table copy target
+  RowDesc* table = nullptr;
+  RowDesc* rows = nullptr;
+  Item* items = nullptr;
+  int64_t* n_items = nullptr;
+  int* error = nullptr;
+  void* partials = nullptr;
+  void* host = nullptr;        // pinned staging: header + table
+  hipEvent_t staged = nullptr; // recorded once the staging buffer may be rewritten
+  bool staged_pending = false;
+  // captured launch sequence
+  hipGraphExec_t graph = nullptr;
+  hipStream_t capture_stream = nullptr;
+  int graph_acc = -1;
+  // timing ring of (before, after) event pairs
+  std::vector<hipEvent_t> events;
+  int64_t timed_calls = 0;
+};
+
+}  // namespace nrm
+
+struct nrm_ctx {
+  nrm_batch_params bparams{};
+  nrm::BatchWorkspace batch;
+  int device = 0;
+  nrm_params params{};
+  // plain-path workspace
+  void* partials = nullptr;
+  int64_t partials_cap = 0;  // entries (each up to 8 bytes)
+  unsigned* ticket = nullptr;
+  float* sum = nullptr;      // 2 floats
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // 3 per recorded call
+  int64_t timed_calls = 0;
+};
+
+namespace nrm {
+// The process-wide default context of the current device (created on first use).
+int default_ctx(nrm_ctx** out);
+// Release the batched workspace of a context (waits for the device).
+void batch_free(nrm_ctx* c);
+}  // namespace nrm

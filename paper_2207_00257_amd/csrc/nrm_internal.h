@@ -58,6 +58,7 @@ struct PlainPlan {
   int64_t chunk;      // vectors per block (layout CHUNK; multiple of block * unroll)
   int layout;         // NRM_LAYOUT_*
   int reduce_nt;      // non-temporal hint on loads
+  int64_t keep_from;  // vectors from this index on are loaded with a temporal hint
   // map kernel
   int map_block;
   int map_unroll;

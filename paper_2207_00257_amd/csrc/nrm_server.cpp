@@ -1,0 +1,461 @@
+// Continuous-batching server for normalize requests (C ABI in include/nrm.h).
+//
+// A request is one normalize of n elements whose input already lives in
+// device memory. The scheduler thread
+//   1. polls the slots: a slot whose batch has finished (its event) releases
+//      its requests' output blocks and budget and reports them complete;
+//   2. admits waiting requests in arrival order while the HBM budget (input +
+//      output bytes of every admitted request) and a free slot allow;
+//   3. launches the admitted requests as one ragged batch (row-table form)
+//      on the free slot's stream, or, in per-request mode, one plain
+//      normalize call per request.
+// Requests that arrive while batches are in flight join the next batch as
+// soon as a slot and memory free up; several slots run concurrently.
+// A replay thread can submit a whole trace at its scheduled arrival times
+// (open loop); latency is measured from the scheduled arrival.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "nrm_ctx.h"
+
+using nrm::DeviceGuard;
+using nrm::fail;
+using nrm::hip_fail;
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Arena {
+ public:
+  explicit Arena(int64_t size) { free_[0] = size; }
+  // Offset of a block of `bytes` (rounded up to 256), or -1.
+  int64_t alloc(int64_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        int64_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_[off] = bytes;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off) {
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    int64_t len = u->second;
+    used_.erase(u);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && next->first == off + len) {
+      len += next->second;
+      free_.erase(next);
+    }
+    auto prev = free_.lower_bound(off);
+    if (prev != free_.begin()) {
+      --prev;
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+
+ private:
+  std::map<int64_t, int64_t> free_;  // offset -> length
+  std::map<int64_t, int64_t> used_;
+};
+
+struct Pending {
+  nrm_request req;
+  int64_t t_submit = 0;  // when the server saw it
+  int64_t t_arrival = 0; // scheduled arrival (the latency origin)
+  int64_t out_off = -1;
+  int64_t budget = 0;
+  int64_t t_launch = 0;
+};
+
+struct Slot {
+  nrm_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<Pending> reqs;
+};
+
+}  // namespace
+
+struct nrm_server {
+  nrm_server_config cfg{};
+  std::map<int64_t, Pending> held;    // completed, output not yet released (hold_outputs)
+  int device = 0;
+  char* arena_base = nullptr;
+  Arena* arena = nullptr;
+  int64_t budget_used = 0;
+  std::vector<Slot> slots;
+  std::mutex mu;                      // guards queue, done, counters
+  std::condition_variable cv;
+  std::deque<Pending> queue;
+  std::vector<nrm_completion> done;
+  std::atomic<bool> stop{false};
+  std::thread scheduler;
+  std::thread replayer;
+  std::atomic<int> replay_running{0};
+  int64_t in_flight = 0;
+  int64_t batches = 0;
+  int64_t launches = 0;
+  int64_t rejected = 0;
+  int error = NRM_OK;
+  std::string error_msg;
+  int64_t t0 = 0;                     // origin of the replay schedule
+
+  void run();
+  void launch(Slot& s, std::vector<Pending>& batch);
+};
+
+namespace {
+
+bool valid_dtype(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
+
+int check_request(const nrm_request& r) {
+  if (r.n < 0) return fail(NRM_EINVAL, "request with n < 0");
+  if (!valid_dtype(r.in_dtype) || !valid_dtype(r.out_dtype)) return fail(NRM_EINVAL, "request with unknown dtype");
+  if (r.n > 0 && !r.in) return fail(NRM_EINVAL, "request with NULL input");
+  return NRM_OK;
+}
+
+}  // namespace
+
+void nrm_server::launch(Slot& s, std::vector<Pending>& batch) {
+  const int64_t t = now_ns();
+  std::vector<nrm_row> rows(batch.size());
+  for (size_t i = 0; i < batch.size(); ++i) {
+    Pending& p = batch[i];
+    p.t_launch = t;
+    rows[i].in = p.req.in;
+    rows[i].out = arena_base + p.out_off;
+    rows[i].n = p.req.n;
+    rows[i].in_dtype = p.req.in_dtype;
+    rows[i].out_dtype = p.req.out_dtype;
+  }
+  int st = NRM_OK;
+  if (cfg.batching) {
+    st = nrm_normalize_rows(s.ctx, rows.data(), (int64_t)rows.size(), cfg.accum, s.stream);
+    launches += 1;
+  } else {
+    for (const nrm_row& r : rows) {
+      st = nrm_normalize_ex(s.ctx, r.out, r.out_dtype, r.in, r.in_dtype, r.n, cfg.accum, s.stream);
+      if (st != NRM_OK) break;
+      launches += 1;
+    }
+  }
+  if (st == NRM_OK) {
+    hipError_t e = hipEventRecord(s.done, s.stream);
+    if (e != hipSuccess) st = hip_fail(e, "hipEventRecord");
+  }
+  if (st != NRM_OK) {
+    std::lock_guard<std::mutex> lk(mu);
+    error = st;
+    error_msg = nrm_last_error();
+  }
+  s.reqs.swap(batch);
+  s.busy = true;
+  batches += 1;
+}
+
+void nrm_server::run() {
+  DeviceGuard g(device);
+  std::vector<Pending> batch;
+  while (true) {
+    bool progressed = false;
+    // 1. completions
+    for (Slot& s : slots) {
+      if (!s.busy) continue;
+      hipError_t e = hipEventQuery(s.done);
+      if (e == hipErrorNotReady) continue;
+      const int64_t t = now_ns();
+      std::lock_guard<std::mutex> lk(mu);
+      if (e != hipSuccess && error == NRM_OK) {
+        error = NRM_EHIP;
+        error_msg = std::string("hipEventQuery: ") + hipGetErrorString(e);
+      }
+      for (Pending& p : s.reqs) {
+        if (cfg.hold_outputs) {
+          held[p.req.id] = p;
+        } else {
+          arena->release(p.out_off);
+          budget_used -= p.budget;
+        }
+        nrm_completion c;
+        c.id = p.req.id;
+        c.out = arena_base + p.out_off;
+        c.t_arrival_ns = p.t_arrival;
+        c.t_launch_ns = p.t_launch;
+        c.t_done_ns = t;
+        c.status = e == hipSuccess ? NRM_OK : NRM_EHIP;
+        done.push_back(c);
+        in_flight -= 1;
+      }
+      s.reqs.clear();
+      s.busy = false;
+      progressed = true;
+    }
+    // 2. admission into one free slot at a time, in arrival order
+    for (Slot& s : slots) {
+      if (s.busy) continue;
+      batch.clear();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        int64_t elems = 0;
+        while (!queue.empty() && (int64_t)batch.size() < cfg.max_batch_rows) {
+          Pending& p = queue.front();
+          const int64_t so = nrm::dtype_size(p.req.out_dtype), si = nrm::dtype_size(p.req.in_dtype);
+          const int64_t need = p.req.n * (si + so);
+          if (!batch.empty() && elems + p.req.n > cfg.max_batch_elems) break;
+          if (budget_used + need > cfg.budget_bytes) break;  // wait for memory
+          int64_t off = arena->alloc(std::max<int64_t>(p.req.n * so, 1));
+          if (off < 0) break;
+          p.out_off = off;
+          p.budget = need;
+          budget_used += need;
+          elems += p.req.n;
+          batch.push_back(p);
+          queue.pop_front();
+        }
+      }
+      if (batch.empty()) break;
+      launch(s, batch);
+      progressed = true;
+    }
+    if (stop.load() && !progressed) {
+      bool idle = true;
+      for (Slot& s : slots) idle = idle && !s.busy;
+      std::lock_guard<std::mutex> lk(mu);
+      if (idle && queue.empty()) break;
+    }
+    if (!progressed) {
+      std::unique_lock<std::mutex> lk(mu);
+      bool any_busy = false;
+      for (Slot& s : slots) any_busy = any_busy || s.busy;
+      if (any_busy) {
+        lk.unlock();
+        std::this_thread::yield();  // poll the slots' events again
+      } else {
+        cv.wait_for(lk, std::chrono::microseconds(200));
+      }
+    }
+  }
+}
+
+extern "C" {
+
+int nrm_server_default_config(nrm_server_config* cfg) {
+  if (!cfg) return fail(NRM_EINVAL, "NULL argument");
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->slots = 4;
+  cfg->budget_bytes = int64_t(64) << 30;
+  cfg->arena_bytes = 0;
+  cfg->max_batch_rows = 256;
+  cfg->max_batch_elems = int64_t(1) << 27;
+  cfg->batching = 1;
+  cfg->graph = 1;
+  cfg->accum = NRM_ACC_F32;
+  return NRM_OK;
+}
+
+int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg) {
+  if (!out || !cfg) return fail(NRM_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (cfg->slots < 1 || cfg->slots > 64) return fail(NRM_EINVAL, "slots must be 1..64");
+  if (cfg->budget_bytes < 1) return fail(NRM_EINVAL, "budget_bytes must be positive");
+  if (cfg->max_batch_rows < 1 || cfg->max_batch_rows > (int64_t(1) << 20)) return fail(NRM_EINVAL, "max_batch_rows must be 1..2^20");
+  if (cfg->max_batch_elems < 1) return fail(NRM_EINVAL, "max_batch_elems must be positive");
+  if (cfg->batching != 0 && cfg->batching != 1) return fail(NRM_EINVAL, "batching must be 0 or 1");
+  if (cfg->graph != 0 && cfg->graph != 1) return fail(NRM_EINVAL, "graph must be 0 or 1");
+  if (cfg->accum != NRM_ACC_F32 && cfg->accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
+  if (cfg->hold_outputs != 0 && cfg->hold_outputs != 1) return fail(NRM_EINVAL, "hold_outputs must be 0 or 1");
+  if (cfg->use_batch_params != 0 && cfg->use_batch_params != 1) return fail(NRM_EINVAL, "use_batch_params must be 0 or 1");
+  if (device < 0) {
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  }
+  DeviceGuard g(device);
+  nrm_server* s = new nrm_server();
+  s->cfg = *cfg;
+  s->device = device;
+  // outputs live in the arena; a request's output is at most two thirds of
+  // its budget (FP32 out of a 2-byte input), which sizes the default arena
+  const int64_t arena = cfg->arena_bytes > 0 ? cfg->arena_bytes : cfg->budget_bytes * 2 / 3 + (int64_t(1) << 20);
+  hipError_t e = hipMalloc(&s->arena_base, (size_t)arena);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(NRM_ENOMEM, std::string("server arena hipMalloc: ") + hipGetErrorString(e));
+  }
+  s->arena = new Arena(arena);
+  s->slots.resize(cfg->slots);
+  for (Slot& sl : s->slots) {
+    int st = nrm_create(&sl.ctx, device);
+    if (st == NRM_OK) {
+      nrm_batch_params bp;
+      nrm_get_batch_params(sl.ctx, &bp);
+      bp.graph = cfg->graph;
+      if (cfg->use_batch_params) bp = cfg->batch_params;
+      st = nrm_set_batch_params(sl.ctx, &bp);
+    }
+    if (st == NRM_OK) st = nrm_batch_reserve(sl.ctx, cfg->max_batch_rows, cfg->max_batch_elems);
+    if (st == NRM_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
+      st = fail(NRM_EHIP, "hipStreamCreate");
+    if (st == NRM_OK && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+      st = fail(NRM_EHIP, "hipEventCreate");
+    if (st != NRM_OK) {
+      nrm_server_destroy(s);
+      return st;
+    }
+  }
+  s->scheduler = std::thread([s] { s->run(); });
+  *out = s;
+  return NRM_OK;
+}
+
+int nrm_server_submit(nrm_server* s, const nrm_request* reqs, int64_t count) {
+  if (!s || (count > 0 && !reqs) || count < 0) return fail(NRM_EINVAL, "bad arguments");
+  for (int64_t i = 0; i < count; ++i) {
+    int st = check_request(reqs[i]);
+    if (st != NRM_OK) return st;
+    const int64_t need = reqs[i].n * (nrm::dtype_size(reqs[i].in_dtype) + nrm::dtype_size(reqs[i].out_dtype));
+    if (need > s->cfg.budget_bytes) return fail(NRM_EINVAL, "request larger than the server's budget");
+  }
+  const int64_t t = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int64_t i = 0; i < count; ++i) {
+      Pending p;
+      p.req = reqs[i];
+      p.t_submit = t;
+      p.t_arrival = reqs[i].t_arrival_ns > 0 ? reqs[i].t_arrival_ns : t;
+      s->queue.push_back(p);
+      s->in_flight += 1;
+    }
+  }
+  s->cv.notify_one();
+  return NRM_OK;
+}
+
+int nrm_server_replay(nrm_server* s, const nrm_request* reqs, int64_t count, int64_t* t0_ns) {
+  if (!s || count < 0 || (count > 0 && !reqs)) return fail(NRM_EINVAL, "bad arguments");
+  if (s->replay_running.load()) return fail(NRM_EINVAL, "a replay is already running");
+  for (int64_t i = 0; i < count; ++i) {
+    int st = check_request(reqs[i]);
+    if (st != NRM_OK) return st;
+    if (i > 0 && reqs[i].t_arrival_ns < reqs[i - 1].t_arrival_ns) return fail(NRM_EINVAL, "arrivals out of order");
+  }
+  if (s->replayer.joinable()) s->replayer.join();
+  std::vector<nrm_request> trace(reqs, reqs + count);
+  const int64_t origin = now_ns() + 2000000;  // start 2 ms from now
+  if (t0_ns) *t0_ns = origin;
+  s->replay_running.store(1);
+  s->replayer = std::thread([s, trace, origin] {
+    size_t i = 0;
+    while (i < trace.size() && !s->stop.load()) {
+      const int64_t due = origin + trace[i].t_arrival_ns;
+      int64_t t = now_ns();
+      if (t < due) {
+        if (due - t > 200000) std::this_thread::sleep_for(std::chrono::nanoseconds(due - t - 100000));
+        continue;
+      }
+      // submit every request that is due, stamped with its scheduled arrival
+      size_t j = i;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        while (j < trace.size() && origin + trace[j].t_arrival_ns <= t) {
+          Pending p;
+          p.req = trace[j];
+          p.t_submit = t;
+          p.t_arrival = origin + trace[j].t_arrival_ns;
+          s->queue.push_back(p);
+          s->in_flight += 1;
+          ++j;
+        }
+      }
+      s->cv.notify_one();
+      i = j;
+    }
+    s->replay_running.store(0);
+  });
+  return NRM_OK;
+}
+
+int nrm_server_poll(nrm_server* s, nrm_completion* out, int64_t max, int64_t* count) {
+  if (!s || !count || max < 0 || (max > 0 && !out)) return fail(NRM_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int64_t k = std::min<int64_t>(max, (int64_t)s->done.size());
+  for (int64_t i = 0; i < k; ++i) out[i] = s->done[i];
+  s->done.erase(s->done.begin(), s->done.begin() + k);
+  *count = k;
+  if (s->error != NRM_OK) return fail(s->error, s->error_msg);
+  return NRM_OK;
+}
+
+int nrm_server_release(nrm_server* s, int64_t id) {
+  if (!s) return fail(NRM_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->held.find(id);
+  if (it == s->held.end()) return fail(NRM_EINVAL, "no held output with this id");
+  s->arena->release(it->second.out_off);
+  s->budget_used -= it->second.budget;
+  s->held.erase(it);
+  s->cv.notify_one();
+  return NRM_OK;
+}
+
+int nrm_server_stats(nrm_server* s, nrm_server_counters* st) {
+  if (!s || !st) return fail(NRM_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  st->in_flight = s->in_flight;
+  st->queued = (int64_t)s->queue.size();
+  st->budget_used = s->budget_used;
+  st->batches = s->batches;
+  st->launches = s->launches;
+  st->replaying = s->replay_running.load();
+  st->held = (int64_t)s->held.size();
+  return NRM_OK;
+}
+
+int nrm_server_destroy(nrm_server* s) {
+  if (!s) return NRM_OK;
+  s->stop.store(true);
+  s->cv.notify_all();
+  if (s->replayer.joinable()) s->replayer.join();
+  if (s->scheduler.joinable()) s->scheduler.join();
+  DeviceGuard g(s->device);
+  for (Slot& sl : s->slots) {
+    if (sl.stream) hipStreamSynchronize(sl.stream);
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.stream) hipStreamDestroy(sl.stream);
+    if (sl.ctx) nrm_destroy(sl.ctx);
+  }
+  if (s->arena_base) hipFree(s->arena_base);
+  delete s->arena;
+  delete s;
+  return NRM_OK;
+}
+
+}  // extern "C"

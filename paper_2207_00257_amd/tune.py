@@ -48,6 +48,20 @@ def load_params(path, in_dtype, out_dtype, accum, n):
     return dict(ent["params"]) if ent else None
 
 
+def load_batch_params(path=None, workload="ragged4096"):
+    """Tuned batched parameters for this device from a cache file, or None."""
+    import torch
+
+    path = path or DEFAULT_CACHE
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        cache = json.load(f)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    ent = cache.get("%s/batched/f32->f32/f32/%s" % (arch, workload))
+    return dict(ent["params"]) if ent else None
+
+
 def _time_call(ctx, out, inp, accum, reps):
     from . import api
 
@@ -102,12 +116,70 @@ def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=Fa
         table.append({"kernel": "map", "params": p, "ms": mt})
         if mt < best_mt:
             best_m, best_mt = p, mt
+    # the tail the reduce leaves in the last-level cache, read first by a reverse map
+    for keep, rev, nt in itertools.product((0, 64, 128, 192, 256, 384), (0, 1), (0, 1)):
+        if nt == 0 and keep:
+            continue  # all of the reduce's loads are temporal anyway
+        if True:
+            p = dict(best_m, reduce_keep_mib=keep, reverse_map=rev, reduce_nt=nt)
+            ctx.set_params(**p)
+            rt, mt = _time_call(ctx, out, inp, accum, reps)
+            table.append({"kernel": "keep", "params": p, "ms": rt + mt, "reduce_ms": rt, "map_ms": mt})
+            if rt + mt < best_rt + best_mt:
+                best_m, best_rt, best_mt = p, rt, mt
     log("map sweep: %d candidates in %.1f s, best %.4f ms %s"
         % (len(map_space), time.time() - t0, best_mt, {k: best_m[k] for k in
                                                         ("map_layout", "map_block", "map_unroll", "map_grid",
                                                          "map_nt", "reverse_map")}))
     ctx.close()
     return best_m, best_rt, best_mt, table
+
+
+def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
+    """Sweep the batched path's launch shape on the ragged workload (rows with
+    log-uniform lengths in [32, 2^20], LogNormal(0,1) FP32), timing whole
+    calls (planner, both phases) with the library's events."""
+    import torch
+
+    from . import api, synth
+
+    dev = torch.device("cuda:0")
+    x, offs = synth.ragged_batch(rows, seed)
+    inp = torch.from_numpy(x).to(dev)
+    out = torch.empty_like(inp)
+    offs_d = torch.from_numpy(offs).to(dev)
+    ctx = api.Context()
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    space = []
+    for block in (256, 512, 1024):
+        for unroll in ((2, 4) if quick else (1, 2, 4, 8)):
+            for tile_log2 in ((14, 16) if quick else (13, 14, 15, 16, 17, 18)):
+                for short_regs in ((4, 8) if quick else (2, 4, 8)):
+                    for gmul in ((2, 4) if quick else (1, 2, 4, 8)):
+                        space.append(dict(block=block, unroll=unroll, map_unroll=unroll, tile_log2=tile_log2,
+                                          short_regs=short_regs, grid=cus * gmul * max(1, 1024 // block // 2),
+                                          graph=1))
+    table, best, best_t = [], None, float("inf")
+    t0 = time.time()
+    ctx.batch_reserve(rows, x.size)
+    for p in space:
+        try:
+            ctx.set_batch_params(**p)
+        except Exception:
+            continue  # shape rejected by the height bound
+        api.normalize_batched(out, inp, offs_d, ctx=ctx)
+        ctx.set_timing(True)
+        for _ in range(reps):
+            api.normalize_batched(out, inp, offs_d, ctx=ctx)
+        t, c = ctx.batch_times()
+        ctx.set_timing(False)
+        ms = t / c
+        table.append({"kernel": "batched", "params": p, "ms": ms})
+        if ms < best_t:
+            best, best_t = p, ms
+    log("batched sweep: %d candidates in %.1f s, best %.4f ms %s" % (len(table), time.time() - t0, best_t, best))
+    ctx.close()
+    return best, best_t, table
 
 
 def main(argv=None):
@@ -120,8 +192,27 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=None, help="JSON file for the best parameters")
     ap.add_argument("--table", default=None, help="JSON file for every measured candidate")
+    ap.add_argument("--batched", action="store_true", help="tune the ragged batched path instead")
     args = ap.parse_args(argv)
     import torch
+
+    if args.batched:
+        best, ms, table = sweep_batched(quick=args.quick)
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        key = "%s/batched/f32->f32/f32/ragged4096" % arch
+        print(json.dumps({"key": key, "params": best, "ms": ms}), flush=True)
+        if args.out:
+            cache = {}
+            if os.path.exists(args.out):
+                with open(args.out) as f:
+                    cache = json.load(f)
+            cache[key] = {"params": best, "ms": ms}
+            with open(args.out, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        if args.table:
+            with open(args.table, "w") as f:
+                json.dump(table, f)
+        return 0
 
     n = 1 << args.log2n
     out_dtype = args.out_dtype or args.dtype

@@ -70,3 +70,53 @@ def test_host_validation_before_any_hip_call(lib):
     assert lib.nrm_set_params(None, None) == L.NRM_EINVAL
     assert lib.nrm_create(None, 0) == L.NRM_EINVAL
     assert lib.nrm_destroy(None) == L.NRM_OK
+
+
+def test_batched_host_validation_before_any_hip_call(lib):
+    ex = lib.nrm_normalize_batched_ex
+    offs = 1 << 20  # an address only used for its non-NULL value; nothing is read at it
+    assert ex(None, 4096, 0, 8192, 0, offs, -1, 10, 0, None) == L.NRM_EINVAL   # rows < 0
+    assert ex(None, 4096, 0, 8192, 0, offs, 0, 10, 0, None) == L.NRM_OK        # no rows
+    assert ex(None, 4096, 0, 8192, 0, None, 3, 10, 0, None) == L.NRM_EINVAL    # NULL offsets
+    assert ex(None, 4096, 0, 8192, 0, offs, 3, 0, 0, None) == L.NRM_OK         # zero capacity
+    assert ex(None, 4096, 5, 8192, 0, offs, 3, 10, 0, None) == L.NRM_EINVAL    # bad dtype
+    assert ex(None, 4096, 0, 8192, 0, offs, 3, 10, 7, None) == L.NRM_EINVAL    # bad accumulation
+    assert ex(None, None, 0, 8192, 0, offs, 3, 10, 0, None) == L.NRM_EINVAL    # NULL out
+    assert ex(None, 4097, 0, 8192, 0, offs, 3, 10, 0, None) == L.NRM_EINVAL    # misaligned out
+    assert ex(None, 4100, 0, 4096, 0, offs, 3, 10, 0, None) == L.NRM_EOVERLAP  # partial overlap
+    rows = (L.NrmRow * 2)()
+    rows[0].in_, rows[0].out, rows[0].n = 8192, 4096, 4
+    rows[1].in_, rows[1].out, rows[1].n = 16384, 12288, -1
+    nr = lib.nrm_normalize_rows
+    assert nr(None, rows, -1, 0, None) == L.NRM_EINVAL
+    assert nr(None, rows, 0, 0, None) == L.NRM_OK
+    assert nr(None, None, 2, 0, None) == L.NRM_EINVAL
+    assert nr(None, rows, 2, 0, None) == L.NRM_EINVAL          # n < 0
+    rows[1].n, rows[1].in_dtype = 4, 9
+    assert nr(None, rows, 2, 0, None) == L.NRM_EINVAL          # bad dtype
+    rows[1].in_dtype, rows[1].out = 0, 16388
+    assert nr(None, rows, 2, 0, None) == L.NRM_EOVERLAP        # row overlaps itself
+    rows[1].out = 12288
+    assert nr(None, rows, 2, 5, None) == L.NRM_EINVAL          # bad accumulation
+    p = L.NrmBatchParams()
+    assert lib.nrm_default_batch_params(ctypes.byref(p)) == L.NRM_OK
+    assert p.block >= 64 and p.tile_log2 >= 10
+    assert lib.nrm_set_batch_params(None, ctypes.byref(p)) == L.NRM_EINVAL
+    assert lib.nrm_batch_reserve(None, 1, 1) == L.NRM_EINVAL
+
+
+def test_server_config_validation_before_any_hip_call(lib):
+    cfg = L.NrmServerConfig()
+    assert lib.nrm_server_default_config(ctypes.byref(cfg)) == L.NRM_OK
+    assert cfg.slots >= 1 and cfg.budget_bytes == 64 << 30 and cfg.batching == 1
+    h = ctypes.c_void_p()
+    for field, bad in (("slots", 0), ("slots", 65), ("budget_bytes", 0), ("max_batch_rows", 0),
+                       ("max_batch_elems", 0), ("batching", 2), ("graph", 5), ("accum", 3),
+                       ("hold_outputs", 7), ("use_batch_params", 2)):
+        c = L.NrmServerConfig()
+        lib.nrm_server_default_config(ctypes.byref(c))
+        setattr(c, field, bad)
+        assert lib.nrm_server_create(ctypes.byref(h), 0, ctypes.byref(c)) == L.NRM_EINVAL, field
+    assert lib.nrm_server_create(None, 0, ctypes.byref(cfg)) == L.NRM_EINVAL
+    assert lib.nrm_server_submit(None, None, 0) == L.NRM_EINVAL
+    assert lib.nrm_server_destroy(None) == L.NRM_OK

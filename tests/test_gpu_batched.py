@@ -1,0 +1,250 @@
+"""GPU parity of the ragged batched path (CSR and row-table forms, with and
+without hipGraph replay) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2207_00257_amd import _lib as L
+from paper_2207_00257_amd import api, synth
+from parity_util import assert_f32_close, assert_within_ulp, bf16_bits_to_f64, ulp_bf16
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def run_csr(x, offs, ctx=None, accum="f32", out_dtype=torch.float32):
+    inp = gpu(x)
+    out = torch.full((x.size,), -7.0, dtype=out_dtype, device=DEV)
+    api.normalize_batched(out, inp, gpu(offs), accum=accum, ctx=ctx)
+    torch.cuda.synchronize()
+    return out
+
+
+def check_rows(got, x, offs, what=""):
+    ref = oracle.normalize_batched(x, offs)
+    covered = np.zeros(x.size, bool)
+    for r in range(offs.size - 1):
+        covered[offs[r]:offs[r + 1]] = True
+    assert_f32_close(got[covered], ref[covered], what=what)
+    return covered
+
+
+def test_golden_three_rows_one_empty():
+    x = np.array([1, 3, 1, 1, 2], np.float32)
+    offs = np.array([0, 2, 2, 5], np.int64)
+    got = run_csr(x, offs).cpu().numpy()
+    assert list(got) == [0.25, 0.75, 0.25, 0.25, 0.5]
+
+
+LENGTHS = [0, 1, 2, 3, 31, 32, 33, 0, 1000, 4095, 4096, 4097, 8191, 8192, 8193, 65535, 65536, 65537,
+           300_001, 1, 0, 1 << 20, 7]
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+def test_mixed_lengths_short_and_tiled(accum):
+    lengths = np.array(LENGTHS, np.int64)
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 50, 1.0)
+    ctx = api.Context()
+    got = run_csr(x, offs, ctx, accum=accum).cpu().numpy()
+    check_rows(got, x, offs, "mixed lengths " + accum)
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+BATCH_PARAMS = [
+    dict(),
+    dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7),
+    dict(block=1024, unroll=8, map_unroll=8, short_regs=8, tile_log2=20, grid=256),
+    dict(block=512, unroll=2, map_unroll=4, short_regs=2, tile_log2=14, grid=3000),
+    dict(block=128, unroll=4, map_unroll=2, short_regs=4, tile_log2=12, grid=1),
+    dict(graph=1),
+    dict(graph=1, block=512, tile_log2=18, short_regs=4),
+]
+
+
+@pytest.mark.parametrize("params", BATCH_PARAMS, ids=lambda p: ",".join("%s=%s" % kv for kv in p.items()) or "default")
+def test_launch_parameters(params):
+    ctx = api.Context()
+    ctx.set_batch_params(**params)
+    lengths = synth.loguniform_lengths(300, 51, 1, 1 << 17)
+    lengths[::17] = 0
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 52, 1.0)
+    got = run_csr(x, offs, ctx).cpu().numpy()
+    check_rows(got, x, offs, str(params))
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+def test_graph_replays_with_new_batches_and_eager_work_between():
+    """One captured graph replayed for several different batches, with eager
+    library calls and synchronizations between the replays; every replay is
+    checked against the oracle and against the same batch run eagerly."""
+    gctx = api.Context()
+    gctx.set_batch_params(graph=1)
+    gctx.batch_reserve(512, 1 << 22)
+    ectx = api.Context()
+    for k in range(4):
+        lengths = synth.loguniform_lengths(200 + 50 * k, 60 + k, 1, 1 << 15)
+        offs = synth.ragged_offsets(lengths)
+        x = synth.lognormal_f32(int(offs[-1]), 70 + k, 1.0)
+        g_out = run_csr(x, offs, gctx)
+        e_out = run_csr(x, offs, ectx)  # eager work between replays
+        check_rows(g_out.cpu().numpy(), x, offs, "graph replay %d" % k)
+        assert torch.equal(g_out, e_out), k
+        y = synth.uniform_f32(100_000, 80 + k)
+        t = gpu(y)
+        api.normalize(t, t)  # plain eager call in between
+        torch.cuda.synchronize()
+    assert gctx.device_error() == L.NRM_OK
+    gctx.close()
+    ectx.close()
+
+
+def test_row_is_position_independent():
+    """A row's bits depend on its length, alignment and dtypes only: the same
+    row alone, or at another place in another batch (same 16-byte alignment),
+    gives identical bits."""
+    ctx = api.Context()
+    row = synth.lognormal_f32(100_004, 90, 1.0)  # a multiple of 4: the next row stays aligned
+    short = synth.lognormal_f32(3001, 91, 1.0)
+    alone = run_csr(row, np.array([0, row.size], np.int64), ctx).cpu().numpy()
+    alone_s = run_csr(short, np.array([0, short.size], np.int64), ctx).cpu().numpy()
+    filler = synth.lognormal_f32(4 * 12345, 92, 1.0)  # a multiple of 4 floats: same alignment after it
+    x = np.concatenate([filler, row, short, filler])
+    offs = np.array([0, 7, filler.size, filler.size + row.size, filler.size + row.size + short.size, x.size],
+                    np.int64)
+    got = run_csr(x, offs, ctx).cpu().numpy()
+    assert np.array_equal(got[filler.size:filler.size + row.size], alone)
+    assert np.array_equal(got[filler.size + row.size:filler.size + row.size + short.size], alone_s)
+    ctx.close()
+
+
+def test_bad_offsets_are_flagged_and_skipped():
+    """Decreasing, negative or out-of-capacity rows are skipped on the device
+    (never read or written) and reported; valid rows are still computed."""
+    x = synth.lognormal_f32(1000, 93, 1.0)
+    ctx = api.Context()
+    offs = np.array([0, 100, -5, 300, 1000], np.int64)  # row 1 decreasing, row 2 negative start
+    got = run_csr(x, offs, ctx).cpu().numpy()
+    assert ctx.device_error() == L.NRM_EDEVICE
+    assert ctx.device_error() == L.NRM_OK  # cleared
+    assert_f32_close(got[:100], oracle.normalize(x[:100]), what="row 0")
+    assert np.all(got[100:300] == -7.0)
+    assert_f32_close(got[300:1000], oracle.normalize(x[300:1000]), what="row 3")
+    # a row ending past the buffer is skipped, the buffer outside rows untouched
+    inp = gpu(x)
+    out = torch.full((1000,), -7.0, device=DEV)
+    bad = gpu(np.array([0, 500, 1200], np.int64))
+    api.normalize_batched(out, inp, bad, ctx=ctx)
+    assert ctx.device_error() == L.NRM_EDEVICE
+    o = out.cpu().numpy()
+    assert_f32_close(o[:500], oracle.normalize(x[:500]), what="valid row")
+    assert np.all(o[500:] == -7.0)
+    ctx.close()
+
+
+def test_rows_table_mixed_dtypes():
+    """Row-table form: each row has its own buffers and dtypes."""
+    specs = [("f32", "f32", 5000), ("bf16", "bf16", 70_000), ("f16", "f32", 1234), ("bf16", "f32", 200_000),
+             ("f32", "bf16", 33), ("f32", "f32", 1 << 18), ("f32", "f32", 0), ("f16", "f16", 3000)]
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+    pairs, refs, infos = [], [], []
+    for i, (di, do, n) in enumerate(specs):
+        v = synth.lognormal_f32(n, 100 + i, 1.0)
+        if di == "f32":
+            host, odt = v, "f32"
+        elif di == "bf16":
+            host, odt = synth.f32_to_bf16_bits(v), "bf16"
+        else:
+            host, odt = synth.f32_to_f16_bits(v), "f16"
+        inp = gpu(host.view(np.int16) if di != "f32" else host)
+        if di != "f32":
+            inp = inp.view(tdt[di])
+        out = torch.empty(n, dtype=tdt[do], device=DEV)
+        pairs.append((out, inp))
+        refs.append(oracle.normalize(host, odt) if n else np.zeros(0))
+        infos.append((di, do, n))
+    ctx = api.Context()
+    ctx.normalize_rows(pairs)
+    torch.cuda.synchronize()
+    for (out, _), ref, (di, do, n) in zip(pairs, refs, infos):
+        if n == 0:
+            continue
+        if do == "f32":
+            assert_f32_close(out.cpu().numpy(), ref, what="%s->%s n=%d" % (di, do, n))
+        elif do == "bf16":
+            got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
+            assert_within_ulp(got, ref, ulp_bf16, what="%s->bf16 n=%d" % (di, n))
+        else:
+            from parity_util import ulp_f16
+            assert_within_ulp(out.cpu().numpy().astype(np.float64), ref, ulp_f16, what="%s->f16" % di)
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+def test_rows_table_graph_replay_same_as_alone():
+    """Rows in a graph-replayed table batch equal the same rows run alone
+    (batch of one), bit for bit."""
+    ctx = api.Context()
+    ctx.set_batch_params(graph=1)
+    ctx.batch_reserve(64, 1 << 22)
+    xs = [synth.lognormal_f32(n, 110 + i, 1.0) for i, n in enumerate([10, 5000, 70_000, 300_000, 2048])]
+    ins = [gpu(v) for v in xs]
+    outs = [torch.empty_like(t) for t in ins]
+    ctx.normalize_rows(list(zip(outs, ins)))
+    torch.cuda.synchronize()
+    for v, t_in, t_out in zip(xs, ins, outs):
+        solo = torch.empty_like(t_in)
+        ctx.normalize_rows([(solo, t_in)])
+        torch.cuda.synchronize()
+        assert torch.equal(solo, t_out)
+        assert_f32_close(t_out.cpu().numpy(), oracle.normalize(v), what="n=%d" % v.size)
+    ctx.close()
+
+
+def test_misaligned_output_rows():
+    """Output buffer offset by one element from the input's alignment: the
+    element-wise store path."""
+    lengths = np.array([5, 5000, 100_000, 3], np.int64)
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 120, 1.0)
+    inp = gpu(x)
+    big = torch.full((x.size + 1,), -7.0, device=DEV)
+    out = big[1:]
+    api.normalize_batched(out, inp, gpu(offs))
+    torch.cuda.synchronize()
+    got = big.cpu().numpy()
+    assert got[0] == -7.0
+    check_rows(got[1:], x, offs, "misaligned out")
+
+
+def test_ragged_4096_rows_full_workload():
+    """The ragged benchmark workload: 4096 rows, lengths log-uniform in
+    [32, 2^20], LogNormal(0,1) FP32 values; every element against the oracle,
+    in the default (benchmark) launch configuration, through a captured graph."""
+    x, offs = synth.ragged_batch(4096, 4)
+    ctx = api.Context()
+    ctx.set_batch_params(graph=1)
+    got = run_csr(x, offs, ctx).cpu().numpy()
+    assert ctx.device_error() == L.NRM_OK
+    ref = oracle.normalize_batched(x, offs)
+    assert_f32_close(got, ref, what="4096 ragged rows")
+    ctx.close()
+
+
+def test_workspace_grows_between_calls():
+    ctx = api.Context()
+    for rows, hi, seed in ((10, 1000, 130), (2000, 1 << 16, 131), (5, 1 << 21, 132)):
+        lengths = synth.loguniform_lengths(rows, seed, 1, hi)
+        offs = synth.ragged_offsets(lengths)
+        x = synth.lognormal_f32(int(offs[-1]), seed, 1.0)
+        check_rows(run_csr(x, offs, ctx).cpu().numpy(), x, offs, "rows=%d" % rows)
+    ctx.close()

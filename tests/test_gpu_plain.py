@@ -162,6 +162,8 @@ PARAM_SETS = [
     dict(max_height=48, grid=65536, map_grid=65536),
     dict(layout=1, grid=8, unroll=8, block=1024, max_height=48),
     dict(layout=0, grid=3, unroll=1, block=64, max_height=48),
+    dict(reduce_keep_mib=1, reverse_map=1),
+    dict(reduce_keep_mib=4096, reverse_map=0, layout=0),
 ]
 
 

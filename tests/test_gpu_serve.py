@@ -1,0 +1,131 @@
+"""GPU tests of the continuous-batching server: results against the oracle,
+each result identical alone and in the mix, admission under a tight HBM
+budget, open-loop replay, and the per-request launch mode."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2207_00257_amd import _lib as L
+from paper_2207_00257_amd import serve
+from parity_util import assert_f32_close, assert_within_ulp, bf16_bits_to_f64, ulp_bf16
+
+pytestmark = pytest.mark.gpu
+
+
+_hip = None
+
+
+def loaded_hip():
+    """The HIP runtime this process already uses (the copy libnrm.so is bound
+    to), opened by its path so that no second runtime is loaded."""
+    global _hip
+    if _hip is None:
+        import ctypes
+
+        L.lib()
+        paths = sorted({ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln})
+        assert len(paths) == 1, paths
+        _hip = ctypes.CDLL(paths[0])
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return _hip
+
+
+def read_out(ptr, n, dt):
+    """Copy a device output (raw pointer) to the host."""
+    esz = 4 if dt == L.NRM_F32 else 2
+    host = np.empty(n, np.float32 if dt == L.NRM_F32 else np.uint16)
+    if n:
+        assert loaded_hip().hipMemcpy(host.ctypes.data, ptr, n * esz, 2) == 0  # device to host
+    return host
+
+
+def check_against_oracle(pool, n, dt, off, host_out, what):
+    if dt == L.NRM_F32:
+        ref = oracle.normalize(pool.host_f32[off:off + n])
+        assert_f32_close(host_out, ref, what=what)
+    else:
+        ref = oracle.normalize(pool.host_bf16[off:off + n], "bf16")
+        assert_within_ulp(bf16_bits_to_f64(host_out), ref, ulp_bf16, what=what)
+
+
+def make_requests(count, seed, hi=1 << 18):
+    tr = serve.make_trace(rate=1e6, duration_s=count / 1e6 * 1.5, seed=seed, lo=1, hi=hi)
+    k = min(count, tr["n"].size)
+    return tr["n"][:k], tr["in_dt"][:k]
+
+
+@pytest.mark.parametrize("batching", [True, False])
+def test_mix_matches_oracle_and_alone(batching):
+    ns, dts = make_requests(120, 5)
+    pool = serve.InputPool(int(ns.max()), 7)
+    offs = pool.offsets(ns, 8)
+    ptrs = pool.pointers(dts, offs)
+    ids = np.arange(ns.size)
+    srv = serve.Server(slots=3, hold_outputs=True, batching=batching, max_batch_rows=32)
+    srv.submit(ids, ptrs, ns, dts, dts)
+    comps = srv.wait_all(ns.size)
+    assert sorted(c[0] for c in comps) == list(ids)
+    mixed = {}
+    for c in comps:
+        i = c[0]
+        assert c[5] == L.NRM_OK
+        mixed[i] = read_out(c[1], int(ns[i]), int(dts[i]))
+        check_against_oracle(pool, int(ns[i]), int(dts[i]), int(offs[i]), mixed[i], "request %d" % i)
+        srv.release(i)
+    assert srv.stats()["budget_used"] == 0
+    srv.close()
+    # each request alone, on a fresh server with the same configuration
+    solo = serve.Server(slots=1, hold_outputs=True, batching=batching, max_batch_rows=32)
+    for i in range(0, ns.size, 7):
+        solo.submit([i], [ptrs[i]], [ns[i]], [dts[i]], [dts[i]])
+        (c,) = solo.wait_all(1)
+        alone = read_out(c[1], int(ns[i]), int(dts[i]))
+        assert np.array_equal(alone, mixed[i]), "request %d differs alone and in the mix" % i
+        solo.release(i)
+    solo.close()
+
+
+def test_tight_budget_admission():
+    """A 4 MiB budget: requests of up to 256 KiB in + out queue for memory,
+    all complete, and the budget is never exceeded."""
+    ns, dts = make_requests(200, 11, hi=1 << 15)
+    pool = serve.InputPool(int(ns.max()), 12, span=1 << 20)
+    offs = pool.offsets(ns, 13)
+    ptrs = pool.pointers(dts, offs)
+    budget = 4 << 20
+    srv = serve.Server(slots=4, budget_bytes=budget, max_batch_rows=16)
+    srv.submit(np.arange(ns.size), ptrs, ns, dts, dts)
+    seen_max = 0
+    done = []
+    while len(done) < ns.size:
+        st = srv.stats()
+        seen_max = max(seen_max, st["budget_used"])
+        done.extend(srv.poll())
+    assert seen_max <= budget
+    assert srv.stats()["budget_used"] == 0
+    srv.close()
+
+
+def test_request_larger_than_budget_is_rejected():
+    pool = serve.InputPool(1 << 16, 14, span=1 << 16)
+    srv = serve.Server(slots=1, budget_bytes=1 << 16)
+    with pytest.raises(L.NrmError):
+        srv.submit([0], [pool.f32.data_ptr()], [1 << 16], [L.NRM_F32], [L.NRM_F32])
+    srv.close()
+
+
+def test_open_loop_replay_completes_and_measures_latency():
+    tr = serve.make_trace(rate=20000, duration_s=0.1, seed=21, hi=1 << 20)
+    k = tr["n"].size
+    pool = serve.InputPool(int(tr["n"].max()), 22)
+    offs = pool.offsets(tr["n"], 23)
+    ptrs = pool.pointers(tr["in_dt"], offs)
+    srv = serve.Server(slots=4)
+    srv.replay(np.arange(k), ptrs, tr["n"], tr["in_dt"], tr["out_dt"], tr["t_ns"])
+    comps = srv.wait_all(k, timeout_s=60)
+    stats = serve.latency_stats(comps)
+    assert stats["requests"] == k
+    assert all(c[4] >= c[2] for c in comps)  # done after scheduled arrival
+    assert stats["p50_ms"] > 0 and stats["p99_ms"] >= stats["p50_ms"]
+    srv.close()

@@ -230,6 +230,10 @@ typedef struct {
   int32_t accum;             /* nrm_accum */
   int32_t hold_outputs;      /* 1: outputs (and their budget) stay until nrm_server_release */
   int32_t use_batch_params;  /* 1: use batch_params for the slots, else the library defaults */
+  int32_t single_plain;      /* 1: a group of one request runs the plain path (two kernels
+                                instead of the batched three); its bits then match the plain
+                                path rather than the batched one, both within the error bound */
+  int32_t pad;
   int64_t budget_bytes;      /* HBM admission budget: input + output bytes of admitted requests */
   int64_t arena_bytes;       /* device arena for outputs (0: two thirds of the budget) */
   int64_t max_batch_rows;    /* requests per batch */

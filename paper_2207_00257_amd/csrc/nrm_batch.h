@@ -22,8 +22,8 @@ static_assert(sizeof(RowDesc) == sizeof(nrm_row), "RowDesc must match nrm_row");
 
 enum { BATCH_CSR = 0, BATCH_TABLE = 1 };
 
-// Per-call inputs, written to device memory before the launches so that a
-// captured graph can replay with new contents.
+// Per-call inputs, written by the host into pinned memory that the planner
+// reads in place, so that a captured graph replays with new contents.
 struct BatchHeader {
   int64_t nrows;
   int32_t mode;            // BATCH_CSR or BATCH_TABLE
@@ -33,7 +33,7 @@ struct BatchHeader {
   const char* csr_in;
   char* csr_out;
   int64_t capacity;        // CSR: elements addressable through csr_in / csr_out
-  const RowDesc* table;    // TABLE: device row table
+  const RowDesc* table;    // TABLE: the row table (pinned host memory)
 };
 
 // Device error bits (OR-ed by the planner, read by nrm_get_device_error).

@@ -20,9 +20,10 @@
 // Each block walks items blockIdx.x, blockIdx.x + gridDim.x, ... and fetches
 // the next item's descriptor while it processes the current one.
 //
-// All per-call inputs are read from device memory (a header and the row
-// table), so the three launches can be captured once in a hipGraph and
-// replayed for any batch that fits the workspace. A row's summation order
+// All per-call inputs are read through fixed pointers (a header and the row
+// table in pinned host memory, read once by the planner), so the three
+// launches can be captured once in a hipGraph and replayed for any batch
+// that fits the workspace. A row's summation order
 // depends only on its length, its start alignment modulo 16 bytes, its
 // dtypes, the accumulation mode and the launch parameters: never on the
 // other rows or its position in the batch.
@@ -88,9 +89,12 @@ __device__ __forceinline__ int64_t long_tiles(int64_t n, int64_t short_max, int6
 __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   __shared__ int64_t scan_long[PLAN_THREADS];
   __shared__ int64_t scan_short[PLAN_THREADS];
-  const BatchHeader* h = a.hdr;
-  const int64_t nrows = h->nrows;
+  __shared__ BatchHeader hs;
   const int t = threadIdx.x;
+  if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
+  __syncthreads();
+  const BatchHeader* h = &hs;
+  const int64_t nrows = h->nrows;
   if (nrows < 0 || nrows > a.cap_rows) {
     if (t == 0) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);

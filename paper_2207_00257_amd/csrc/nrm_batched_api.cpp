@@ -1,6 +1,8 @@
 // C ABI of the ragged batched path (include/nrm.h): workspace and pinned
 // staging management, host validation, the launch sequence (planner, phase 1,
-// phase 2) and its optional capture in a hipGraph.
+// phase 2) and its optional capture in a hipGraph. The per-call header and
+// row table are written to pinned, coherent host memory that the planner
+// reads in place, so a captured graph replays new batches unchanged.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +22,10 @@ using nrm::hip_fail;
 namespace {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Staging layout: the header, then the row table from this offset.
+constexpr size_t kTableOffset = 256;
+static_assert(sizeof(BatchHeader) <= kTableOffset, "header must fit before the table");
 int64_t align_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 nrm_batch_params default_batch_params() {
@@ -79,8 +85,8 @@ Layout layout_for(int64_t cap_rows, int64_t cap_items) {
     off = (size_t)align_up((int64_t)(off + bytes), 256);
     return at;
   };
-  L.hdr = take(sizeof(BatchHeader));
-  L.table = take(sizeof(RowDesc) * cap_rows);
+  L.hdr = 0;
+  L.table = 0;
   L.rows = take(sizeof(RowDesc) * cap_rows);
   L.items = take(sizeof(nrm::Item) * cap_items);
   L.small = take(64);  // n_items (2 x 8 bytes) + error (4 bytes)
@@ -102,11 +108,21 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   void* dev = nullptr;
   e = hipMalloc(&dev, L.total);
   if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("batched workspace hipMalloc: ") + hipGetErrorString(e));
+  // Per-call header and row table: pinned, coherent host memory that the
+  // planner reads directly (no copy, no DMA latency per call).
   void* host = nullptr;
-  e = hipHostMalloc(&host, L.table + sizeof(RowDesc) * cap_rows, hipHostMallocDefault);
+  const size_t staging = kTableOffset + sizeof(RowDesc) * (size_t)cap_rows;
+  e = hipHostMalloc(&host, staging, hipHostMallocCoherent | hipHostMallocMapped);
   if (e != hipSuccess) {
     hipFree(dev);
     return fail(NRM_ENOMEM, std::string("pinned staging hipHostMalloc: ") + hipGetErrorString(e));
+  }
+  void* host_dev = nullptr;
+  e = hipHostGetDevicePointer(&host_dev, host, 0);
+  if (e != hipSuccess) {
+    hipFree(dev);
+    hipHostFree(host);
+    return hip_fail(e, "hipHostGetDevicePointer");
   }
   int err_word = 0;
   if (w.dev) {
@@ -117,8 +133,8 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   char* d = static_cast<char*>(dev);
   w.dev = dev;
   w.host = host;
-  w.hdr = reinterpret_cast<BatchHeader*>(d + L.hdr);
-  w.table = reinterpret_cast<RowDesc*>(d + L.table);
+  w.hdr = reinterpret_cast<BatchHeader*>(host_dev);
+  w.table = reinterpret_cast<RowDesc*>(static_cast<char*>(host_dev) + kTableOffset);
   w.rows = reinterpret_cast<RowDesc*>(d + L.rows);
   w.items = reinterpret_cast<nrm::Item*>(d + L.items);
   w.n_items = reinterpret_cast<int64_t*>(d + L.small);
@@ -169,13 +185,6 @@ BatchPlan plan_of(const nrm_ctx* c, int acc) {
   return p;
 }
 
-// Bytes of staging copied per call: the header, plus the table in table mode.
-// A captured graph always copies the header and a full-capacity table.
-size_t staged_bytes(const BatchWorkspace& w, int64_t table_rows) {
-  return (size_t)(reinterpret_cast<char*>(w.table) - reinterpret_cast<char*>(w.hdr)) +
-         sizeof(RowDesc) * (size_t)table_rows;
-}
-
 int capture_graph(nrm_ctx* c, int acc) {
   BatchWorkspace& w = c->batch;
   destroy_graph(w);
@@ -186,12 +195,9 @@ int capture_graph(nrm_ctx* c, int acc) {
   }
   e = hipStreamBeginCapture(w.capture_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t e1 = hipMemcpyAsync(w.hdr, w.host, staged_bytes(w, w.cap_rows), hipMemcpyHostToDevice,
-                                 w.capture_stream);
-  hipError_t e2 = e1 == hipSuccess ? nrm::launch_batch(plan_of(c, acc), args_of(c), w.capture_stream) : e1;
+  hipError_t e2 = nrm::launch_batch(plan_of(c, acc), args_of(c), w.capture_stream);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(w.capture_stream, &graph);
-  if (e1 != hipSuccess) return hip_fail(e1, "hipMemcpyAsync (capture)");
   if (e2 != hipSuccess) return hip_fail(e2, "batched launch (capture)");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&w.graph, graph, nullptr, nullptr, 0);
@@ -217,8 +223,7 @@ int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nr
   BatchHeader hd = h;
   hd.table = w.table;
   std::memcpy(w.host, &hd, sizeof(hd));
-  char* host_table = static_cast<char*>(w.host) + (reinterpret_cast<char*>(w.table) - reinterpret_cast<char*>(w.hdr));
-  if (table) std::memcpy(host_table, table, sizeof(RowDesc) * (size_t)nrows);
+  if (table) std::memcpy(static_cast<char*>(w.host) + kTableOffset, table, sizeof(RowDesc) * (size_t)nrows);
   hipEvent_t* ev = nullptr;
   if (c->timing) {
     ev = &w.events[2 * (w.timed_calls % nrm::kTimingRing)];
@@ -233,8 +238,6 @@ int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nr
     e = hipGraphLaunch(w.graph, s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   } else {
-    e = hipMemcpyAsync(w.hdr, w.host, staged_bytes(w, table ? nrows : 0), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     e = nrm::launch_batch(plan_of(c, acc), args_of(c), s);
     if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
   }

@@ -47,14 +47,14 @@ struct BatchWorkspace {
   int64_t cap_rows = 0;
   int64_t cap_items = 0;
   void* dev = nullptr;         // one allocation, carved into the pointers below
-  BatchHeader* hdr = nullptr;  // followed by the table copy target
-  RowDesc* table = nullptr;
+  BatchHeader* hdr = nullptr;  // device view of the pinned staging header
+  RowDesc* table = nullptr;    // device view of the pinned staging row table
   RowDesc* rows = nullptr;
   Item* items = nullptr;
   int64_t* n_items = nullptr;
   int* error = nullptr;
   void* partials = nullptr;
-  void* host = nullptr;        // pinned staging: header + table
+  void* host = nullptr;        // pinned staging (host view): header, then the table
   hipEvent_t staged = nullptr; // recorded once the staging buffer may be rewritten
   bool staged_pending = false;
   // captured launch sequence

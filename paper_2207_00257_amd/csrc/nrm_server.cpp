@@ -7,8 +7,9 @@
 //   2. admits waiting requests in arrival order while the HBM budget (input +
 //      output bytes of every admitted request) and a free slot allow;
 //   3. launches the admitted requests as one ragged batch (row-table form)
-//      on the free slot's stream, or, in per-request mode, one plain
-//      normalize call per request.
+//      on the free slot's stream (a group of one request may take the plain
+//      two-kernel path instead), or, in per-request mode, one plain normalize
+//      call per request.
 // Requests that arrive while batches are in flight join the next batch as
 // soon as a slot and memory free up; several slots run concurrently.
 // A replay thread can submit a whole trace at its scheduled arrival times
@@ -157,7 +158,7 @@ void nrm_server::launch(Slot& s, std::vector<Pending>& batch) {
     rows[i].out_dtype = p.req.out_dtype;
   }
   int st = NRM_OK;
-  if (cfg.batching) {
+  if (cfg.batching && !(cfg.single_plain && rows.size() == 1)) {
     st = nrm_normalize_rows(s.ctx, rows.data(), (int64_t)rows.size(), cfg.accum, s.stream);
     launches += 1;
   } else {
@@ -278,6 +279,7 @@ int nrm_server_default_config(nrm_server_config* cfg) {
   cfg->batching = 1;
   cfg->graph = 1;
   cfg->accum = NRM_ACC_F32;
+  cfg->single_plain = 1;
   return NRM_OK;
 }
 
@@ -293,6 +295,7 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
   if (cfg->accum != NRM_ACC_F32 && cfg->accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
   if (cfg->hold_outputs != 0 && cfg->hold_outputs != 1) return fail(NRM_EINVAL, "hold_outputs must be 0 or 1");
   if (cfg->use_batch_params != 0 && cfg->use_batch_params != 1) return fail(NRM_EINVAL, "use_batch_params must be 0 or 1");
+  if (cfg->single_plain != 0 && cfg->single_plain != 1) return fail(NRM_EINVAL, "single_plain must be 0 or 1");
   if (device < 0) {
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -23,7 +23,8 @@ ELEM_SIZE = {L.NRM_F32: 4, L.NRM_BF16: 2, L.NRM_F16: 2}
 class Server:
     def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, batching: bool = True, graph: bool = True,
                  hold_outputs: bool = False, max_batch_rows: int = 256, max_batch_elems: int = 1 << 27,
-                 accum: str = "f32", batch_params: Optional[dict] = None, arena_bytes: int = 0, device: int = -1):
+                 accum: str = "f32", batch_params: Optional[dict] = None, arena_bytes: int = 0, device: int = -1,
+                 single_plain: bool = True):
         lib = L.lib()
         cfg = L.NrmServerConfig()
         L.check(lib.nrm_server_default_config(ctypes.byref(cfg)), "nrm_server_default_config")
@@ -36,6 +37,7 @@ class Server:
         cfg.arena_bytes = arena_bytes
         cfg.max_batch_rows = max_batch_rows
         cfg.max_batch_elems = max_batch_elems
+        cfg.single_plain = int(single_plain)
         if batch_params:
             lib.nrm_default_batch_params(ctypes.byref(cfg.batch_params))
             for k, v in batch_params.items():

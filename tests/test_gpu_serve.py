@@ -62,7 +62,9 @@ def test_mix_matches_oracle_and_alone(batching):
     offs = pool.offsets(ns, 8)
     ptrs = pool.pointers(dts, offs)
     ids = np.arange(ns.size)
-    srv = serve.Server(slots=3, hold_outputs=True, batching=batching, max_batch_rows=32)
+    # groups of one run the batched kernels too, so that alone and in the mix
+    # the same kernel computes each request (bitwise comparison below)
+    srv = serve.Server(slots=3, hold_outputs=True, batching=batching, max_batch_rows=32, single_plain=False)
     srv.submit(ids, ptrs, ns, dts, dts)
     comps = srv.wait_all(ns.size)
     assert sorted(c[0] for c in comps) == list(ids)
@@ -76,7 +78,7 @@ def test_mix_matches_oracle_and_alone(batching):
     assert srv.stats()["budget_used"] == 0
     srv.close()
     # each request alone, on a fresh server with the same configuration
-    solo = serve.Server(slots=1, hold_outputs=True, batching=batching, max_batch_rows=32)
+    solo = serve.Server(slots=1, hold_outputs=True, batching=batching, max_batch_rows=32, single_plain=False)
     for i in range(0, ns.size, 7):
         solo.submit([i], [ptrs[i]], [ns[i]], [dts[i]], [dts[i]])
         (c,) = solo.wait_all(1)
@@ -128,4 +130,27 @@ def test_open_loop_replay_completes_and_measures_latency():
     assert stats["requests"] == k
     assert all(c[4] >= c[2] for c in comps)  # done after scheduled arrival
     assert stats["p50_ms"] > 0 and stats["p99_ms"] >= stats["p50_ms"]
+    srv.close()
+
+
+def test_single_request_plain_policy_matches_oracle():
+    """With single_plain (the default), a lone request takes the plain path and
+    a group the batched one: both within the error bound of the oracle."""
+    ns, dts = make_requests(40, 31)
+    pool = serve.InputPool(int(ns.max()), 32)
+    offs = pool.offsets(ns, 33)
+    ptrs = pool.pointers(dts, offs)
+    srv = serve.Server(slots=2, hold_outputs=True, max_batch_rows=8)
+    for i in range(0, 10):  # one at a time: groups of one
+        srv.submit([i], [ptrs[i]], [ns[i]], [dts[i]], [dts[i]])
+        (c,) = srv.wait_all(1)
+        check_against_oracle(pool, int(ns[i]), int(dts[i]), int(offs[i]), read_out(c[1], int(ns[i]), int(dts[i])),
+                             "alone %d" % i)
+        srv.release(i)
+    srv.submit(np.arange(10, 40), ptrs[10:], ns[10:], dts[10:], dts[10:])
+    for c in srv.wait_all(30):
+        i = c[0]
+        check_against_oracle(pool, int(ns[i]), int(dts[i]), int(offs[i]), read_out(c[1], int(ns[i]), int(dts[i])),
+                             "grouped %d" % i)
+        srv.release(i)
     srv.close()

@@ -28,12 +28,16 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 METRIC = "normalize effective HBM GB/s (% of peak); served req/s with p50/p99 latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_plain_2p28.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_00257_amd", "csrc", "nrm_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2207_00257_amd", "csrc", f) for f in ("nrm_kernels.hip", "nrm_device.h")]
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 over the plain path's kernel sources (first 16 hex digits)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(n_bytes_elem_in: int, n: int):
@@ -86,7 +90,7 @@ def main():
     ap.add_argument("--params", default=None,
                     help="JSON file of tuned launch parameters (default: the committed tuning cache "
                          "if it has an entry for this device and size, else the library defaults)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "ragged", "serve"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "ragged", "serve", "precision", "ladder"],
                     help="plain: n=2^log2n FP32 (the headline); ragged: 4096 rows, lengths log-uniform "
                          "in [32, 2^20], LogNormal(0,1) FP32, one graph-replayed batched call per step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -102,6 +106,10 @@ def main():
         return bench_ragged(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "precision":
+        return bench_precision(args)
+    if args.workload == "ladder":
+        return bench_ladder(args)
 
     import numpy as np
     import torch
@@ -374,6 +382,125 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
         "batched": batched, "per_request_launch": per_req, "budget_256MiB": stress, "rate_sweep": sweep,
         "sample_max_rel_err_f32": worst, "sample_max_err_bf16_ulps": worst_bf16,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_precision(args):
+    """Precision workload: n = 2^26 BF16 inputs, values bf16(exp(2 N(0,1)))
+    (seed 5), binary32 plain vs Kahan-compensated accumulation, BF16 and FP32
+    outputs. For each variant: time per call, effective GB/s (2 x 2 B read +
+    sizeof(out) written per element), the sum's error in binary32 ulps and
+    the outputs' errors against the FP64 oracle (which sees the quantised
+    BF16 inputs)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2207_00257_amd import api, synth
+
+    n = 1 << 26
+    bits = synth.lognormal_bf16(n, 5, 2.0)
+    ref, S_ref = oracle.normalize(bits, "bf16", return_sum=True)
+    ref_bf16 = oracle.round_bf16(ref)
+    dev = torch.device("cuda:0")
+    inp = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16)
+    stream = torch.cuda.current_stream(dev)
+    ulp_S = float(np.spacing(np.float32(S_ref)))
+    results = []
+    for accum in ("f32", "kahan"):
+        for odt in ("bf16", "f32"):
+            out = torch.empty(n, dtype=torch.bfloat16 if odt == "bf16" else torch.float32, device=dev)
+            ctx = api.Context()
+            for _ in range(args.warmup):
+                api.normalize(out, inp, accum=accum, ctx=ctx)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                api.normalize(out, inp, accum=accum, ctx=ctx)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            S = ctx.last_sum()
+            so = 2 if odt == "bf16" else 4
+            r = {"accum": accum, "out": odt, "ms": round(ms, 5),
+                 "GBps": round((4 + so) * n / (ms * 1e-3) / 1e9, 1),
+                 "sum_err_ulps": round(abs(S - S_ref) / ulp_S, 3),
+                 "sum_rel_err": abs(S - S_ref) / S_ref}
+            if odt == "f32":
+                got = out.cpu().numpy().astype(np.float64)
+                rel = np.abs(got - ref) / ref
+                r.update(max_rel_err=float(rel.max()), mean_rel_err=float(rel.mean()),
+                         max_err_f32_ulps=float(np.max(np.abs(got - ref) / np.spacing(ref.astype(np.float32)))))
+            else:
+                ob = out.view(torch.int16).cpu().numpy().view(np.uint16)
+                got = (ob.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+                ulp = np.exp2(np.floor(np.log2(ref)) - 7)
+                r.update(max_err_bf16_ulps=float(np.max(np.abs(got - ref) / ulp)),
+                         frac_correctly_rounded=float(np.mean(ob == ref_bf16)),
+                         max_rel_err=float(np.max(np.abs(got - ref) / ref)))
+            results.append(r)
+            ctx.close()
+    main_r = results[0]
+    line = {
+        "metric": METRIC, "value": main_r["GBps"], "unit": "GB/s",
+        "pct_of_peak": round(100.0 * main_r["GBps"] / PEAK_HBM_GBS, 2), "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_r["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 in, f32 accumulate", "data": "synthetic",
+        "config": {"workload": "precision: n=2^26 BF16 in, values bf16(exp(2 N(0,1))) seed 5; plain vs Kahan "
+                               "binary32 accumulation; BF16 and FP32 out; errors against the FP64 oracle",
+                   "n": n, "oracle_sum": S_ref},
+        "variants": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_ladder(args):
+    """The transformation ladder of Fig. 1 on the GPU: the naive form (every
+    thread sums the input, O(n^2)), the per-block form (one sum per block of
+    256 behind a barrier, O(n^2/256)) and the hoisted form (this library's
+    normalize, O(n)), timed at n = 2^10 .. 2^18 (FP32, U[0.5,1.5), seed 12)."""
+    import numpy as np
+    import torch
+
+    from paper_2207_00257_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for k in (10, 12, 14, 16, 18):
+        n = 1 << k
+        inp = torch.from_numpy(synth.uniform_f32(n, 12)).to(dev)
+        out = torch.empty_like(inp)
+        r = {"n": n}
+        for form in ("naive", "perblock", "hoisted"):
+            def call():
+                if form == "hoisted":
+                    api.normalize(out, inp)
+                else:
+                    api.normalize_form(out, inp, form, block=256)
+            call()
+            torch.cuda.synchronize()
+            reps = 3 if (form == "naive" and k >= 16) else 10
+            e0.record(stream)
+            for _ in range(reps):
+                call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            r[form + "_us"] = round(e0.elapsed_time(e1) / reps * 1e3, 2)
+        rows.append(r)
+    def slope(key):
+        xs = np.log2([r["n"] for r in rows[-3:]])
+        ys = np.log2([r[key] for r in rows[-3:]])
+        return round(float(np.polyfit(xs, ys, 1)[0]), 2)
+    line = {"metric": METRIC, "value": rows[-1]["naive_us"] / rows[-1]["hoisted_us"], "unit": "x (naive/hoisted at n=2^18)",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "transformation ladder: naive O(n^2), per-block O(n^2/256), hoisted O(n); "
+                                   "FP32 U[0.5,1.5) seed 12"},
+            "ladder": rows,
+            "log2_time_slope_last_three": {"naive": slope("naive_us"), "perblock": slope("perblock_us"),
+                                           "hoisted": slope("hoisted_us")}}
     print(json.dumps(line), flush=True)
 
 

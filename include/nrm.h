@@ -166,6 +166,17 @@ int nrm_get_params(const nrm_ctx* ctx, nrm_params* params);
 int nrm_normalize_ex(nrm_ctx* ctx, void* out, int out_dtype, const void* in, int in_dtype,
                      int64_t n, int accum, void* stream);
 
+/* ---- the un-hoisted forms, for measurement ------------------------------- */
+
+/* Fig. 1's two slower forms on the GPU: NRM_FORM_NAIVE, every thread sums the
+ * whole input itself (O(n^2) work); NRM_FORM_PERBLOCK, thread 0 of each block
+ * sums it into block-shared memory, a block barrier, then every thread
+ * divides (O(n^2 / block)). FP32, 1 <= n <= 2^20, block 64..1024 (multiple
+ * of 64). Each per-thread sum is a Kahan-compensated binary32 chain. They
+ * exist to measure what the hoisted form saves; they are not fast paths. */
+typedef enum { NRM_FORM_NAIVE = 1, NRM_FORM_PERBLOCK = 2 } nrm_form;
+int nrm_normalize_form(int form, float* out, const float* in, int64_t n, int block, void* stream);
+
 /* ---- extended batched forms ---------------------------------------------- */
 
 /* CSR form with dtypes, accumulation, context and stream. `capacity` is the
@@ -272,6 +283,11 @@ int nrm_server_stats(nrm_server* server, nrm_server_counters* counters);
 int nrm_server_destroy(nrm_server* server);
 
 /* ---- diagnostics and measurement ------------------------------------------ */
+
+/* The hoisted sum S of the last plain call on this context, as the kernels
+ * used it (binary32; compensated mode: hi + lo rounded once), read after
+ * synchronizing `stream`. ctx NULL: the default context. */
+int nrm_get_last_sum(nrm_ctx* ctx, void* stream, float* sum);
 
 /* Static text for a status code. */
 const char* nrm_status_string(int status);

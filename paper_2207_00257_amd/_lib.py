@@ -16,6 +16,7 @@ NRM_OK, NRM_EINVAL, NRM_EOVERLAP, NRM_ENOMEM, NRM_EHIP, NRM_EUNSUPPORTED, NRM_ED
 NRM_F32, NRM_BF16, NRM_F16 = 0, 1, 2
 NRM_ACC_F32, NRM_ACC_KAHAN = 0, 1
 NRM_LAYOUT_CHUNK, NRM_LAYOUT_STRIDE = 0, 1
+NRM_FORM_NAIVE, NRM_FORM_PERBLOCK = 1, 2
 
 
 class NrmParams(ctypes.Structure):
@@ -139,6 +140,8 @@ def _declare(lib):
         "nrm_set_batch_params": (i32, [p, ctypes.POINTER(NrmBatchParams)]),
         "nrm_get_batch_params": (i32, [p, ctypes.POINTER(NrmBatchParams)]),
         "nrm_get_device_error": (i32, [p, p]),
+        "nrm_get_last_sum": (i32, [p, p, ctypes.POINTER(ctypes.c_float)]),
+        "nrm_normalize_form": (i32, [i32, p, p, i64, i32, p]),
         "nrm_server_default_config": (i32, [ctypes.POINTER(NrmServerConfig)]),
         "nrm_server_create": (i32, [ctypes.POINTER(p), i32, ctypes.POINTER(NrmServerConfig)]),
         "nrm_server_submit": (i32, [p, ctypes.POINTER(NrmRequest), i64]),

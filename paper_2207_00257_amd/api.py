@@ -115,6 +115,15 @@ class Context:
         L.check(L.lib().nrm_batch_times(self.handle, ctypes.byref(t), ctypes.byref(c)), "nrm_batch_times")
         return t.value, c.value
 
+    def last_sum(self, stream: Optional[int] = None) -> float:
+        """The hoisted sum of the last plain call (synchronizes the stream)."""
+        import torch
+
+        v = ctypes.c_float()
+        s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+        L.check(L.lib().nrm_get_last_sum(self.handle, s, ctypes.byref(v)), "nrm_get_last_sum")
+        return v.value
+
     def set_timing(self, enable: bool) -> None:
         L.check(L.lib().nrm_set_timing(self.handle, int(bool(enable))), "nrm_set_timing")
 
@@ -198,3 +207,17 @@ def device_error(ctx: Optional[Context] = None, stream: Optional[int] = None) ->
 
     s = torch.cuda.current_stream().cuda_stream if stream is None else stream
     return L.lib().nrm_get_device_error(ctx.handle if ctx else None, s)
+
+
+def normalize_form(out, inp, form: str, block: int = 256, stream: Optional[int] = None):
+    """One of Fig. 1's un-hoisted forms on the device, for measurement:
+    form "naive" (every thread sums the input) or "perblock" (one sum per
+    block behind a block barrier). FP32 tensors, n <= 2^20, out != inp."""
+    _check_tensors(out, inp)
+    codes = {"naive": L.NRM_FORM_NAIVE, "perblock": L.NRM_FORM_PERBLOCK}
+    if form not in codes:
+        raise ValueError("form must be 'naive' or 'perblock'")
+    s = _stream_of(inp) if stream is None else stream
+    st = L.lib().nrm_normalize_form(codes[form], out.data_ptr(), inp.data_ptr(), inp.numel(), int(block), s)
+    L.check(st, "nrm_normalize_form")
+    return out

@@ -36,17 +36,18 @@ nrm_params default_params() {
   nrm_params p;
   std::memset(&p, 0, sizeof(p));
   p.block = 1024;
-  p.unroll = 2;
+  p.unroll = 4;
   p.grid = 256;
   p.layout = NRM_LAYOUT_STRIDE;
   p.reduce_nt = 1;
   p.max_height = 36;
-  p.map_block = 512;
+  p.map_block = 256;
   p.map_unroll = 4;
   p.map_grid = 8192;
   p.map_layout = NRM_LAYOUT_STRIDE;
   p.map_nt = 1;
-  p.reverse_map = 1;
+  p.reverse_map = 0;
+  p.reduce_keep_mib = 0;
   return p;
 }
 
@@ -173,7 +174,8 @@ int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_d
     while (nrm::thread_tree_height(in_dt, acc, q.unroll, max_iters + 1) <= q.max_height) ++max_iters;
   }
   split(p->nvec, (int64_t)q.block * q.unroll, q.grid, max_iters, &p->grid, &p->chunk);
-  split(p->nvec, (int64_t)q.map_block * q.map_unroll, q.map_grid, 0, &p->map_grid, &p->map_chunk);
+  p->map_units = (si == 2 && so == 4) ? 2 * p->nvec : p->nvec;
+  split(p->map_units, (int64_t)q.map_block * q.map_unroll, q.map_grid, 0, &p->map_grid, &p->map_chunk);
   if (p->grid > 65536) return fail(NRM_EINVAL, "n too large for these launch parameters (over 65536 reduce blocks)");
   if (p->map_grid > INT32_MAX) return fail(NRM_EINVAL, "n too large for one launch");
   return NRM_OK;
@@ -366,6 +368,33 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
   e = nrm::launch_map(plan, ws, s);
   if (e != hipSuccess) return hip_fail(e, "map kernel launch");
   if (ev) hipEventRecord(ev[2], s);
+  return NRM_OK;
+}
+
+int nrm_get_last_sum(nrm_ctx* c, void* stream, float* sum) {
+  if (!sum) return fail(NRM_EINVAL, "sum is NULL");
+  if (!c) {
+    int st = nrm::default_ctx(&c);
+    if (st != NRM_OK) return st;
+  }
+  DeviceGuard g(c->device);
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = hipMemcpy(sum, c->sum, sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading the last sum");
+  return NRM_OK;
+}
+
+int nrm_normalize_form(int form, float* out, const float* in, int64_t n, int block, void* stream) {
+  if (form != NRM_FORM_NAIVE && form != NRM_FORM_PERBLOCK) return fail(NRM_EINVAL, "unknown form");
+  if (n < 1 || n > (int64_t(1) << 20)) return fail(NRM_EINVAL, "n must be 1..2^20");
+  if (block < 64 || block > 1024 || block % 64) return fail(NRM_EINVAL, "block must be 64..1024, a multiple of 64");
+  if (!in || !out) return fail(NRM_EINVAL, "NULL data pointer");
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % 4)
+    return fail(NRM_EINVAL, "pointers must be 4-byte aligned");
+  if (ranges_partially_overlap(in, n * 4, out, n * 4) || in == out)
+    return fail(NRM_EOVERLAP, "the un-hoisted forms read the input while others write: in and out must not overlap");
+  hipError_t e = nrm::launch_form(form, out, in, n, block, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "form kernel launch");
   return NRM_OK;
 }
 

@@ -119,6 +119,27 @@ __device__ __forceinline__ u4 load_vec(const u4* p) {
   else return *p;
 }
 
+template <bool NT>
+__device__ __forceinline__ u2 load_vec(const u2* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+// Widen 8 bytes of a 2-byte type (4 elements) to binary32.
+template <int DT>
+__device__ __forceinline__ void widen_half(u2 r, float (&x)[4]) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if constexpr (DT == NRM_BF16) {
+      x[2 * k] = f32_bits(r[k] << 16);
+      x[2 * k + 1] = f32_bits(r[k] & 0xFFFF0000u);
+    } else {
+      x[2 * k] = f32_of_f16_bits((unsigned short)(r[k] & 0xFFFFu));
+      x[2 * k + 1] = f32_of_f16_bits((unsigned short)(r[k] >> 16));
+    }
+  }
+}
+
 // ---- accumulators ------------------------------------------------------------
 
 template <int ACC>
@@ -271,14 +292,37 @@ __device__ __forceinline__ void merge_chains(Acc<ACC> (&acc)[NA]) {
 }
 
 // Merge `count` partials (published with `publish`) into one value in a
-// fixed order: tiles of COMBINE_TILE partials are merged by a halving tree in
-// LDS (each level adds slot i + s into slot i, then a barrier: the shared-
-// memory reduction pattern of Fig. 7), and thread 0 merges the tile results
-// pairwise. Every thread of the block must call it; the result is valid in
-// thread 0. count <= COMBINE_TILE * MAX_COMBINE_TILES.
+// fixed order that depends only on count: up to 1024 partials in wavefront 0
+// (registers and DPP); more in tiles of COMBINE_TILE partials merged by a
+// halving tree in LDS (each level adds slot i + s into slot i, then a
+// barrier: the shared-memory reduction pattern of Fig. 7), after which thread
+// 0 merges the tile results pairwise. Every thread of the block must call it;
+// the result is valid in thread 0. count <= COMBINE_TILE * MAX_COMBINE_TILES.
 template <int ACC>
 __device__ __forceinline__ Acc<ACC> combine_partials(const Acc<ACC>* part, int64_t count,
                                                      Acc<ACC>* tree, Acc<ACC>* tiles) {
+  if (count <= 64 * 16) {
+    // Wavefront 0 alone, no barrier: lane l holds partials l, l + 64, ...
+    // (up to 16), merges them pairwise, then the DPP wavefront tree; the same
+    // height (4 + 6) as the LDS tree below.
+    Acc<ACC> total;
+    total.zero();
+    if (threadIdx.x < 64) {
+      Acc<ACC> v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        v[k].zero();
+        const int64_t i = threadIdx.x + 64 * k;
+        if (i < count) fetch(part, i, v[k]);
+      }
+#pragma unroll
+      for (int s = 1; s < 16; s <<= 1)
+#pragma unroll
+        for (int k = 0; k + s < 16; k += 2 * s) v[k].merge(v[k + s]);
+      total = wave_reduce<ACC>(v[0]);
+    }
+    return total;
+  }
   const int ntiles = (int)((count + COMBINE_TILE - 1) / COMBINE_TILE);
   for (int t = 0; t < ntiles; ++t) {
     const int64_t t0 = (int64_t)t * COMBINE_TILE;

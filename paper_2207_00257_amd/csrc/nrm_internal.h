@@ -63,7 +63,9 @@ struct PlainPlan {
   int map_block;
   int map_unroll;
   int64_t map_grid;
-  int64_t map_chunk;
+  int64_t map_chunk;  // map units per block (layout CHUNK)
+  int64_t map_units;  // map units in the body: 16-byte vectors, or 8-byte halves
+                      // for a 2-byte input with binary32 output
   int map_layout;
   int map_nt;
   int reverse_map;
@@ -78,6 +80,7 @@ struct PlainWorkspace {
 };
 
 hipError_t launch_reduce(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t s);
+hipError_t launch_form(int form, float* out, const float* in, int64_t n, int block, hipStream_t s);
 hipError_t launch_map(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t s);
 
 }  // namespace nrm

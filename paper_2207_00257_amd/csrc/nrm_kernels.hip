@@ -23,6 +23,8 @@
 // The kernel boundary between the two is the grid-wide barrier. No float
 // atomics are used: for given sizes, alignment and launch parameters every
 // addition happens in the same order on every run.
+#include <type_traits>
+
 #include "nrm_device.h"
 
 namespace nrm {
@@ -79,33 +81,18 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
     stride = (int64_t)gridDim.x * step;
   }
   const u4* p = a.body + threadIdx.x;
-  for (int64_t base = begin; base < end; base += stride) {
+  // Full iterations only in the steady-state loops (non-temporal loads, then
+  // temporal ones from keep_from on); at most one partial iteration remains.
+  auto full = [&](int64_t base, auto nt) {
     u4 r[U];
-    if (base + step <= end) {
-      if (NT && base < a.keep_from) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = load_vec<true>(p + base + u * B);
-      } else {
+    for (int u = 0; u < U; ++u) r[u] = load_vec<decltype(nt)::value>(p + base + u * B);
 #pragma unroll
-        for (int u = 0; u < U; ++u) r[u] = load_vec<false>(p + base + u * B);
-      }
+    for (int u = 0; u < U; ++u) {
+      float x[VEC];
+      widen<DT>(r[u], x);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        float x[VEC];
-        widen<DT>(r[u], x);
-#pragma unroll
-        for (int k = 0; k < VEC; ++k) acc[(u * VEC + k) % NA].add(x[k]);
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (base + u * B + (int64_t)threadIdx.x < end) {
-          float x[VEC];
-          widen<DT>(load_vec<NT>(p + base + u * B), x);
-#pragma unroll
-          for (int k = 0; k < VEC; ++k) acc[(u * VEC + k) % NA].add(x[k]);
-        }
-      }
+      for (int k = 0; k < VEC; ++k) acc[(u * VEC + k) % NA].add(x[k]);
     }
     if constexpr (ACC == NRM_ACC_F32) {
       if (++since_flush == FLUSH) {
@@ -114,6 +101,24 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
         run.merge(acc[0]);
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[k].zero();
+      }
+    }
+  };
+  const int64_t last_full = end - step;  // a base <= last_full starts a full iteration
+  int64_t base = begin;
+  if (NT) {
+    const int64_t nt_end = a.keep_from < last_full + 1 ? a.keep_from : last_full + 1;
+    for (; base < nt_end; base += stride) full(base, std::integral_constant<bool, true>());
+  }
+  for (; base <= last_full; base += stride) full(base, std::integral_constant<bool, false>());
+  if (base < end) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (base + u * B + (int64_t)threadIdx.x < end) {
+        float x[VEC];
+        widen<DT>(load_vec<NT>(p + base + u * B), x);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) acc[(u * VEC + k) % NA].add(x[k]);
       }
     }
   }
@@ -163,9 +168,22 @@ struct MapArgs {
   const float* sum;
 };
 
+// Units of the map: a 16-byte input vector, or, for a 2-byte input with
+// binary32 output, 8 bytes (4 elements), so that every lane stores exactly
+// one 16-byte output vector and each store instruction is fully coalesced.
+template <int DTI, int DTO>
+struct MapUnit {
+  static constexpr bool HALF = Elem<DTI>::SIZE == 2 && DTO == NRM_F32;
+  static constexpr int ELEMS = HALF ? 4 : Elem<DTI>::VEC;
+  using T = typename std::conditional<HALF, u2, u4>::type;
+};
+
 template <int DTI, int DTO, int U, bool NT>
 __global__ void __launch_bounds__(1024) map_kernel(MapArgs a) {
-  constexpr int VEC = Elem<DTI>::VEC;
+  using MU = MapUnit<DTI, DTO>;
+  using T = typename MU::T;
+  constexpr int VEC = MU::ELEMS;
+  const T* body = reinterpret_cast<const T*>(a.body);
   const float S = a.sum[0];
   const int64_t B = blockDim.x;
   const int64_t step = B * U;
@@ -179,18 +197,22 @@ __global__ void __launch_bounds__(1024) map_kernel(MapArgs a) {
     end = a.nvec;
     stride = (int64_t)gridDim.x * step;
   }
+  auto widen_unit = [](T r, float (&x)[VEC]) {
+    if constexpr (MU::HALF) widen_half<DTI>(r, x);
+    else widen<DTI>(r, x);
+  };
   const int64_t iters = end > begin ? (end - begin + stride - 1) / stride : 0;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t base = begin + (a.reverse ? iters - 1 - it : it) * stride;
     const int64_t v0 = base + threadIdx.x;
     if (base + step <= end) {
-      u4 r[U];
+      T r[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = load_vec<NT>(a.body + v0 + u * B);
+      for (int u = 0; u < U; ++u) r[u] = load_vec<NT>(body + v0 + u * B);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         float x[VEC], q[VEC];
-        widen<DTI>(r[u], x);
+        widen_unit(r[u], x);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) q[k] = x[k] / S;
         store_vec<DTO, VEC>(a.out_body, v0 + u * B, q);
@@ -200,7 +222,7 @@ __global__ void __launch_bounds__(1024) map_kernel(MapArgs a) {
       for (int u = 0; u < U; ++u) {
         if (v0 + u * B < end) {
           float x[VEC], q[VEC];
-          widen<DTI>(load_vec<NT>(a.body + v0 + u * B), x);
+          widen_unit(load_vec<NT>(body + v0 + u * B), x);
 #pragma unroll
           for (int k = 0; k < VEC; ++k) q[k] = x[k] / S;
           store_vec<DTO, VEC>(a.out_body, v0 + u * B, q);
@@ -319,7 +341,7 @@ hipError_t launch_map(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t 
   a.body = reinterpret_cast<const u4*>(a.in + p.head * dtype_size(p.in_dt));
   a.out_body = a.out + p.head * dtype_size(p.out_dt);
   a.head = p.head;
-  a.nvec = p.nvec;
+  a.nvec = p.map_units;
   a.tail_begin = p.tail_begin;
   a.n = p.n;
   a.chunk = p.map_chunk;

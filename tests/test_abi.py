@@ -120,3 +120,14 @@ def test_server_config_validation_before_any_hip_call(lib):
     assert lib.nrm_server_create(None, 0, ctypes.byref(cfg)) == L.NRM_EINVAL
     assert lib.nrm_server_submit(None, None, 0) == L.NRM_EINVAL
     assert lib.nrm_server_destroy(None) == L.NRM_OK
+
+
+def test_forms_validation_before_any_hip_call(lib):
+    f = lib.nrm_normalize_form
+    assert f(0, 4096, 8192, 10, 256, None) == L.NRM_EINVAL          # unknown form
+    assert f(1, 4096, 8192, 0, 256, None) == L.NRM_EINVAL           # n < 1
+    assert f(1, 4096, 8192, (1 << 20) + 1, 256, None) == L.NRM_EINVAL
+    assert f(2, 4096, 8192, 10, 100, None) == L.NRM_EINVAL          # block not a multiple of 64
+    assert f(2, None, 8192, 10, 256, None) == L.NRM_EINVAL
+    assert f(1, 4098, 8192, 10, 256, None) == L.NRM_EINVAL          # misaligned
+    assert f(1, 4096, 4096, 10, 256, None) == L.NRM_EOVERLAP        # in place is not allowed here

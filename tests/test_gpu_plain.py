@@ -279,3 +279,37 @@ def test_too_many_blocks_is_rejected():
     ctx.close()
     del x, out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+def test_sum_error_bound(accum):
+    """The hoisted sum itself: plain binary32 within the tree-height bound
+    gamma_62 * S (non-negative inputs), compensated within a few ulps."""
+    bits = synth.lognormal_bf16(1 << 24, 44, 2.0)
+    _, S_ref = oracle.normalize(bits, "bf16", return_sum=True)
+    inp = gpu(bits.view(np.int16)).view(torch.bfloat16)
+    out = torch.empty(inp.numel(), device=DEV)
+    ctx = api.Context()
+    api.normalize(out, inp, accum=accum, ctx=ctx)
+    S = ctx.last_sum()
+    ulp = float(np.spacing(np.float32(S_ref)))
+    if accum == "kahan":
+        assert abs(S - S_ref) <= 2 * ulp, (S, S_ref)
+    else:
+        u = 2.0 ** -24
+        assert abs(S - S_ref) <= 62 * u / (1 - 62 * u) * S_ref + ulp, (S, S_ref)
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", ["naive", "perblock"])
+@pytest.mark.parametrize("n", [1, 33, 1000, 1024, 4097, 65536])
+def test_unhoisted_forms_match_oracle(form, n):
+    """Fig. 1's naive and per-block forms on the GPU agree with the oracle's
+    naive and per-block forms (and so with the hoisted result)."""
+    x = synth.uniform_f32(n, 60 + n % 89)
+    inp = gpu(x)
+    out = torch.empty_like(inp)
+    api.normalize_form(out, inp, form, block=256 if n > 64 else 64)
+    torch.cuda.synchronize()
+    ref = oracle.normalize_naive(x) if form == "naive" else oracle.normalize_perblock(x, 256)
+    assert_f32_close(out.cpu().numpy(), ref, what="%s n=%d" % (form, n))

@@ -108,13 +108,15 @@ typedef struct {
   int32_t block;       /* threads per block: 64..1024, multiple of 64 */
   int32_t unroll;      /* tile sums: 16-byte vectors per thread per iteration: 1, 2, 4, 8 */
   int32_t map_unroll;  /* tile divides: 16-byte vectors per thread per iteration: 1, 2, 4, 8 */
-  int32_t grid;        /* persistent blocks of both phases */
+  int32_t grid;        /* persistent blocks of the planner-fed phase 1 (sums, single-pass rows) */
   int32_t tile_log2;   /* a long row is cut into tiles of 2^tile_log2 elements: 10..22 */
   int32_t short_regs;  /* 16-byte vectors per thread held in registers by a single-pass row:
                           1, 2, 4 or 8; rows with n <= block * short_regs * 4 take one pass
                           (one read, one write) */
   int32_t graph;       /* 1: capture the launch sequence once in a hipGraph and replay it */
-  int32_t reserved[5];
+  int32_t map_block;   /* threads per block of the divide phase: 64..1024, multiple of 64 */
+  int32_t map_grid;    /* persistent blocks of the divide phase */
+  int32_t reserved[3];
 } nrm_batch_params;
 
 /* One row of a batch given as a table: `in` and `out` are device arrays of

@@ -47,7 +47,9 @@ class NrmBatchParams(ctypes.Structure):
         ("tile_log2", ctypes.c_int32),
         ("short_regs", ctypes.c_int32),
         ("graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("map_block", ctypes.c_int32),
+        ("map_grid", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

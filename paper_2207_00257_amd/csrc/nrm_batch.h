@@ -51,18 +51,36 @@ struct Item {
   int32_t tile;
 };
 
+// Counters the planner leaves for the later kernels (device memory).
+enum {
+  CNT_ITEMS = 0,       // all work items of phase 1
+  CNT_LONG_ITEMS = 1,  // the leading items that are tiles of long rows
+  CNT_LONG_ROWS = 2,   // long rows
+  CNT_LONG_ELEMS = 3,  // elements in long rows: the length of phase 2's range
+  CNT_CHUNK = 4,       // elements per phase-2 chunk
+  CNT_CHUNKS = 5,      // phase-2 chunks
+  CNT_COUNT = 6,
+};
+
 // Kernel arguments: workspace pointers, fixed for a context's workspace.
 struct BatchArgs {
   const BatchHeader* hdr;
   RowDesc* rows;         // resolved rows [cap_rows]
   Item* items;           // [cap_items]: the long rows' tiles first, then the short rows
-  int64_t* n_items;      // [2]: all items, items that are tiles of long rows
+  int64_t* lrow_first;   // [cap_rows]: first item (and partial) of each long row, in row order
+  RowDesc* lrows;        // [cap_rows]: the long rows' descriptors, in row order
+  int64_t* lstart;       // [cap_rows]: each long row's first position in the long rows' concatenation
+  float* lsum;           // [cap_rows]: each long row's sum (written between the phases)
+  int32_t* chunk_lrow;   // [cap_chunks]: the long row in which each phase-2 chunk starts
+  int64_t* cnt;          // [CNT_COUNT]
   int* error;            // [1]
   void* partials;        // [cap_items] x 8 bytes
   int64_t cap_rows;
   int64_t cap_items;
+  int64_t cap_chunks;
   int64_t tile;          // elements per tile of a long row
   int64_t short_max;     // rows with n <= short_max take one pass
+  int64_t map_grid;      // phase 2 blocks: the chunks are sized to a multiple of it
 };
 
 struct BatchPlan {
@@ -71,7 +89,9 @@ struct BatchPlan {
   int unroll;       // tile reduce: vectors per thread per iteration
   int map_unroll;   // tile map
   int short_regs;   // vectors per thread held for a single-pass row
-  int64_t grid;     // persistent blocks
+  int64_t grid;     // persistent blocks of phase 1 and of the row sums
+  int map_block;    // phase 2
+  int64_t map_grid;
 };
 
 hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s);

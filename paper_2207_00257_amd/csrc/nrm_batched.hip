@@ -5,26 +5,30 @@
 //
 //   batch_plan_kernel    one block: resolves the row table (from CSR offsets
 //                        or a descriptor table), validates it, classifies
-//                        rows, and writes the work-item table by exclusive
-//                        scans: first the tiles of every long row
-//                        (ceil(n / tile) each, consecutive per row), then one
-//                        item per short row (n <= short_max).
+//                        rows, and by exclusive scans writes the work-item
+//                        table (first the tiles of every long row,
+//                        ceil(n / tile) each and consecutive per row, then
+//                        one item per short row, n <= short_max), the long
+//                        rows' descriptors and starts, and phase 2's chunk
+//                        table.
 //   batch_phase1_kernel  persistent blocks walk the items. A single-pass item
 //                        keeps its row in registers: one read, block sum,
 //                        divide, one write. A tile item writes its partial.
-//   batch_phase2_kernel  persistent blocks walk the tile items: each merges
-//                        its row's partials in a fixed order (the kernel
-//                        boundary is the barrier that makes them visible;
-//                        every tile of a row computes the same sum) and
-//                        divides its tile by it.
-// Each block walks items blockIdx.x, blockIdx.x + gridDim.x, ... and fetches
-// the next item's descriptor while it processes the current one.
+//   batch_rowsum_kernel  one block per long row merges the row's tile
+//                        partials in a fixed order into the row's sum (the
+//                        kernel boundary is the barrier that makes the
+//                        partials visible).
+//   batch_phase2_kernel  persistent blocks divide equal chunks of the long
+//                        rows' concatenation by their rows' sums, so every
+//                        block moves the same number of elements.
+// Both persistent phases walk their work blockIdx.x, blockIdx.x + gridDim.x,
+// ... and fetch the next unit's descriptor while the current one streams.
 //
 // All per-call inputs are read through fixed pointers (a header and the row
-// table in pinned host memory, read once by the planner), so the three
+// table in pinned host memory, read once by the planner), so the four
 // launches can be captured once in a hipGraph and replayed for any batch
 // that fits the workspace. A row's summation order
-// depends only on its length, its start alignment modulo 16 bytes, its
+// depends only on its length, its start alignment modulo 128 bytes, its
 // dtypes, the accumulation mode and the launch parameters: never on the
 // other rows or its position in the batch.
 #include "nrm_batch.h"
@@ -37,9 +41,18 @@ using namespace dev;
 
 // ---- geometry of one contiguous segment --------------------------------------
 
+// A segment's vector body starts on a 128-byte boundary (one cache line), so
+// every wavefront's 1 KiB access covers whole lines: a body that is only
+// 16-byte aligned straddles a line at each end of every access, and with
+// non-temporal stores those partial lines cost about a tenth of the map's
+// bandwidth. The head before the boundary (at most 31 binary32 or 63 2-byte
+// elements, fewer than the 64 threads of the smallest block) and the tail
+// after the last whole vector are handled one element per thread.
+constexpr int BODY_ALIGN = 128;
+
 struct Geom {
-  int64_t head;        // elements before the first 16-byte aligned vector
-  int64_t nvec;        // whole 16-byte vectors after the head
+  int64_t head;        // elements before the body's 128-byte boundary
+  int64_t nvec;        // whole 16-byte vectors in the body
   int64_t tail_begin;  // first element after the vectors
 };
 
@@ -47,8 +60,8 @@ template <int DT>
 __device__ __forceinline__ Geom geometry(const char* p, int64_t n) {
   constexpr int SI = Elem<DT>::SIZE, VEC = Elem<DT>::VEC;
   Geom g;
-  const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(p) & 15);
-  g.head = mis ? (16 - mis) / SI : 0;
+  const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(p) & (BODY_ALIGN - 1));
+  g.head = mis ? (BODY_ALIGN - mis) / SI : 0;
   if (g.head > n) g.head = n;
   g.nvec = (n - g.head) / VEC;
   g.tail_begin = g.head + g.nvec * VEC;
@@ -86,10 +99,112 @@ __device__ __forceinline__ int64_t long_tiles(int64_t n, int64_t short_max, int6
   return n <= short_max ? 0 : (n + tile - 1) / tile;
 }
 
+// Resolve and validate row r; returns it with n = 0 if invalid.
+__device__ __forceinline__ RowDesc resolve_row(const BatchHeader* h, int64_t r, int& err) {
+  RowDesc d;
+  if (h->mode == BATCH_CSR) {
+    const int64_t b = h->offsets[r], e = h->offsets[r + 1];
+    const int si = h->csr_in_dt == NRM_F32 ? 4 : 2, so = h->csr_out_dt == NRM_F32 ? 4 : 2;
+    d.in = h->csr_in + b * si;
+    d.out = h->csr_out + b * so;
+    d.n = e - b;
+    d.in_dt = h->csr_in_dt;
+    d.out_dt = h->csr_out_dt;
+    if (b < 0 || e < b || e > h->capacity) {
+      err |= NRM_DEVERR_OFFSETS;
+      d.n = 0;
+    }
+  } else {
+    d = h->table[r];
+    if (d.n < 0 || !valid_dt(d.in_dt) || !valid_dt(d.out_dt) || (d.n > 0 && (!d.in || !d.out))) {
+      err |= NRM_DEVERR_ROW;
+      d.n = 0;
+    }
+  }
+  return d;
+}
+
+// Per-row counters of the planner: tile items, single-pass item, long row,
+// elements of a long row.
+constexpr int NCNT = 4;
+constexpr int PLAN_WAVES = PLAN_THREADS / 64;
+
+// Inclusive block-wide scan of the NCNT counters: a shuffle scan inside each
+// wavefront, the wavefront totals scanned by wavefront 0, two barriers.
+__device__ __forceinline__ void scan_counts(int64_t (&v)[NCNT], int64_t (*sc)[PLAN_WAVES]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      int64_t w = __shfl_up(v[k], off, 64);
+      if (lane >= off) v[k] += w;
+    }
+  }
+  if (lane == 63)
+    for (int k = 0; k < NCNT; ++k) sc[k][wave] = v[k];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < NCNT; ++k) {
+      int64_t x = lane < PLAN_WAVES ? sc[k][lane] : 0;
+#pragma unroll
+      for (int off = 1; off < PLAN_WAVES; off <<= 1) {
+        int64_t w = __shfl_up(x, off, 64);
+        if (lane >= off) x += w;
+      }
+      if (lane < PLAN_WAVES) sc[k][lane] = x;  // inclusive totals of waves 0..lane
+    }
+  }
+  __syncthreads();
+  if (wave > 0)
+    for (int k = 0; k < NCNT; ++k) v[k] += sc[k][wave - 1];
+}
+
+__device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int64_t tile, int64_t (&v)[NCNT]) {
+  v[0] = long_tiles(n, short_max, tile);
+  v[1] = (n > 0 && n <= short_max) ? 1 : 0;
+  v[2] = v[0] > 0 ? 1 : 0;
+  v[3] = v[0] > 0 ? n : 0;
+}
+
+// The last j in [0, PLAN_THREADS) with ex[j] <= x, for a non-decreasing ex
+// with ex[0] = 0 <= x: the thread whose range [ex[j], ex[j] + count) holds x.
+template <typename T>
+__device__ __forceinline__ int last_le(const T* ex, int64_t x) {
+  int lo = 0;
+#pragma unroll
+  for (int step = PLAN_THREADS / 2; step > 0; step >>= 1)
+    if ((int64_t)ex[lo + step] <= x) lo += step;
+  return lo;
+}
+
+// Rows are taken PLAN_THREADS at a time, row q * PLAN_THREADS + t in thread t
+// (coalesced reads of the offsets or of the table).
+//
+// Pass 1 resolves and validates every row and counts, by a block scan per
+// round, its tile items, single-pass item, long-row slot and long-row
+// elements. The first PLAN_ROUNDS rounds keep their scans in registers; later
+// rounds are scanned again in pass 2.
+//
+// Pass 2 writes, per round: each short row's item and each long row's first
+// item, descriptor and start in the long rows' concatenation (one thread per
+// row); then, cooperatively, the round's tile items and the chunk table, each
+// entry finding its row by a binary search over the round's scan in LDS.
+//
+// Phase 2 covers the concatenation of the long rows in equal chunks, about
+// G * m of them for G phase-2 blocks (m chunks per block, each at most about
+// one tile, a multiple of 64 elements), so that every block moves the same
+// number of elements however the row lengths fall.
+constexpr int PLAN_ROUNDS = 4;
+
 __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
-  __shared__ int64_t scan_long[PLAN_THREADS];
-  __shared__ int64_t scan_short[PLAN_THREADS];
+  __shared__ int64_t sc[NCNT][PLAN_WAVES];
   __shared__ BatchHeader hs;
+  __shared__ int64_t ks[PLAN_ROUNDS + 1][NCNT];  // totals before each kept round
+  __shared__ int32_t ex_tile[PLAN_THREADS];      // in-round exclusive scans
+  __shared__ int32_t ex_lrow[PLAN_THREADS];
+  __shared__ int64_t ex_elem[PLAN_THREADS];
   const int t = threadIdx.x;
   if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
   __syncthreads();
@@ -98,78 +213,139 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   if (nrows < 0 || nrows > a.cap_rows) {
     if (t == 0) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
-      a.n_items[0] = 0;
-      a.n_items[1] = 0;
+      for (int k = 0; k < CNT_COUNT; ++k) a.cnt[k] = 0;
     }
     return;
   }
-  const int64_t per = (nrows + PLAN_THREADS - 1) / PLAN_THREADS;
-  const int64_t r0 = t * per < nrows ? t * per : nrows;
-  const int64_t r1 = r0 + per < nrows ? r0 + per : nrows;
+  const int64_t rounds = (nrows + PLAN_THREADS - 1) / PLAN_THREADS;
   int err = 0;
-  int64_t nl = 0, ns = 0;
-  for (int64_t r = r0; r < r1; ++r) {
-    RowDesc d;
-    if (h->mode == BATCH_CSR) {
-      const int64_t b = h->offsets[r], e = h->offsets[r + 1];
-      const int si = h->csr_in_dt == NRM_F32 ? 4 : 2, so = h->csr_out_dt == NRM_F32 ? 4 : 2;
-      d.in = h->csr_in + b * si;
-      d.out = h->csr_out + b * so;
-      d.n = e - b;
-      d.in_dt = h->csr_in_dt;
-      d.out_dt = h->csr_out_dt;
-      if (b < 0 || e < b || e > h->capacity) {
-        err |= NRM_DEVERR_OFFSETS;
-        d.n = 0;
-      }
-    } else {
-      d = h->table[r];
-      if (d.n < 0 || !valid_dt(d.in_dt) || !valid_dt(d.out_dt) || (d.n > 0 && (!d.in || !d.out))) {
-        err |= NRM_DEVERR_ROW;
-        d.n = 0;
-      }
-    }
+  // resolve row q * PLAN_THREADS + t, store it, return its length (0 if
+  // invalid or past the end)
+  auto resolve = [&](int64_t q) -> int64_t {
+    const int64_t r = q * PLAN_THREADS + t;
+    if (r >= nrows) return 0;
+    RowDesc d = resolve_row(h, r, err);
     if (long_tiles(d.n, a.short_max, a.tile) > MAX_ROW_TILES) {
       err |= NRM_DEVERR_ROW;
       d.n = 0;
     }
     a.rows[r] = d;
-    nl += long_tiles(d.n, a.short_max, a.tile);
-    ns += (d.n > 0 && d.n <= a.short_max) ? 1 : 0;
+    return d.n;
+  };
+  auto scan_round = [&](int64_t n, int64_t (&incl)[NCNT], int64_t (&last)[NCNT]) {
+    row_counts(n, a.short_max, a.tile, incl);
+    scan_counts(incl, sc);
+    for (int k = 0; k < NCNT; ++k) last[k] = sc[k][PLAN_WAVES - 1];
+    __syncthreads();  // sc is rewritten by the next scan
+  };
+
+  // pass 1
+  int64_t carry[NCNT] = {0, 0, 0, 0};
+  int64_t kn[PLAN_ROUNDS], ki3[PLAN_ROUNDS];
+  int32_t ki0[PLAN_ROUNDS], ki1[PLAN_ROUNDS], ki2[PLAN_ROUNDS];
+#pragma unroll
+  for (int q = 0; q < PLAN_ROUNDS; ++q) {
+    if (t == 0)
+      for (int k = 0; k < NCNT; ++k) ks[q][k] = carry[k];
+    if (q < rounds) {
+      int64_t incl[NCNT], last[NCNT];
+      kn[q] = resolve(q);
+      scan_round(kn[q], incl, last);
+      ki0[q] = (int32_t)incl[0];  // at most PLAN_THREADS * MAX_ROW_TILES
+      ki1[q] = (int32_t)incl[1];
+      ki2[q] = (int32_t)incl[2];
+      ki3[q] = incl[3];
+      for (int k = 0; k < NCNT; ++k) carry[k] += last[k];
+    }
   }
-  scan_long[t] = nl;
-  scan_short[t] = ns;
-  __syncthreads();
-  for (int off = 1; off < PLAN_THREADS; off <<= 1) {
-    int64_t vl = t >= off ? scan_long[t - off] : 0;
-    int64_t vs = t >= off ? scan_short[t - off] : 0;
-    __syncthreads();
-    scan_long[t] += vl;
-    scan_short[t] += vs;
-    __syncthreads();
+  if (t == 0)
+    for (int k = 0; k < NCNT; ++k) ks[PLAN_ROUNDS][k] = carry[k];
+  for (int64_t q = PLAN_ROUNDS; q < rounds; ++q) {
+    int64_t incl[NCNT], last[NCNT];
+    scan_round(resolve(q), incl, last);
+    for (int k = 0; k < NCNT; ++k) carry[k] += last[k];
   }
-  const int64_t total_long = scan_long[PLAN_THREADS - 1];
-  const int64_t total = total_long + scan_short[PLAN_THREADS - 1];
+  const int64_t total_long = carry[0], total = carry[0] + carry[1], n_lrows = carry[2], elems = carry[3];
+
+  // phase-2 chunks: G * m of them when the workspace holds that many
+  int64_t chunk = 1, n_chunks = 0;
+  if (elems > 0) {
+    const int64_t G = a.map_grid;
+    int64_t m = (elems + G * a.tile - 1) / (G * a.tile);
+    int64_t most = G * (m > 0 ? m : 1);
+    if (most > a.cap_chunks) most = a.cap_chunks;
+    chunk = (elems + most - 1) / most;
+    chunk = (chunk + 63) / 64 * 64;  // rows that start on a line keep their chunks on lines
+    n_chunks = (elems + chunk - 1) / chunk;
+  }
+
+  // pass 2
+  auto place_round = [&](int64_t q, int64_t n, const int64_t (&incl)[NCNT], const int64_t (&c)[NCNT],
+                         const int64_t (&last)[NCNT]) {
+    const int64_t r = q * PLAN_THREADS + t;
+    int64_t v[NCNT];
+    row_counts(n, a.short_max, a.tile, v);
+    ex_tile[t] = (int32_t)(incl[0] - v[0]);
+    ex_lrow[t] = (int32_t)(incl[2] - v[2]);
+    ex_elem[t] = incl[3] - v[3];
+    if (v[1]) a.items[total_long + c[1] + incl[1] - 1] = Item{(int32_t)r, 0};
+    if (v[2]) {
+      const int64_t k = c[2] + incl[2] - 1;
+      a.lrow_first[k] = c[0] + incl[0] - v[0];
+      a.lrows[k] = a.rows[r];  // written by this thread in pass 1
+      a.lstart[k] = c[3] + incl[3] - v[3];
+    }
+    __syncthreads();
+    for (int64_t i = t; i < last[0]; i += PLAN_THREADS) {
+      const int j = last_le(ex_tile, i);
+      a.items[c[0] + i] = Item{(int32_t)(q * PLAN_THREADS + j), (int32_t)(i - ex_tile[j])};
+    }
+    // the chunks whose first element lies in this round's long rows
+    int64_t ce = (c[3] + last[3] + chunk - 1) / chunk;
+    if (ce > n_chunks) ce = n_chunks;
+    for (int64_t cc = (c[3] + chunk - 1) / chunk + t; cc < ce; cc += PLAN_THREADS) {
+      const int j = last_le(ex_elem, cc * chunk - c[3]);
+      a.chunk_lrow[cc] = (int32_t)(c[2] + ex_lrow[j]);
+    }
+    __syncthreads();  // the LDS scans are rewritten by the next round
+  };
+  __syncthreads();  // ks is complete
   if (total <= a.cap_items) {
-    int64_t sl = scan_long[t] - nl;                // this thread's first long-tile item
-    int64_t ss = total_long + scan_short[t] - ns;  // and first short-row item
-    for (int64_t r = r0; r < r1; ++r) {
-      const int64_t n = a.rows[r].n;
-      const int64_t k = long_tiles(n, a.short_max, a.tile);
-      for (int64_t j = 0; j < k; ++j) a.items[sl + j] = Item{(int32_t)r, (int32_t)j};
-      sl += k;
-      if (n > 0 && n <= a.short_max) a.items[ss++] = Item{(int32_t)r, 0};
+#pragma unroll
+    for (int q = 0; q < PLAN_ROUNDS; ++q) {
+      if (q < rounds) {
+        const int64_t incl[NCNT] = {ki0[q], ki1[q], ki2[q], ki3[q]};
+        int64_t c[NCNT], last[NCNT];
+        for (int k = 0; k < NCNT; ++k) {
+          c[k] = ks[q][k];
+          last[k] = ks[q + 1][k] - ks[q][k];
+        }
+        place_round(q, kn[q], incl, c, last);
+      }
+    }
+    int64_t c[NCNT];
+    for (int k = 0; k < NCNT; ++k) c[k] = ks[PLAN_ROUNDS][k];
+    for (int64_t q = PLAN_ROUNDS; q < rounds; ++q) {
+      const int64_t r = q * PLAN_THREADS + t;
+      const int64_t n = r < nrows ? a.rows[r].n : 0;  // written by this thread in pass 1
+      int64_t incl[NCNT], last[NCNT];
+      scan_round(n, incl, last);
+      place_round(q, n, incl, c, last);
+      for (int k = 0; k < NCNT; ++k) c[k] += last[k];
     }
   }
   if (err) atomicOr(a.error, err);
-  if (t == PLAN_THREADS - 1) {
+  if (t == 0) {
     if (total > a.cap_items) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
-      a.n_items[0] = 0;
-      a.n_items[1] = 0;
+      for (int k = 0; k < CNT_COUNT; ++k) a.cnt[k] = 0;
     } else {
-      a.n_items[0] = total;
-      a.n_items[1] = total_long;
+      a.cnt[CNT_ITEMS] = total;
+      a.cnt[CNT_LONG_ITEMS] = total_long;
+      a.cnt[CNT_LONG_ROWS] = n_lrows;
+      a.cnt[CNT_LONG_ELEMS] = elems;
+      a.cnt[CNT_CHUNK] = chunk;
+      a.cnt[CNT_CHUNKS] = n_chunks;
     }
   }
 }
@@ -247,6 +423,12 @@ __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, i
   Acc<ACC> run;
   run.zero();
   int since_flush = 0;
+  // the unaligned head and the short tail, loaded before the stream so their
+  // latency overlaps it
+  const bool has_head = (int64_t)threadIdx.x < g.head;
+  const bool has_tail = (int64_t)threadIdx.x < n - g.tail_begin;
+  const float xh = has_head ? load_one<DTI>(seg, threadIdx.x) : 0.0f;
+  const float xt = has_tail ? load_one<DTI>(seg, g.tail_begin + threadIdx.x) : 0.0f;
   for (int64_t base = 0; base < g.nvec; base += step) {
     if (base + step <= g.nvec) {
       u4 r[U];
@@ -280,8 +462,8 @@ __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, i
       }
     }
   }
-  if ((int64_t)threadIdx.x < g.head) acc[0].add(load_one<DTI>(seg, threadIdx.x));
-  if ((int64_t)threadIdx.x < n - g.tail_begin) acc[0].add(load_one<DTI>(seg, g.tail_begin + threadIdx.x));
+  if (has_head) acc[0].add(xh);
+  if (has_tail) acc[0].add(xt);
   merge_chains<ACC, NA>(acc);
   run.merge(acc[0]);
   return block_reduce<ACC>(run, slots);
@@ -298,6 +480,11 @@ __device__ __forceinline__ void tile_map(const RowDesc& d, int64_t b, int64_t e,
   const u4* body = reinterpret_cast<const u4*>(in_seg + g.head * Elem<DTI>::SIZE);
   const bool vec_ok = out_vector_ok<DTI, DTO>(out_seg, g.head);
   const int64_t B = blockDim.x, step = B * U;
+  const bool has_head = (int64_t)threadIdx.x < g.head;
+  const int64_t ti = g.tail_begin + threadIdx.x;
+  const bool has_tail = ti < n;
+  const float xh = has_head ? load_one<DTI>(in_seg, threadIdx.x) : 0.0f;
+  const float xt = has_tail ? load_one<DTI>(in_seg, ti) : 0.0f;
   for (int64_t base = 0; base < g.nvec; base += step) {
     const int64_t v0 = base + threadIdx.x;
     if (base + step <= g.nvec) {
@@ -325,10 +512,8 @@ __device__ __forceinline__ void tile_map(const RowDesc& d, int64_t b, int64_t e,
       }
     }
   }
-  if ((int64_t)threadIdx.x < g.head)
-    store_one<DTO>(out_seg, threadIdx.x, load_one<DTI>(in_seg, threadIdx.x) / S);
-  const int64_t i = g.tail_begin + threadIdx.x;
-  if (i < n) store_one<DTO>(out_seg, i, load_one<DTI>(in_seg, i) / S);
+  if (has_head) store_one<DTO>(out_seg, threadIdx.x, xh / S);
+  if (has_tail) store_one<DTO>(out_seg, ti, xt / S);
 }
 
 // ---- dtype dispatch of one item --------------------------------------------------------
@@ -383,18 +568,25 @@ template <int ACC, int U, int KB>
 __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
   __shared__ Acc<ACC> slots[MAX_WAVES];
   __shared__ float s_bcast;
-  const int64_t n_items = a.n_items[0];
-  const int64_t n_long = a.n_items[1];
+  const int64_t n_items = a.cnt[CNT_ITEMS];
+  const int64_t n_long = a.cnt[CNT_LONG_ITEMS];
   Acc<ACC>* part = reinterpret_cast<Acc<ACC>*>(a.partials);
+  const int64_t G = gridDim.x;
   int64_t item = blockIdx.x;
   if (item >= n_items) return;
   Item it = a.items[item];
   RowDesc d = a.rows[it.row];
+  Item it_next = item + G < n_items ? a.items[item + G] : it;
   while (true) {
-    // the next item's descriptor is fetched while this one is processed
-    const int64_t next = item + gridDim.x;
-    Item it_next = it;
-    if (next < n_items) it_next = a.items[next];
+    // Two deep: the next item's descriptor (its index is already here) and
+    // the index of the one after are fetched while this item streams.
+    const int64_t next = item + G;
+    RowDesc d_next = d;
+    Item it_after = it_next;
+    if (next < n_items) {
+      d_next = a.rows[it_next.row];
+      if (next + G < n_items) it_after = a.items[next + G];
+    }
     if (item >= n_long) {
       dispatch_single<ACC, KB>(d, slots, &s_bcast);
     } else {
@@ -405,60 +597,79 @@ __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
     }
     if (next >= n_items) break;
     it = it_next;
-    d = a.rows[it.row];
+    d = d_next;
+    it_next = it_after;
     item = next;
     __syncthreads();  // the block's LDS is reused by the next item
   }
 }
 
-// The row's sum from its `count` tile partials, in a fixed order that
-// depends only on count: up to 64 partials one per lane of wavefront 0,
-// merged by the DPP tree; more through the LDS halving tree. Valid in
-// every thread on return.
+// Each long row's sum from its tile partials, in a fixed order that depends
+// only on the number of tiles (combine_partials: one wavefront for up to 1024
+// partials, the LDS tree beyond). One block per long row at a time.
 template <int ACC>
-__device__ __forceinline__ float row_sum(const Acc<ACC>* part, int64_t count, Acc<ACC>* tree,
-                                         Acc<ACC>* tiles, float* s_bcast) {
-  if (count <= 64) {
-    if (threadIdx.x < 64) {
-      Acc<ACC> v;
-      v.zero();
-      if ((int64_t)threadIdx.x < count) v = part[threadIdx.x];
-      v = wave_reduce<ACC>(v);
-      if (threadIdx.x == 0) *s_bcast = v.value();
-    }
-  } else {
-    Acc<ACC> tot = combine_partials<ACC>(part, count, tree, tiles);
-    if (threadIdx.x == 0) *s_bcast = tot.value();
-  }
-  __syncthreads();
-  return *s_bcast;
-}
-
-template <int ACC, int U>
-__global__ void __launch_bounds__(1024) batch_phase2_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(1024) batch_rowsum_kernel(BatchArgs a) {
   __shared__ Acc<ACC> tree[COMBINE_TILE];
   __shared__ Acc<ACC> tiles[MAX_COMBINE_TILES];
-  __shared__ float s_bcast;
-  const int64_t n_long = a.n_items[1];
+  const int64_t n_lrows = a.cnt[CNT_LONG_ROWS];
   const Acc<ACC>* part = reinterpret_cast<const Acc<ACC>*>(a.partials);
-  int64_t item = blockIdx.x;
-  if (item >= n_long) return;
-  Item it = a.items[item];
-  RowDesc d = a.rows[it.row];
+  for (int64_t k = blockIdx.x; k < n_lrows; k += gridDim.x) {
+    const int64_t first = a.lrow_first[k];
+    const int64_t count = (a.lrows[k].n + a.tile - 1) / a.tile;
+    Acc<ACC> tot = combine_partials<ACC>(part + first, count, tree, tiles);
+    if (threadIdx.x == 0) a.lsum[k] = tot.value();
+    __syncthreads();  // the trees are reused by the next row
+  }
+}
+
+// Phase 2 walks equal chunks of the long rows' concatenation: chunk c covers
+// positions [c * chunk, (c + 1) * chunk) and starts in long row
+// chunk_lrow[c]; a chunk that reaches past its row's end continues in the
+// following long rows.
+template <int U>
+__global__ void __launch_bounds__(1024) batch_phase2_kernel(BatchArgs a) {
+  const int64_t elems = a.cnt[CNT_LONG_ELEMS], chunk = a.cnt[CNT_CHUNK], n_chunks = a.cnt[CNT_CHUNKS];
+  const int64_t G = gridDim.x;
+  int64_t c = blockIdx.x;
+  if (c >= n_chunks) return;
+  int64_t k = a.chunk_lrow[c];
+  RowDesc d = a.lrows[k];
+  int64_t start = a.lstart[k];
+  float S = a.lsum[k];
+  int64_t k_next = c + G < n_chunks ? a.chunk_lrow[c + G] : k;
   while (true) {
-    const int64_t next = item + gridDim.x;
-    Item it_next = it;
-    if (next < n_long) it_next = a.items[next];
-    const int64_t count = (d.n + a.tile - 1) / a.tile;
-    const float S = row_sum<ACC>(part + (item - it.tile), count, tree, tiles, &s_bcast);
-    const int64_t b = (int64_t)it.tile * a.tile;
-    const int64_t e = b + a.tile < d.n ? b + a.tile : d.n;
-    dispatch_tile_map<U>(d, b, e, S);
-    if (next >= n_long) break;
-    it = it_next;
-    d = a.rows[it.row];
-    item = next;
-    __syncthreads();  // s_bcast and the trees are reused by the next item
+    // Two deep, as in phase 1: the next chunk's row (its index is already
+    // here) and the index of the one after.
+    const int64_t next = c + G;
+    RowDesc d_next = d;
+    int64_t start_next = start;
+    float S_next = S;
+    int64_t k_after = k_next;
+    if (next < n_chunks) {
+      d_next = a.lrows[k_next];
+      start_next = a.lstart[k_next];
+      S_next = a.lsum[k_next];
+      if (next + G < n_chunks) k_after = a.chunk_lrow[next + G];
+    }
+    int64_t pos = c * chunk;
+    const int64_t end = pos + chunk < elems ? pos + chunk : elems;
+    while (true) {
+      const int64_t e = end - start < d.n ? end - start : d.n;
+      dispatch_tile_map<U>(d, pos - start, e, S);
+      pos = start + e;
+      if (pos >= end) break;
+      ++k;  // the chunk continues in the next long row
+      d = a.lrows[k];
+      start = a.lstart[k];
+      S = a.lsum[k];
+    }
+    if (next >= n_chunks) break;
+    c = next;
+    k = k_next;
+    d = d_next;
+    start = start_next;
+    S = S_next;
+    k_next = k_after;
   }
 }
 
@@ -484,12 +695,17 @@ hipError_t phase1_u(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
 }
 
 template <int ACC>
-hipError_t phase2_u(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
+hipError_t rowsum_acc(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((batch_rowsum_kernel<ACC>), dim3(p.grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t phase2(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   switch (p.map_unroll) {
-    case 1: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 1>), dim3(p.grid), dim3(p.block), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 2>), dim3(p.grid), dim3(p.block), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 4>), dim3(p.grid), dim3(p.block), 0, s, a); break;
-    default: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 8>), dim3(p.grid), dim3(p.block), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((batch_phase2_kernel<1>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((batch_phase2_kernel<2>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((batch_phase2_kernel<4>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
+    default: hipLaunchKernelGGL((batch_phase2_kernel<8>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
   }
   return hipGetLastError();
 }
@@ -502,7 +718,9 @@ hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = p.acc == NRM_ACC_KAHAN ? phase1_u<NRM_ACC_KAHAN>(p, a, s) : phase1_u<NRM_ACC_F32>(p, a, s);
   if (e != hipSuccess) return e;
-  return p.acc == NRM_ACC_KAHAN ? phase2_u<NRM_ACC_KAHAN>(p, a, s) : phase2_u<NRM_ACC_F32>(p, a, s);
+  e = p.acc == NRM_ACC_KAHAN ? rowsum_acc<NRM_ACC_KAHAN>(p, a, s) : rowsum_acc<NRM_ACC_F32>(p, a, s);
+  if (e != hipSuccess) return e;
+  return phase2(p, a, s);
 }
 
 }  // namespace nrm

@@ -25,6 +25,10 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Staging layout: the header, then the row table from this offset.
 constexpr size_t kTableOffset = 256;
+// The planner's counters, then the device error word, in one small region.
+constexpr size_t kErrorOffset = sizeof(int64_t) * nrm::CNT_COUNT;
+constexpr size_t kSmallBytes = 64;
+static_assert(kErrorOffset + sizeof(int) <= kSmallBytes, "counters and error word must fit");
 static_assert(sizeof(BatchHeader) <= kTableOffset, "header must fit before the table");
 int64_t align_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
@@ -39,12 +43,16 @@ nrm_batch_params default_batch_params() {
   p.tile_log2 = 15;
   p.short_regs = 2;
   p.graph = 0;
+  p.map_block = 1024;
+  p.map_grid = 1024;
   return p;
 }
 
 int check_batch_params(const nrm_batch_params& p) {
   auto ok_u = [](int u) { return u == 1 || u == 2 || u == 4 || u == 8; };
-  if (p.block < 64 || p.block > 1024 || p.block % 64) return fail(NRM_EINVAL, "block must be 64..1024, a multiple of 64");
+  if (p.block < 64 || p.block > 1024 || p.block % 64 || p.map_block < 64 || p.map_block > 1024 || p.map_block % 64)
+    return fail(NRM_EINVAL, "block and map_block must be 64..1024, multiples of 64");
+  if (p.map_grid < 1 || p.map_grid > (1 << 20)) return fail(NRM_EINVAL, "map_grid must be 1..2^20");
   if (!ok_u(p.unroll) || !ok_u(p.map_unroll) || !ok_u(p.short_regs))
     return fail(NRM_EINVAL, "unroll, map_unroll and short_regs must be 1, 2, 4 or 8");
   if (p.grid < 1 || p.grid > (1 << 20)) return fail(NRM_EINVAL, "grid must be 1..2^20");
@@ -74,10 +82,14 @@ void destroy_graph(BatchWorkspace& w) {
 
 // Layout of the single device allocation.
 struct Layout {
-  size_t hdr, table, rows, items, small, partials, total;
+  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, small, partials, total;
 };
 
-Layout layout_for(int64_t cap_rows, int64_t cap_items) {
+// Phase-2 chunks a workspace holds beyond one per item: the planner sizes the
+// chunks to a multiple of the phase-2 grid when this allows it.
+constexpr int64_t kExtraChunks = 2048;
+
+Layout layout_for(int64_t cap_rows, int64_t cap_items, int64_t cap_chunks) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -85,11 +97,14 @@ Layout layout_for(int64_t cap_rows, int64_t cap_items) {
     off = (size_t)align_up((int64_t)(off + bytes), 256);
     return at;
   };
-  L.hdr = 0;
-  L.table = 0;
   L.rows = take(sizeof(RowDesc) * cap_rows);
   L.items = take(sizeof(nrm::Item) * cap_items);
-  L.small = take(64);  // n_items (2 x 8 bytes) + error (4 bytes)
+  L.lrow_first = take(sizeof(int64_t) * cap_rows);
+  L.lrows = take(sizeof(RowDesc) * cap_rows);
+  L.lstart = take(sizeof(int64_t) * cap_rows);
+  L.lsum = take(sizeof(float) * cap_rows);
+  L.chunk_lrow = take(sizeof(int32_t) * cap_chunks);
+  L.small = take(kSmallBytes);  // the planner's counters, then the error word
   L.partials = take(8 * cap_items);
   L.total = off;
   return L;
@@ -100,7 +115,8 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   if (rows <= w.cap_rows && items <= w.cap_items && w.dev) return NRM_OK;
   int64_t cap_rows = std::max<int64_t>({rows, w.cap_rows, 64});
   int64_t cap_items = std::max<int64_t>({items, w.cap_items, 1024});
-  Layout L = layout_for(cap_rows, cap_items);
+  const int64_t cap_chunks = cap_items + kExtraChunks;
+  Layout L = layout_for(cap_rows, cap_items, cap_chunks);
   // the old buffers may still be in use by enqueued work
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -137,13 +153,19 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   w.table = reinterpret_cast<RowDesc*>(static_cast<char*>(host_dev) + kTableOffset);
   w.rows = reinterpret_cast<RowDesc*>(d + L.rows);
   w.items = reinterpret_cast<nrm::Item*>(d + L.items);
-  w.n_items = reinterpret_cast<int64_t*>(d + L.small);
-  w.error = reinterpret_cast<int*>(d + L.small + 16);
+  w.lrow_first = reinterpret_cast<int64_t*>(d + L.lrow_first);
+  w.lrows = reinterpret_cast<RowDesc*>(d + L.lrows);
+  w.lstart = reinterpret_cast<int64_t*>(d + L.lstart);
+  w.lsum = reinterpret_cast<float*>(d + L.lsum);
+  w.chunk_lrow = reinterpret_cast<int32_t*>(d + L.chunk_lrow);
+  w.cnt = reinterpret_cast<int64_t*>(d + L.small);
+  w.error = reinterpret_cast<int*>(d + L.small + kErrorOffset);
   w.partials = d + L.partials;
   w.cap_rows = cap_rows;
   w.cap_items = cap_items;
+  w.cap_chunks = cap_chunks;
   w.staged_pending = false;
-  e = hipMemset(d + L.small, 0, 64);
+  e = hipMemset(d + L.small, 0, kSmallBytes);
   if (e == hipSuccess && err_word) e = hipMemcpy(w.error, &err_word, sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemset");
   if (!w.staged) {
@@ -164,13 +186,20 @@ BatchArgs args_of(const nrm_ctx* c) {
   a.hdr = w.hdr;
   a.rows = w.rows;
   a.items = w.items;
-  a.n_items = w.n_items;
+  a.lrow_first = w.lrow_first;
+  a.lrows = w.lrows;
+  a.lstart = w.lstart;
+  a.lsum = w.lsum;
+  a.chunk_lrow = w.chunk_lrow;
+  a.cnt = w.cnt;
   a.error = w.error;
   a.partials = w.partials;
   a.cap_rows = w.cap_rows;
   a.cap_items = w.cap_items;
+  a.cap_chunks = w.cap_chunks;
   a.tile = int64_t(1) << c->bparams.tile_log2;
   a.short_max = short_max_of(c->bparams);
+  a.map_grid = c->bparams.map_grid;
   return a;
 }
 
@@ -182,6 +211,8 @@ BatchPlan plan_of(const nrm_ctx* c, int acc) {
   p.map_unroll = c->bparams.map_unroll;
   p.short_regs = c->bparams.short_regs;
   p.grid = c->bparams.grid;
+  p.map_block = c->bparams.map_block;
+  p.map_grid = c->bparams.map_grid;
   return p;
 }
 

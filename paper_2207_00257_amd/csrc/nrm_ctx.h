@@ -46,12 +46,18 @@ class DeviceGuard {
 struct BatchWorkspace {
   int64_t cap_rows = 0;
   int64_t cap_items = 0;
+  int64_t cap_chunks = 0;
   void* dev = nullptr;         // one allocation, carved into the pointers below
   BatchHeader* hdr = nullptr;  // device view of the pinned staging header
   RowDesc* table = nullptr;    // device view of the pinned staging row table
   RowDesc* rows = nullptr;
   Item* items = nullptr;
-  int64_t* n_items = nullptr;
+  int64_t* lrow_first = nullptr;
+  RowDesc* lrows = nullptr;
+  int64_t* lstart = nullptr;
+  float* lsum = nullptr;
+  int32_t* chunk_lrow = nullptr;
+  int64_t* cnt = nullptr;
   int* error = nullptr;
   void* partials = nullptr;
   void* host = nullptr;        // pinned staging (host view): header, then the table

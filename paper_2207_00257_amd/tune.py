@@ -150,33 +150,51 @@ def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
     offs_d = torch.from_numpy(offs).to(dev)
     ctx = api.Context()
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    space = []
+    base_p = ctx.get_batch_params()
+    base_p["graph"] = 1
+    stage1 = []
     for block in (256, 512, 1024):
         for unroll in ((2, 4) if quick else (1, 2, 4, 8)):
-            for tile_log2 in ((14, 16) if quick else (13, 14, 15, 16, 17, 18)):
-                for short_regs in ((4, 8) if quick else (2, 4, 8)):
+            for tile_log2 in ((14, 15, 16) if quick else (13, 14, 15, 16, 17)):
+                for short_regs in ((2, 8) if quick else (1, 2, 4, 8)):
                     for gmul in ((2, 4) if quick else (1, 2, 4, 8)):
-                        space.append(dict(block=block, unroll=unroll, map_unroll=unroll, tile_log2=tile_log2,
-                                          short_regs=short_regs, grid=cus * gmul * max(1, 1024 // block // 2),
-                                          graph=1))
+                        stage1.append(dict(base_p, block=block, unroll=unroll, tile_log2=tile_log2,
+                                           short_regs=short_regs, grid=cus * gmul * max(1, 1024 // block)))
     table, best, best_t = [], None, float("inf")
     t0 = time.time()
     ctx.batch_reserve(rows, x.size)
-    for p in space:
+
+    def measure(p):
         try:
             ctx.set_batch_params(**p)
         except Exception:
-            continue  # shape rejected by the height bound
+            return None  # shape rejected by the height bound
         api.normalize_batched(out, inp, offs_d, ctx=ctx)
         ctx.set_timing(True)
         for _ in range(reps):
             api.normalize_batched(out, inp, offs_d, ctx=ctx)
         t, c = ctx.batch_times()
         ctx.set_timing(False)
-        ms = t / c
+        return t / c
+
+    for p in stage1:
+        ms = measure(p)
+        if ms is None:
+            continue
         table.append({"kernel": "batched", "params": p, "ms": ms})
         if ms < best_t:
             best, best_t = p, ms
+    for map_block in (256, 512, 1024):
+        for map_unroll in (1, 2, 4, 8):
+            for gmul in (1, 2, 4, 8, 16):
+                p = dict(best, map_block=map_block, map_unroll=map_unroll,
+                         map_grid=cus * gmul * max(1, 1024 // map_block))
+                ms = measure(p)
+                if ms is None:
+                    continue
+                table.append({"kernel": "batched", "params": p, "ms": ms})
+                if ms < best_t:
+                    best, best_t = p, ms
     log("batched sweep: %d candidates in %.1f s, best %.4f ms %s" % (len(table), time.time() - t0, best_t, best))
     ctx.close()
     return best, best_t, table

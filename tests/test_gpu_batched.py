@@ -66,6 +66,8 @@ BATCH_PARAMS = [
     dict(block=128, unroll=4, map_unroll=2, short_regs=4, tile_log2=12, grid=1),
     dict(graph=1),
     dict(graph=1, block=512, tile_log2=18, short_regs=4),
+    dict(map_block=64, map_grid=3, map_unroll=8),
+    dict(map_block=1024, map_grid=5000, tile_log2=11, grid=64),
 ]
 
 
@@ -110,14 +112,14 @@ def test_graph_replays_with_new_batches_and_eager_work_between():
 
 def test_row_is_position_independent():
     """A row's bits depend on its length, alignment and dtypes only: the same
-    row alone, or at another place in another batch (same 16-byte alignment),
+    row alone, or at another place in another batch (same 128-byte alignment),
     gives identical bits."""
     ctx = api.Context()
-    row = synth.lognormal_f32(100_004, 90, 1.0)  # a multiple of 4: the next row stays aligned
+    row = synth.lognormal_f32(100_000, 90, 1.0)  # a multiple of 32: the next row stays aligned
     short = synth.lognormal_f32(3001, 91, 1.0)
     alone = run_csr(row, np.array([0, row.size], np.int64), ctx).cpu().numpy()
     alone_s = run_csr(short, np.array([0, short.size], np.int64), ctx).cpu().numpy()
-    filler = synth.lognormal_f32(4 * 12345, 92, 1.0)  # a multiple of 4 floats: same alignment after it
+    filler = synth.lognormal_f32(32 * 1543, 92, 1.0)  # a multiple of 32 floats: same alignment after it
     x = np.concatenate([filler, row, short, filler])
     offs = np.array([0, 7, filler.size, filler.size + row.size, filler.size + row.size + short.size, x.size],
                     np.int64)
@@ -247,4 +249,31 @@ def test_workspace_grows_between_calls():
         offs = synth.ragged_offsets(lengths)
         x = synth.lognormal_f32(int(offs[-1]), seed, 1.0)
         check_rows(run_csr(x, offs, ctx).cpu().numpy(), x, offs, "rows=%d" % rows)
+    ctx.close()
+
+
+def test_rows_with_many_tiles():
+    """Rows of more than 64 and more than 1024 tiles: the row sum merges its
+    partials in one wavefront, then through the LDS tree."""
+    ctx = api.Context()
+    ctx.set_batch_params(tile_log2=10, block=64, unroll=1, map_unroll=1)
+    lengths = np.array([70 * 1024 + 5, 3, 1100 * 1024 + 17, 5000], np.int64)
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 140, 1.0)
+    check_rows(run_csr(x, offs, ctx).cpu().numpy(), x, offs, "many tiles")
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+def test_many_rows_planner_rounds():
+    """More rows than the planner's threads (several scan rounds), with empty,
+    short and long rows interleaved."""
+    lengths = synth.loguniform_lengths(5000, 141, 1, 1 << 14)
+    lengths[::7] = 0
+    lengths[3::11] = 40000
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 142, 1.0)
+    ctx = api.Context()
+    check_rows(run_csr(x, offs, ctx).cpu().numpy(), x, offs, "5000 rows")
+    assert ctx.device_error() == L.NRM_OK
     ctx.close()

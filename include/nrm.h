@@ -70,9 +70,11 @@ typedef enum { NRM_F32 = 0, NRM_BF16 = 1, NRM_F16 = 2 } nrm_dtype;
  * (TwoSum). */
 typedef enum { NRM_ACC_F32 = 0, NRM_ACC_KAHAN = 1 } nrm_accum;
 
-/* How blocks cover the input: each block a contiguous chunk, or the grid
- * strides over the input one block-iteration at a time. */
-typedef enum { NRM_LAYOUT_CHUNK = 0, NRM_LAYOUT_STRIDE = 1 } nrm_layout;
+/* How blocks cover the input: each block a contiguous chunk; the grid
+ * strides over the input one block-iteration at a time; or the input is cut
+ * into tiles of 2^tile_log2 elements (rounded up to whole block-iterations)
+ * and block b streams tiles b, b + grid, b + 2 grid, ... */
+typedef enum { NRM_LAYOUT_CHUNK = 0, NRM_LAYOUT_STRIDE = 1, NRM_LAYOUT_TILE = 2 } nrm_layout;
 
 /* Launch parameters of the plain path. Start from nrm_default_params() and
  * change fields; nrm_set_params validates every field. Changing them changes
@@ -98,7 +100,13 @@ typedef struct {
   int32_t reduce_keep_mib; /* 0..4096: the reduce reads the last this many MiB of the input with a
                               temporal hint (the rest non-temporal), so that a reverse map may find
                               them in the last-level cache */
-  int32_t reserved[3];
+  int32_t tile_log2;    /* layout TILE (either kernel): log2 of the elements per tile, 10..22 */
+  int32_t fused_combine;/* 1: the reduce ends without a grid-wide ticket or fence and every map
+                           block merges the reduce's partials itself, in the same fixed order
+                           (height 10), so all blocks divide by the same value. Taken when the
+                           reduce has at most 1024 blocks and out is aligned like in; otherwise
+                           the last reduce block combines as with 0. */
+  int32_t reserved[1];
 } nrm_params;
 
 /* Launch parameters of the ragged batched path. Start from

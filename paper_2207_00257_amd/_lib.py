@@ -34,7 +34,9 @@ class NrmParams(ctypes.Structure):
         ("map_nt", ctypes.c_int32),
         ("reverse_map", ctypes.c_int32),
         ("reduce_keep_mib", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("tile_log2", ctypes.c_int32),
+        ("fused_combine", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 

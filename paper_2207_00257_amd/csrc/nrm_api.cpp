@@ -29,32 +29,36 @@ std::string& last_error() {
 namespace {
 
 // Defaults: the best shape found by the tuner (paper_2207_00257_amd/tune.py)
-// on MI355X for n = 2^28 FP32. The reduce streams with one 1024-thread block
-// per CU and non-temporal loads; the map runs many smaller blocks, both
-// striding over the whole input a block-iteration at a time.
+// on MI355X for n = 2^28 FP32. The reduce streams tiles of 2^13 elements
+// (block b takes tiles b, b + grid, ...) with one block per CU and ends
+// without a grid-wide ticket: every map block merges the reduce's partials
+// itself. The map runs many blocks striding over the whole input a
+// block-iteration at a time, each walking its share from the end.
 nrm_params default_params() {
   nrm_params p;
   std::memset(&p, 0, sizeof(p));
-  p.block = 1024;
-  p.unroll = 4;
+  p.block = 256;
+  p.unroll = 8;
   p.grid = 256;
-  p.layout = NRM_LAYOUT_STRIDE;
+  p.layout = NRM_LAYOUT_TILE;
   p.reduce_nt = 1;
   p.max_height = 36;
-  p.map_block = 256;
+  p.map_block = 512;
   p.map_unroll = 4;
   p.map_grid = 8192;
   p.map_layout = NRM_LAYOUT_STRIDE;
   p.map_nt = 1;
-  p.reverse_map = 0;
-  p.reduce_keep_mib = 0;
+  p.reverse_map = 1;
+  p.reduce_keep_mib = 64;
+  p.tile_log2 = 13;
+  p.fused_combine = 1;
   return p;
 }
 
 int check_params(const nrm_params& p) {
   auto ok_b = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
   auto ok_u = [](int u) { return u == 1 || u == 2 || u == 4 || u == 8; };
-  auto ok_l = [](int l) { return l == NRM_LAYOUT_CHUNK || l == NRM_LAYOUT_STRIDE; };
+  auto ok_l = [](int l) { return l == NRM_LAYOUT_CHUNK || l == NRM_LAYOUT_STRIDE || l == NRM_LAYOUT_TILE; };
   auto ok_f = [](int f) { return f == 0 || f == 1; };
   if (!ok_b(p.block) || !ok_b(p.map_block)) return fail(NRM_EINVAL, "block sizes must be 64..1024, multiples of 64");
   if (!ok_u(p.unroll) || !ok_u(p.map_unroll)) return fail(NRM_EINVAL, "unroll and map_unroll must be 1, 2, 4 or 8");
@@ -64,6 +68,8 @@ int check_params(const nrm_params& p) {
   if (!ok_f(p.reduce_nt) || !ok_f(p.map_nt) || !ok_f(p.reverse_map))
     return fail(NRM_EINVAL, "reduce_nt, map_nt and reverse_map must be 0 or 1");
   if (p.reduce_keep_mib < 0 || p.reduce_keep_mib > 4096) return fail(NRM_EINVAL, "reduce_keep_mib must be 0..4096");
+  if (p.tile_log2 < 10 || p.tile_log2 > 22) return fail(NRM_EINVAL, "tile_log2 must be 10..22");
+  if (!ok_f(p.fused_combine)) return fail(NRM_EINVAL, "fused_combine must be 0 or 1");
   for (int r : p.reserved)
     if (r != 0) return fail(NRM_EINVAL, "reserved fields must be zero");
   return NRM_OK;
@@ -149,8 +155,12 @@ int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_d
   p->in_dt = in_dt;
   p->out_dt = out_dt;
   p->acc = acc;
-  int64_t mis = (int64_t)(ai & 15);
-  p->head = std::min<int64_t>(mis ? (16 - mis) / si : 0, n);
+  // The vector body starts on a 128-byte line so that every wavefront's
+  // accesses cover whole lines (partial lines at both ends of each access
+  // cost about a tenth of the bandwidth with non-temporal stores); the head
+  // before it (at most 63 elements) is handled by block 0, one per thread.
+  int64_t mis = (int64_t)(ai & 127);
+  p->head = std::min<int64_t>(mis ? (128 - mis) / si : 0, n);
   p->nvec = (n - p->head) / vec;
   p->tail_begin = p->head + p->nvec * vec;
   const int64_t out_align = std::min(16, vec * so);
@@ -173,9 +183,30 @@ int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_d
     max_iters = 1;
     while (nrm::thread_tree_height(in_dt, acc, q.unroll, max_iters + 1) <= q.max_height) ++max_iters;
   }
-  split(p->nvec, (int64_t)q.block * q.unroll, q.grid, max_iters, &p->grid, &p->chunk);
+  const int64_t step = (int64_t)q.block * q.unroll;
+  split(p->nvec, step, q.grid, max_iters, &p->grid, &p->chunk);
+  p->tile = 0;
+  if (q.layout == NRM_LAYOUT_TILE) {
+    // whole block-iterations per tile; a block's tiles together stay within
+    // max_iters iterations
+    int64_t per_tile = std::max<int64_t>(1, ceil_div((int64_t(1) << q.tile_log2) / vec, step));
+    if (max_iters > 0) per_tile = std::min(per_tile, max_iters);
+    p->tile = per_tile * step;
+    const int64_t ntiles = std::max<int64_t>(1, ceil_div(p->nvec, p->tile));
+    int64_t g = std::min<int64_t>(q.grid, ntiles);
+    if (max_iters > 0) g = std::max(g, ceil_div(ntiles, max_iters / per_tile));
+    p->grid = g;
+  }
   p->map_units = (si == 2 && so == 4) ? 2 * p->nvec : p->nvec;
-  split(p->map_units, (int64_t)q.map_block * q.map_unroll, q.map_grid, 0, &p->map_grid, &p->map_chunk);
+  const int64_t map_step = (int64_t)q.map_block * q.map_unroll;
+  split(p->map_units, map_step, q.map_grid, 0, &p->map_grid, &p->map_chunk);
+  p->map_tile = 0;
+  if (q.map_layout == NRM_LAYOUT_TILE) {
+    const int unit_elems = (si == 2 && so == 4) ? 4 : vec;
+    p->map_tile = std::max<int64_t>(1, ceil_div((int64_t(1) << q.tile_log2) / unit_elems, map_step)) * map_step;
+    p->map_grid = std::min<int64_t>(q.map_grid, std::max<int64_t>(1, ceil_div(p->map_units, p->map_tile)));
+  }
+  p->fused = q.fused_combine && p->vector_map && p->grid <= 1024;
   if (p->grid > 65536) return fail(NRM_EINVAL, "n too large for these launch parameters (over 65536 reduce blocks)");
   if (p->map_grid > INT32_MAX) return fail(NRM_EINVAL, "n too large for one launch");
   return NRM_OK;

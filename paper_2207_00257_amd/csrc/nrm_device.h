@@ -291,6 +291,31 @@ __device__ __forceinline__ void merge_chains(Acc<ACC> (&acc)[NA]) {
     for (int k = 0; k + s < NA; k += 2 * s) acc[k].merge(acc[k + s]);
 }
 
+// Up to 1024 partials merged by wavefront 0 alone, no LDS and no barrier:
+// lane l holds partials l, l + 64, ... (up to 16), merges them pairwise, then
+// the DPP wavefront tree; height 4 + 6. Call from all 64 lanes of wavefront
+// 0; the result is valid in lane 0. ATOMIC: read with agent-scope atomic
+// loads (partials published inside the same kernel); otherwise plain loads
+// (partials written by an earlier kernel).
+template <int ACC, bool ATOMIC>
+__device__ __forceinline__ Acc<ACC> combine_wave(const Acc<ACC>* part, int64_t count) {
+  Acc<ACC> v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k].zero();
+    const int64_t i = threadIdx.x + 64 * k;
+    if (i < count) {
+      if constexpr (ATOMIC) fetch(part, i, v[k]);
+      else v[k] = part[i];
+    }
+  }
+#pragma unroll
+  for (int s = 1; s < 16; s <<= 1)
+#pragma unroll
+    for (int k = 0; k + s < 16; k += 2 * s) v[k].merge(v[k + s]);
+  return wave_reduce<ACC>(v[0]);
+}
+
 // Merge `count` partials (published with `publish`) into one value in a
 // fixed order that depends only on count: up to 1024 partials in wavefront 0
 // (registers and DPP); more in tiles of COMBINE_TILE partials merged by a
@@ -302,25 +327,10 @@ template <int ACC>
 __device__ __forceinline__ Acc<ACC> combine_partials(const Acc<ACC>* part, int64_t count,
                                                      Acc<ACC>* tree, Acc<ACC>* tiles) {
   if (count <= 64 * 16) {
-    // Wavefront 0 alone, no barrier: lane l holds partials l, l + 64, ...
-    // (up to 16), merges them pairwise, then the DPP wavefront tree; the same
-    // height (4 + 6) as the LDS tree below.
+    // wavefront 0 alone; the same height as the LDS tree below
     Acc<ACC> total;
     total.zero();
-    if (threadIdx.x < 64) {
-      Acc<ACC> v[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        v[k].zero();
-        const int64_t i = threadIdx.x + 64 * k;
-        if (i < count) fetch(part, i, v[k]);
-      }
-#pragma unroll
-      for (int s = 1; s < 16; s <<= 1)
-#pragma unroll
-        for (int k = 0; k + s < 16; k += 2 * s) v[k].merge(v[k + s]);
-      total = wave_reduce<ACC>(v[0]);
-    }
+    if (threadIdx.x < 64) total = combine_wave<ACC, true>(part, count);
     return total;
   }
   const int ntiles = (int)((count + COMBINE_TILE - 1) / COMBINE_TILE);

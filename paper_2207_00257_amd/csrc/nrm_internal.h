@@ -47,7 +47,7 @@ struct PlainPlan {
   void* out;
   int64_t n;
   int in_dt, out_dt, acc;
-  int64_t head;       // elements before the first 16-byte aligned input vector
+  int64_t head;       // elements before the input's first 128-byte line
   int64_t nvec;       // 16-byte input vectors in the aligned body
   int64_t tail_begin; // first element after the body
   bool vector_map;    // out is aligned like in, so the map can use vector stores
@@ -56,7 +56,9 @@ struct PlainPlan {
   int unroll;         // 16-byte vectors per thread per iteration
   int64_t grid;       // blocks
   int64_t chunk;      // vectors per block (layout CHUNK; multiple of block * unroll)
+  int64_t tile;       // vectors per tile (layout TILE; multiple of block * unroll)
   int layout;         // NRM_LAYOUT_*
+  bool fused;         // no grid-wide ticket: every map block merges the partials
   int reduce_nt;      // non-temporal hint on loads
   int64_t keep_from;  // vectors from this index on are loaded with a temporal hint
   // map kernel
@@ -64,6 +66,7 @@ struct PlainPlan {
   int map_unroll;
   int64_t map_grid;
   int64_t map_chunk;  // map units per block (layout CHUNK)
+  int64_t map_tile;   // map units per tile (layout TILE)
   int64_t map_units;  // map units in the body: 16-byte vectors, or 8-byte halves
                       // for a 2-byte input with binary32 output
   int map_layout;

@@ -42,7 +42,9 @@ struct ReduceArgs {
   int64_t tail_begin;  // first element after the body
   int64_t n;
   int64_t chunk;       // vectors per block (layout CHUNK), multiple of blockDim * U
+  int64_t tile;        // vectors per tile (layout TILE), multiple of blockDim * U
   int layout;
+  int fused;           // 1: publish the partial and end; the map blocks combine
   int64_t keep_from;   // vectors from here on: temporal loads even when NT
   void* partials;      // Acc<ACC>[gridDim.x]
   unsigned* ticket;    // 0 on entry, left 0 on exit
@@ -104,14 +106,8 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
       }
     }
   };
-  const int64_t last_full = end - step;  // a base <= last_full starts a full iteration
-  int64_t base = begin;
-  if (NT) {
-    const int64_t nt_end = a.keep_from < last_full + 1 ? a.keep_from : last_full + 1;
-    for (; base < nt_end; base += stride) full(base, std::integral_constant<bool, true>());
-  }
-  for (; base <= last_full; base += stride) full(base, std::integral_constant<bool, false>());
-  if (base < end) {
+  // the one partial iteration a block can have: vectors [base, end)
+  auto partial = [&](int64_t base, int64_t end) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (base + u * B + (int64_t)threadIdx.x < end) {
@@ -121,6 +117,29 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
         for (int k = 0; k < VEC; ++k) acc[(u * VEC + k) % NA].add(x[k]);
       }
     }
+  };
+  if (a.layout == NRM_LAYOUT_TILE) {
+    // tiles blockIdx.x, blockIdx.x + gridDim.x, ...; only the input's last
+    // tile can end in a partial iteration, and it is its block's last
+    const int64_t tile_stride = (int64_t)gridDim.x * a.tile;
+    for (int64_t tb = (int64_t)blockIdx.x * a.tile; tb < a.nvec; tb += tile_stride) {
+      const int64_t te = tb + a.tile < a.nvec ? tb + a.tile : a.nvec;
+      int64_t base = tb;
+      for (; base + step <= te; base += step) {
+        if (NT && base < a.keep_from) full(base, std::integral_constant<bool, NT>());
+        else full(base, std::integral_constant<bool, false>());
+      }
+      if (base < te) partial(base, te);
+    }
+  } else {
+    const int64_t last_full = end - step;  // a base <= last_full starts a full iteration
+    int64_t base = begin;
+    if (NT) {
+      const int64_t nt_end = a.keep_from < last_full + 1 ? a.keep_from : last_full + 1;
+      for (; base < nt_end; base += stride) full(base, std::integral_constant<bool, NT>());
+    }
+    for (; base <= last_full; base += stride) full(base, std::integral_constant<bool, false>());
+    if (base < end) partial(base, end);
   }
   // unaligned head and the tail shorter than a vector: block 0
   if (blockIdx.x == 0) {
@@ -132,8 +151,14 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
 
   Acc<ACC> blk = block_reduce<ACC>(run, slots);
 
-  // publish the partial; the last block to arrive combines all of them
+  // publish the partial; the last block to arrive combines all of them, or,
+  // fused, every block of the map kernel does (after the kernel boundary, so
+  // no fence and no ticket here)
   Acc<ACC>* part = reinterpret_cast<Acc<ACC>*>(a.partials);
+  if (a.fused) {
+    if (threadIdx.x == 0) publish(part, blockIdx.x, blk);
+    return;
+  }
   if (threadIdx.x == 0) {
     publish(part, blockIdx.x, blk);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -162,10 +187,17 @@ struct MapArgs {
   const u4* body;      // first aligned input vector
   char* out_body;      // output element `head`
   int64_t head, nvec, tail_begin, n;
-  int64_t chunk;       // vectors per block (layout CHUNK), multiple of blockDim * U
+  int64_t chunk;       // units per block (layout CHUNK), multiple of blockDim * U
+  int64_t tile;        // units per tile (layout TILE), multiple of blockDim * U
   int layout;
   int reverse;
-  const float* sum;
+  const float* sum;    // the sum (not fused)
+  // fused combine: every block merges the reduce's partials itself
+  int fused;
+  int acc;             // nrm_accum of the partials
+  const void* partials;
+  int64_t nparts;      // at most 1024
+  float* sum_out;      // block 0 stores the merged sum here
 };
 
 // Units of the map: a 16-byte input vector, or, for a 2-byte input with
@@ -178,32 +210,42 @@ struct MapUnit {
   using T = typename std::conditional<HALF, u2, u4>::type;
 };
 
+// The divisor of the map: the reduce's sum, or (fused) the merge of its
+// partials by wavefront 0 of this block, in the same fixed order in every
+// block (bitwise the same value everywhere).
+__device__ __forceinline__ float map_divisor(const MapArgs& a) {
+  if (!a.fused) return a.sum[0];
+  __shared__ float s_sum;
+  if (threadIdx.x < 64) {
+    float v;
+    if (a.acc == NRM_ACC_KAHAN)
+      v = combine_wave<NRM_ACC_KAHAN, false>(static_cast<const Acc<NRM_ACC_KAHAN>*>(a.partials), a.nparts).value();
+    else
+      v = combine_wave<NRM_ACC_F32, false>(static_cast<const Acc<NRM_ACC_F32>*>(a.partials), a.nparts).value();
+    if (threadIdx.x == 0) {
+      s_sum = v;
+      if (blockIdx.x == 0) a.sum_out[0] = v;
+    }
+  }
+  __syncthreads();
+  return s_sum;
+}
+
 template <int DTI, int DTO, int U, bool NT>
 __global__ void __launch_bounds__(1024) map_kernel(MapArgs a) {
   using MU = MapUnit<DTI, DTO>;
   using T = typename MU::T;
   constexpr int VEC = MU::ELEMS;
   const T* body = reinterpret_cast<const T*>(a.body);
-  const float S = a.sum[0];
+  const float S = map_divisor(a);
   const int64_t B = blockDim.x;
   const int64_t step = B * U;
-  int64_t begin, end, stride;
-  if (a.layout == NRM_LAYOUT_CHUNK) {
-    begin = (int64_t)blockIdx.x * a.chunk;
-    end = begin + a.chunk < a.nvec ? begin + a.chunk : a.nvec;
-    stride = step;
-  } else {
-    begin = (int64_t)blockIdx.x * step;
-    end = a.nvec;
-    stride = (int64_t)gridDim.x * step;
-  }
   auto widen_unit = [](T r, float (&x)[VEC]) {
     if constexpr (MU::HALF) widen_half<DTI>(r, x);
     else widen<DTI>(r, x);
   };
-  const int64_t iters = end > begin ? (end - begin + stride - 1) / stride : 0;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t base = begin + (a.reverse ? iters - 1 - it : it) * stride;
+  // one block-iteration over units [base, base + step) clipped to end
+  auto iteration = [&](int64_t base, int64_t end) {
     const int64_t v0 = base + threadIdx.x;
     if (base + step <= end) {
       T r[U];
@@ -229,6 +271,26 @@ __global__ void __launch_bounds__(1024) map_kernel(MapArgs a) {
         }
       }
     }
+  };
+  if (a.layout == NRM_LAYOUT_TILE) {
+    const int64_t tile_stride = (int64_t)gridDim.x * a.tile;
+    for (int64_t tb = (int64_t)blockIdx.x * a.tile; tb < a.nvec; tb += tile_stride) {
+      const int64_t te = tb + a.tile < a.nvec ? tb + a.tile : a.nvec;
+      for (int64_t base = tb; base < te; base += step) iteration(base, te);
+    }
+  } else {
+    int64_t begin, end, stride;
+    if (a.layout == NRM_LAYOUT_CHUNK) {
+      begin = (int64_t)blockIdx.x * a.chunk;
+      end = begin + a.chunk < a.nvec ? begin + a.chunk : a.nvec;
+      stride = step;
+    } else {
+      begin = (int64_t)blockIdx.x * step;
+      end = a.nvec;
+      stride = (int64_t)gridDim.x * step;
+    }
+    const int64_t iters = end > begin ? (end - begin + stride - 1) / stride : 0;
+    for (int64_t it = 0; it < iters; ++it) iteration(begin + (a.reverse ? iters - 1 - it : it) * stride, end);
   }
   if (blockIdx.x == 0) {
     if ((int64_t)threadIdx.x < a.head)
@@ -322,7 +384,9 @@ hipError_t launch_reduce(const PlainPlan& p, const PlainWorkspace& ws, hipStream
   a.tail_begin = p.tail_begin;
   a.n = p.n;
   a.chunk = p.chunk;
+  a.tile = p.tile;
   a.layout = p.layout;
+  a.fused = p.fused;
   a.keep_from = p.keep_from;
   a.partials = ws.partials;
   a.ticket = ws.ticket;
@@ -345,9 +409,15 @@ hipError_t launch_map(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t 
   a.tail_begin = p.tail_begin;
   a.n = p.n;
   a.chunk = p.map_chunk;
+  a.tile = p.map_tile;
   a.layout = p.map_layout;
   a.reverse = p.reverse_map;
   a.sum = ws.sum;
+  a.fused = p.fused;
+  a.acc = p.acc;
+  a.partials = ws.partials;
+  a.nparts = p.grid;
+  a.sum_out = ws.sum;
   switch (p.in_dt) {
     case NRM_F32: return map_in<NRM_F32>(p, a, s);
     case NRM_BF16: return map_in<NRM_BF16>(p, a, s);

@@ -1,10 +1,11 @@
 """Autotuner for the plain normalize path's launch parameters.
 
-Sweeps the reduce kernel's shape (layout, block, unroll, grid, load hint)
-with the map at its defaults, then the map kernel's shape (layout, block,
-unroll, grid, load hint, traversal direction) with the best reduce, timing
-each kernel with the HIP events the library records around it on the call's
-stream. Every candidate is a valid parameter set of the C ABI, so the sweep
+Sweeps the reduce kernel's shape (layout, block, unroll, grid, load hint,
+fused combine) with the map at its defaults, then the map kernel's shape
+(layout, block, unroll, grid, load hint, traversal direction) with the best
+reduce, then the tile size; every candidate is scored by the time of both
+kernels, measured with the HIP events the library records around them on
+the call's stream. Every candidate is a valid parameter set of the C ABI, so the sweep
 changes only speed and the low bits allowed by the error bound.
 
     python -m paper_2207_00257_amd.tune --log2n 28 [--dtype f32] [--out FILE]
@@ -75,6 +76,12 @@ def _time_call(ctx, out, inp, accum, reps):
 
 
 def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=False, log=print):
+    """Three stages, each scored by the time of both kernels (the fused
+    combine moves work from the reduce into the map): the reduce's shape
+    (layout, block, unroll, grid, load hint, fused combine) with the map at
+    its defaults; the map's shape (layout, block, unroll, grid, load hint,
+    direction) with the best reduce; then the tile size and the temporal tail
+    of the reduce."""
     import torch
 
     from . import api, synth
@@ -88,51 +95,74 @@ def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=Fa
     base = ctx.get_params()
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
 
-    grids = [cus * k for k in ((2, 4, 8) if quick else (1, 2, 4, 8, 16))]
-    red_space = list(itertools.product((0, 1), (256, 512, 1024), (2, 4, 8), grids, (0, 1)))
+    grids = [cus * k for k in ((1, 2, 4) if quick else (1, 2, 4, 8, 16))]
+    red_space = list(itertools.product((0, 1, 2), (256, 512, 1024), (2, 4, 8), grids, (0, 1), (0, 1)))
     map_grids = [cus * k for k in ((4, 8) if quick else (2, 4, 8, 16, 32))]
-    map_space = list(itertools.product((0, 1), (256, 512, 1024), (1, 2, 4, 8), map_grids, (0, 1), (0, 1)))
+    map_space = [c for c in itertools.product((0, 1, 2), (256, 512, 1024), (1, 2, 4, 8), map_grids, (0, 1), (0, 1))
+                 if not (c[0] == 2 and c[5])]  # the tiled map has no reverse walk
 
     table = []
-    best_r, best_rt = None, float("inf")
-    t0 = time.time()
-    for layout, block, unroll, grid, nt in red_space:
-        p = dict(base, layout=layout, block=block, unroll=unroll, grid=grid, reduce_nt=nt)
+    best, best_t = None, float("inf")
+
+    def measure(p, stage):
+        nonlocal best, best_t
         ctx.set_params(**p)
-        rt, _ = _time_call(ctx, out, inp, accum, reps)
-        table.append({"kernel": "reduce", "params": p, "ms": rt})
-        if rt < best_rt:
-            best_r, best_rt = p, rt
+        rt, mt = _time_call(ctx, out, inp, accum, reps)
+        table.append({"kernel": stage, "params": p, "ms": rt + mt, "reduce_ms": rt, "map_ms": mt})
+        if rt + mt < best_t:
+            best, best_t = dict(p), rt + mt
+        return rt, mt
+
+    t0 = time.time()
+    for layout, block, unroll, grid, nt, fused in red_space:
+        if fused and grid > 1024:
+            continue  # the fused combine takes at most 1024 partials
+        measure(dict(base, layout=layout, block=block, unroll=unroll, grid=grid, reduce_nt=nt,
+                     fused_combine=fused), "reduce")
     log("reduce sweep: %d candidates in %.1f s, best %.4f ms %s"
-        % (len(red_space), time.time() - t0, best_rt, {k: best_r[k] for k in
-                                                        ("layout", "block", "unroll", "grid", "reduce_nt")}))
-    best_m, best_mt = None, float("inf")
+        % (len(red_space), time.time() - t0, best_t, {k: best[k] for k in
+                                                       ("layout", "block", "unroll", "grid", "reduce_nt",
+                                                        "fused_combine")}))
+    best_r = dict(best)
     t0 = time.time()
     for layout, block, unroll, grid, nt, rev in map_space:
-        p = dict(best_r, map_layout=layout, map_block=block, map_unroll=unroll, map_grid=grid, map_nt=nt,
-                 reverse_map=rev)
-        ctx.set_params(**p)
-        _, mt = _time_call(ctx, out, inp, accum, reps)
-        table.append({"kernel": "map", "params": p, "ms": mt})
-        if mt < best_mt:
-            best_m, best_mt = p, mt
-    # the tail the reduce leaves in the last-level cache, read first by a reverse map
+        measure(dict(best_r, map_layout=layout, map_block=block, map_unroll=unroll, map_grid=grid, map_nt=nt,
+                     reverse_map=rev), "map")
+    log("map sweep: %d candidates in %.1f s, best %.4f ms %s"
+        % (len(map_space), time.time() - t0, best_t, {k: best[k] for k in
+                                                       ("map_layout", "map_block", "map_unroll", "map_grid",
+                                                        "map_nt", "reverse_map")}))
+    # tile size (either kernel tiled), then the tail the reduce leaves in the
+    # last-level cache, read first by a reverse map
+    if best["layout"] == 2 or best["map_layout"] == 2:
+        for tl in range(12, 20):
+            measure(dict(best, tile_log2=tl), "tile")
     for keep, rev, nt in itertools.product((0, 64, 128, 192, 256, 384), (0, 1), (0, 1)):
-        if nt == 0 and keep:
-            continue  # all of the reduce's loads are temporal anyway
-        if True:
-            p = dict(best_m, reduce_keep_mib=keep, reverse_map=rev, reduce_nt=nt)
+        if (nt == 0 and keep) or (rev and best["map_layout"] == 2):
+            continue  # all of the reduce's loads are temporal anyway / no reverse walk when tiled
+        measure(dict(best, reduce_keep_mib=keep, reverse_map=rev, reduce_nt=nt), "keep")
+    # the leaders again, interleaved round by round with more repetitions, so
+    # that neither a single noisy measurement nor drift picks the winner
+    leaders = []
+    for r in sorted(table, key=lambda r: r["ms"]):
+        if r["params"] not in leaders:
+            leaders.append(r["params"])
+        if len(leaders) == (4 if quick else 10):
+            break
+    sums = [[0.0, 0.0] for _ in leaders]
+    for _ in range(6):
+        for i, p in enumerate(leaders):
             ctx.set_params(**p)
             rt, mt = _time_call(ctx, out, inp, accum, reps)
-            table.append({"kernel": "keep", "params": p, "ms": rt + mt, "reduce_ms": rt, "map_ms": mt})
-            if rt + mt < best_rt + best_mt:
-                best_m, best_rt, best_mt = p, rt, mt
-    log("map sweep: %d candidates in %.1f s, best %.4f ms %s"
-        % (len(map_space), time.time() - t0, best_mt, {k: best_m[k] for k in
-                                                        ("map_layout", "map_block", "map_unroll", "map_grid",
-                                                         "map_nt", "reverse_map")}))
+            sums[i][0] += rt
+            sums[i][1] += mt
+    i = min(range(len(leaders)), key=lambda i: sums[i][0] + sums[i][1])
+    best, rt, mt = leaders[i], sums[i][0] / 6, sums[i][1] / 6
+    for p, (r_, m_) in zip(leaders, sums):
+        table.append({"kernel": "final", "params": p, "ms": (r_ + m_) / 6, "reduce_ms": r_ / 6, "map_ms": m_ / 6})
+    log("final: best of %d leaders %.4f ms" % (len(leaders), rt + mt))
     ctx.close()
-    return best_m, best_rt, best_mt, table
+    return best, rt, mt, table
 
 
 def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):

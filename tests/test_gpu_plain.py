@@ -164,6 +164,17 @@ PARAM_SETS = [
     dict(layout=0, grid=3, unroll=1, block=64, max_height=48),
     dict(reduce_keep_mib=1, reverse_map=1),
     dict(reduce_keep_mib=4096, reverse_map=0, layout=0),
+    # tiled layout (2) and the fused combine
+    dict(layout=2, map_layout=2),
+    dict(layout=2, map_layout=2, fused_combine=1, grid=1024, map_grid=1024, block=1024, unroll=2,
+         map_block=1024, map_unroll=2, tile_log2=15),
+    dict(layout=2, map_layout=2, fused_combine=1, tile_log2=10, block=64, unroll=1, map_block=64, map_unroll=1),
+    dict(layout=2, tile_log2=22, max_height=24, grid=4),
+    dict(layout=2, map_layout=2, tile_log2=22, grid=1, map_grid=1, fused_combine=1),
+    dict(fused_combine=1),
+    dict(fused_combine=1, max_height=24, grid=4096),
+    dict(fused_combine=1, layout=0, map_layout=0, reverse_map=1),
+    dict(layout=2, map_layout=1, reduce_keep_mib=1, fused_combine=1, map_nt=0, reduce_nt=0),
 ]
 
 
@@ -251,8 +262,9 @@ def test_parameter_validation():
     ctx = api.Context()
     good = ctx.get_params()
     for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(grid=0),
-                dict(layout=2), dict(max_height=23), dict(max_height=49), dict(reverse_map=2),
-                dict(map_nt=-1)):
+                dict(layout=3), dict(map_layout=-1), dict(max_height=23), dict(max_height=49),
+                dict(reverse_map=2), dict(map_nt=-1), dict(tile_log2=9), dict(tile_log2=23),
+                dict(fused_combine=2)):
         with pytest.raises(L.NrmError):
             ctx.set_params(**bad)
         assert ctx.get_params() == good, bad
@@ -313,3 +325,42 @@ def test_unhoisted_forms_match_oracle(form, n):
     torch.cuda.synchronize()
     ref = oracle.normalize_naive(x) if form == "naive" else oracle.normalize_perblock(x, 256)
     assert_f32_close(out.cpu().numpy(), ref, what="%s n=%d" % (form, n))
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+@pytest.mark.parametrize("layout", [1, 2])
+def test_fused_combine_is_bitwise_the_ticket_combine(accum, layout):
+    """With at most 1024 reduce blocks the fused combine (every map block
+    merges the partials) uses the same fixed merge order as the last-block
+    combine: outputs and the sum are bitwise equal."""
+    bits = synth.lognormal_bf16((1 << 22) + 77, 45, 2.0)
+    inp = gpu(bits.view(np.int16)).view(torch.bfloat16)
+    outs, sums = [], []
+    for fused in (0, 1):
+        ctx = api.Context(layout=layout, map_layout=layout, grid=1000, fused_combine=fused)
+        out = torch.empty(inp.numel(), device=DEV)
+        api.normalize(out, inp, accum=accum, ctx=ctx)
+        sums.append(ctx.last_sum())
+        outs.append(out.cpu().numpy())
+        ctx.close()
+    assert sums[0] == sums[1]
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    assert_f32_close(outs[1], oracle.normalize(bits, "bf16"), what="fused " + accum)
+
+
+@pytest.mark.parametrize("in_off,out_off", [(1, 1), (3, 3), (1, 0), (0, 3)])
+def test_fused_tiled_misaligned_pointers(in_off, out_off):
+    """Offsets from 128-byte alignment with the tiled layout and the fused
+    combine (a differently aligned out falls back to the element-wise map and
+    the last-block combine)."""
+    n = 300_017
+    x = synth.lognormal_f32(n + 8, 46, 1.0)
+    base_in = gpu(x)
+    base_out = torch.zeros(n + 8, device=DEV)
+    ctx = api.Context(layout=2, map_layout=2, fused_combine=1, tile_log2=12)
+    api.normalize(base_out[out_off:out_off + n], base_in[in_off:in_off + n], ctx=ctx)
+    torch.cuda.synchronize()
+    got = base_out.cpu().numpy()
+    assert_f32_close(got[out_off:out_off + n], oracle.normalize(x[in_off:in_off + n]), what="fused misaligned")
+    assert not got[:out_off].any() and not got[out_off + n:].any()
+    ctx.close()

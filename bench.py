@@ -317,12 +317,12 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
     offs = pool.offsets(trace["n"], 8)
     ptrs = pool.pointers(trace["in_dt"], offs)
     ids = np.arange(k)
-    bp = tune.load_batch_params(args.params)
+    bp = tune.load_batch_params(args.params, workload="serve")
     warm_ns = int(warm_s * 1e9)
 
-    def run(batching, budget=64 << 30, tr=trace, pt=ptrs, n_req=None, warm_ns=warm_ns):
+    def run(batching, budget=64 << 30, tr=trace, pt=ptrs, n_req=None, warm_ns=warm_ns, spread=True):
         n_req = tr["n"].size if n_req is None else n_req
-        srv = serve.Server(slots=4, budget_bytes=budget, batching=batching, batch_params=bp)
+        srv = serve.Server(slots=4, budget_bytes=budget, batching=batching, batch_params=bp, spread=spread)
         t0 = srv.replay(np.arange(n_req), pt[:n_req], tr["n"][:n_req], tr["in_dt"][:n_req], tr["out_dt"][:n_req],
                         tr["t_ns"][:n_req])
         comps = srv.wait_all(n_req, timeout_s=600)
@@ -336,14 +336,16 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
 
     batched = run(True)
     per_req = run(False)
+    grouped = run(True, spread=False)
     stress = run(True, budget=256 << 20)
     sweep = []
     for r in (50000.0, 100000.0, 200000.0):
         tr = serve.make_trace(r, 1.2, seed=9)
         pt = pool.pointers(tr["in_dt"], pool.offsets(tr["n"], 10))
         res_b = run(True, tr=tr, pt=pt, warm_ns=int(0.2e9))
+        res_g = run(True, tr=tr, pt=pt, warm_ns=int(0.2e9), spread=False)
         res_p = run(False, tr=tr, pt=pt, warm_ns=int(0.2e9))
-        sweep.append({"offered_req_per_s": r, "batched": res_b, "per_request": res_p})
+        sweep.append({"offered_req_per_s": r, "batched": res_b, "batched_no_spread": res_g, "per_request": res_p})
     # results of a sample of requests, held and checked against the oracle
     srv = serve.Server(slots=4, hold_outputs=True, batch_params=bp)
     sel = np.arange(0, k, max(1, k // 64))[:64]
@@ -379,7 +381,8 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
                                "[2^8, 2^24], 70%% FP32 / 30%% BF16 (BF16 in and out), inputs device-resident, "
                                "64 GiB HBM admission budget, 4 slots, open-loop replay, latency from scheduled "
                                "arrival" % (rate, measure_s, warm_s), "requests": int(k)},
-        "batched": batched, "per_request_launch": per_req, "budget_256MiB": stress, "rate_sweep": sweep,
+        "batched": batched, "per_request_launch": per_req, "batched_no_spread": grouped,
+        "budget_256MiB": stress, "rate_sweep": sweep,
         "sample_max_rel_err_f32": worst, "sample_max_err_bf16_ulps": worst_bf16,
     }
     print(json.dumps(line), flush=True)

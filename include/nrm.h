@@ -123,7 +123,9 @@ typedef struct {
                           (one read, one write) */
   int32_t graph;       /* 1: capture the launch sequence once in a hipGraph and replay it */
   int32_t map_block;   /* threads per block of the divide phase: 64..1024, multiple of 64 */
-  int32_t map_grid;    /* persistent blocks of the divide phase */
+  int32_t map_grid;    /* persistent blocks G of the divide phase: the long rows' concatenation is
+                          cut into about G * m equal chunks of at most about one tile each, so
+                          that every block divides the same number of elements */
   int32_t reserved[3];
 } nrm_batch_params;
 
@@ -252,9 +254,13 @@ typedef struct {
   int32_t hold_outputs;      /* 1: outputs (and their budget) stay until nrm_server_release */
   int32_t use_batch_params;  /* 1: use batch_params for the slots, else the library defaults */
   int32_t single_plain;      /* 1: a group of one request runs the plain path (two kernels
-                                instead of the batched three); its bits then match the plain
+                                instead of the batched four); its bits then match the plain
                                 path rather than the batched one, both within the error bound */
-  int32_t pad;
+  int32_t spread;            /* 1: waiting requests are spread over the free slots, each free slot
+                                taking ceil(waiting / free slots) of them in arrival order, so that
+                                requests run alone and concurrently while slots are free and are
+                                grouped only when the queue outgrows the slots; 0: the first free
+                                slot takes all it can */
   int64_t budget_bytes;      /* HBM admission budget: input + output bytes of admitted requests */
   int64_t arena_bytes;       /* device arena for outputs (0: two thirds of the budget) */
   int64_t max_batch_rows;    /* requests per batch */

@@ -97,7 +97,7 @@ class NrmServerConfig(ctypes.Structure):
         ("hold_outputs", ctypes.c_int32),
         ("use_batch_params", ctypes.c_int32),
         ("single_plain", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("spread", ctypes.c_int32),
         ("budget_bytes", ctypes.c_int64),
         ("arena_bytes", ctypes.c_int64),
         ("max_batch_rows", ctypes.c_int64),

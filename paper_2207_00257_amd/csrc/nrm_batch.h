@@ -81,6 +81,7 @@ struct BatchArgs {
   int64_t tile;          // elements per tile of a long row
   int64_t short_max;     // rows with n <= short_max take one pass
   int64_t map_grid;      // phase 2 blocks: the chunks are sized to a multiple of it
+  int64_t min_chunk;     // elements of one full phase-2 block-iteration: the smallest chunk
 };
 
 struct BatchPlan {

@@ -99,11 +99,31 @@ __device__ __forceinline__ int64_t long_tiles(int64_t n, int64_t short_max, int6
   return n <= short_max ? 0 : (n + tile - 1) / tile;
 }
 
-// Resolve and validate row r; returns it with n = 0 if invalid.
-__device__ __forceinline__ RowDesc resolve_row(const BatchHeader* h, int64_t r, int& err) {
+// The raw description of one row: its two CSR offsets, or its table entry.
+union RawRow {
+  RowDesc d;
+  struct {
+    int64_t b, e;
+  } o;
+};
+
+// Loads only, so that several rounds' rows can be in flight at once.
+__device__ __forceinline__ RawRow fetch_row(const BatchHeader* h, int64_t r) {
+  RawRow x;
+  if (h->mode == BATCH_CSR) {
+    x.o.b = h->offsets[r];
+    x.o.e = h->offsets[r + 1];
+  } else {
+    x.d = h->table[r];
+  }
+  return x;
+}
+
+// Resolve and validate a fetched row; returns it with n = 0 if invalid.
+__device__ __forceinline__ RowDesc resolve_row(const BatchHeader* h, const RawRow& x, int& err) {
   RowDesc d;
   if (h->mode == BATCH_CSR) {
-    const int64_t b = h->offsets[r], e = h->offsets[r + 1];
+    const int64_t b = x.o.b, e = x.o.e;
     const int si = h->csr_in_dt == NRM_F32 ? 4 : 2, so = h->csr_out_dt == NRM_F32 ? 4 : 2;
     d.in = h->csr_in + b * si;
     d.out = h->csr_out + b * so;
@@ -115,7 +135,7 @@ __device__ __forceinline__ RowDesc resolve_row(const BatchHeader* h, int64_t r, 
       d.n = 0;
     }
   } else {
-    d = h->table[r];
+    d = x.d;
     if (d.n < 0 || !valid_dt(d.in_dt) || !valid_dt(d.out_dt) || (d.n > 0 && (!d.in || !d.out))) {
       err |= NRM_DEVERR_ROW;
       d.n = 0;
@@ -129,36 +149,93 @@ __device__ __forceinline__ RowDesc resolve_row(const BatchHeader* h, int64_t r, 
 constexpr int NCNT = 4;
 constexpr int PLAN_WAVES = PLAN_THREADS / 64;
 
-// Inclusive block-wide scan of the NCNT counters: a shuffle scan inside each
-// wavefront, the wavefront totals scanned by wavefront 0, two barriers.
-__device__ __forceinline__ void scan_counts(int64_t (&v)[NCNT], int64_t (*sc)[PLAN_WAVES]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Wavefront scans with DPP lane moves (a few cycles a step, no LDS):
+// row_shr by 1, 2, 4 and 8 scans each row of 16 lanes (lanes shifted in from
+// outside the row read 0); the totals of rows 0..2 (lanes 15, 31, 47) are then
+// added to the rows after them. A 64-bit value moves as two 32-bit halves.
+template <int N>
+__device__ __forceinline__ uint32_t row_shr(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x110 + N, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t row_scan32(uint32_t x) {
+  x += row_shr<1>(x);
+  x += row_shr<2>(x);
+  x += row_shr<4>(x);
+  x += row_shr<8>(x);
+  return x;
+}
+
+template <int N>
+__device__ __forceinline__ void add_shr64(uint32_t& lo, uint32_t& hi) {
+  const uint32_t slo = row_shr<N>(lo), shi = row_shr<N>(hi);
+  const uint32_t nlo = lo + slo;
+  hi = hi + shi + (nlo < lo ? 1u : 0u);
+  lo = nlo;
+}
+
+__device__ __forceinline__ uint64_t row_scan64(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  add_shr64<1>(lo, hi);
+  add_shr64<2>(lo, hi);
+  add_shr64<4>(lo, hi);
+  add_shr64<8>(lo, hi);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t lane_value64(uint64_t x, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scan over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_scan32(uint32_t x, int lane) {
+  x = row_scan32(x);
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 31);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 47);
+  if (lane >= 16) x += r0;
+  if (lane >= 32) x += r1;
+  if (lane >= 48) x += r2;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_scan64(uint64_t x, int lane) {
+  x = row_scan64(x);
+  const uint64_t r0 = lane_value64(x, 15), r1 = lane_value64(x, 31), r2 = lane_value64(x, 47);
+  if (lane >= 16) x += r0;
+  if (lane >= 32) x += r1;
+  if (lane >= 48) x += r2;
+  return x;
+}
+
+// Inclusive block-wide scan of the NCNT counters, and their block totals in
+// last. Each wavefront scans its lanes and leaves its totals in sc; after one
+// barrier every wavefront scans the PLAN_WAVES (= 16, one DPP row) totals
+// itself and adds those of the wavefronts before it. The first three
+// counters of one round fit 32 bits (at most PLAN_THREADS * MAX_ROW_TILES);
+// the element count takes 64. The caller must pass a barrier before sc is
+// written again.
+static_assert(PLAN_WAVES == 16, "the cross-wavefront scan is one DPP row");
+__device__ __forceinline__ void scan_counts(int64_t (&v)[NCNT], int64_t (&last)[NCNT], int64_t (*sc)[PLAN_WAVES]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
-  for (int k = 0; k < NCNT; ++k) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      int64_t w = __shfl_up(v[k], off, 64);
-      if (lane >= off) v[k] += w;
-    }
-  }
+  for (int k = 0; k < NCNT - 1; ++k) v[k] = (int64_t)wave_scan32((uint32_t)v[k], lane);
+  v[NCNT - 1] = (int64_t)wave_scan64((uint64_t)v[NCNT - 1], lane);
   if (lane == 63)
     for (int k = 0; k < NCNT; ++k) sc[k][wave] = v[k];
-  __syncthreads();
-  if (wave == 0) {
+  lds_barrier();
 #pragma unroll
-    for (int k = 0; k < NCNT; ++k) {
-      int64_t x = lane < PLAN_WAVES ? sc[k][lane] : 0;
-#pragma unroll
-      for (int off = 1; off < PLAN_WAVES; off <<= 1) {
-        int64_t w = __shfl_up(x, off, 64);
-        if (lane >= off) x += w;
-      }
-      if (lane < PLAN_WAVES) sc[k][lane] = x;  // inclusive totals of waves 0..lane
-    }
+  for (int k = 0; k < NCNT - 1; ++k) {
+    const uint32_t w = row_scan32(lane < PLAN_WAVES ? (uint32_t)sc[k][lane] : 0u);
+    if (wave > 0) v[k] += (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)w, wave - 1);
+    last[k] = (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)w, PLAN_WAVES - 1);
   }
-  __syncthreads();
-  if (wave > 0)
-    for (int k = 0; k < NCNT; ++k) v[k] += sc[k][wave - 1];
+  const uint64_t w = row_scan64(lane < PLAN_WAVES ? (uint64_t)sc[NCNT - 1][lane] : 0u);
+  if (wave > 0) v[NCNT - 1] += (int64_t)lane_value64(w, wave - 1);
+  last[NCNT - 1] = (int64_t)lane_value64(w, PLAN_WAVES - 1);
 }
 
 __device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int64_t tile, int64_t (&v)[NCNT]) {
@@ -168,16 +245,22 @@ __device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int64_t
   v[3] = v[0] > 0 ? n : 0;
 }
 
-// The last j in [0, PLAN_THREADS) with ex[j] <= x, for a non-decreasing ex
-// with ex[0] = 0 <= x: the thread whose range [ex[j], ex[j] + count) holds x.
-template <typename T>
-__device__ __forceinline__ int last_le(const T* ex, int64_t x) {
-  int lo = 0;
+// For each of S values x[u]: the last j in [0, PLAN_THREADS) with
+// ex[j] <= x[u], for a non-decreasing ex with ex[0] = 0 <= x[u] (the thread
+// whose range [ex[j], ex[j] + count) holds x[u]). The S binary searches are
+// interleaved so that their dependent LDS reads overlap.
+template <int S, typename T>
+__device__ __forceinline__ void last_le(const T* ex, const int64_t (&x)[S], int (&j)[S]) {
+#pragma unroll
+  for (int u = 0; u < S; ++u) j[u] = 0;
 #pragma unroll
   for (int step = PLAN_THREADS / 2; step > 0; step >>= 1)
-    if ((int64_t)ex[lo + step] <= x) lo += step;
-  return lo;
+#pragma unroll
+    for (int u = 0; u < S; ++u)
+      if ((int64_t)ex[j[u] + step] <= x[u]) j[u] += step;
 }
+
+constexpr int PLAN_SEARCHES = 4;  // binary searches in flight per thread
 
 // Rows are taken PLAN_THREADS at a time, row q * PLAN_THREADS + t in thread t
 // (coalesced reads of the offsets or of the table).
@@ -194,8 +277,9 @@ __device__ __forceinline__ int last_le(const T* ex, int64_t x) {
 //
 // Phase 2 covers the concatenation of the long rows in equal chunks, about
 // G * m of them for G phase-2 blocks (m chunks per block, each at most about
-// one tile, a multiple of 64 elements), so that every block moves the same
-// number of elements however the row lengths fall.
+// one tile, a multiple of 64 elements, at least one full block-iteration), so
+// that every block moves the same number of elements however the row lengths
+// fall.
 constexpr int PLAN_ROUNDS = 4;
 
 __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
@@ -207,7 +291,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   __shared__ int64_t ex_elem[PLAN_THREADS];
   const int t = threadIdx.x;
   if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
-  __syncthreads();
+  lds_barrier();
   const BatchHeader* h = &hs;
   const int64_t nrows = h->nrows;
   if (nrows < 0 || nrows > a.cap_rows) {
@@ -219,38 +303,50 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   }
   const int64_t rounds = (nrows + PLAN_THREADS - 1) / PLAN_THREADS;
   int err = 0;
-  // resolve row q * PLAN_THREADS + t, store it, return its length (0 if
-  // invalid or past the end)
-  auto resolve = [&](int64_t q) -> int64_t {
+  // validate row q * PLAN_THREADS + t (fetched as x) and store it; n = 0 if
+  // invalid or past the end
+  auto resolve = [&](int64_t q, const RawRow& x) -> RowDesc {
     const int64_t r = q * PLAN_THREADS + t;
-    if (r >= nrows) return 0;
-    RowDesc d = resolve_row(h, r, err);
+    RowDesc d;
+    d.n = 0;
+    if (r >= nrows) return d;
+    d = resolve_row(h, x, err);
     if (long_tiles(d.n, a.short_max, a.tile) > MAX_ROW_TILES) {
       err |= NRM_DEVERR_ROW;
       d.n = 0;
     }
     a.rows[r] = d;
-    return d.n;
+    return d;
+  };
+  auto fetch = [&](int64_t q) {
+    const int64_t r = q * PLAN_THREADS + t;
+    RawRow x;
+    if (r < nrows) x = fetch_row(h, r);
+    return x;
   };
   auto scan_round = [&](int64_t n, int64_t (&incl)[NCNT], int64_t (&last)[NCNT]) {
     row_counts(n, a.short_max, a.tile, incl);
-    scan_counts(incl, sc);
-    for (int k = 0; k < NCNT; ++k) last[k] = sc[k][PLAN_WAVES - 1];
-    __syncthreads();  // sc is rewritten by the next scan
+    scan_counts(incl, last, sc);
+    lds_barrier();  // sc is rewritten by the next scan
   };
 
-  // pass 1
+  // pass 1; the kept rounds' rows are all fetched first (one round trip)
   int64_t carry[NCNT] = {0, 0, 0, 0};
-  int64_t kn[PLAN_ROUNDS], ki3[PLAN_ROUNDS];
+  RowDesc kd[PLAN_ROUNDS];
+  int64_t ki3[PLAN_ROUNDS];
   int32_t ki0[PLAN_ROUNDS], ki1[PLAN_ROUNDS], ki2[PLAN_ROUNDS];
+  RawRow fetched[PLAN_ROUNDS];
+#pragma unroll
+  for (int q = 0; q < PLAN_ROUNDS; ++q)
+    if (q < rounds) fetched[q] = fetch(q);
 #pragma unroll
   for (int q = 0; q < PLAN_ROUNDS; ++q) {
     if (t == 0)
       for (int k = 0; k < NCNT; ++k) ks[q][k] = carry[k];
     if (q < rounds) {
       int64_t incl[NCNT], last[NCNT];
-      kn[q] = resolve(q);
-      scan_round(kn[q], incl, last);
+      kd[q] = resolve(q, fetched[q]);
+      scan_round(kd[q].n, incl, last);
       ki0[q] = (int32_t)incl[0];  // at most PLAN_THREADS * MAX_ROW_TILES
       ki1[q] = (int32_t)incl[1];
       ki2[q] = (int32_t)incl[2];
@@ -262,7 +358,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     for (int k = 0; k < NCNT; ++k) ks[PLAN_ROUNDS][k] = carry[k];
   for (int64_t q = PLAN_ROUNDS; q < rounds; ++q) {
     int64_t incl[NCNT], last[NCNT];
-    scan_round(resolve(q), incl, last);
+    scan_round(resolve(q, fetch(q)).n, incl, last);
     for (int k = 0; k < NCNT; ++k) carry[k] += last[k];
   }
   const int64_t total_long = carry[0], total = carry[0] + carry[1], n_lrows = carry[2], elems = carry[3];
@@ -275,16 +371,17 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     int64_t most = G * (m > 0 ? m : 1);
     if (most > a.cap_chunks) most = a.cap_chunks;
     chunk = (elems + most - 1) / most;
+    if (chunk < a.min_chunk) chunk = a.min_chunk;  // small batches: fewer, fully used blocks
     chunk = (chunk + 63) / 64 * 64;  // rows that start on a line keep their chunks on lines
     n_chunks = (elems + chunk - 1) / chunk;
   }
 
   // pass 2
-  auto place_round = [&](int64_t q, int64_t n, const int64_t (&incl)[NCNT], const int64_t (&c)[NCNT],
+  auto place_round = [&](int64_t q, const RowDesc& d, const int64_t (&incl)[NCNT], const int64_t (&c)[NCNT],
                          const int64_t (&last)[NCNT]) {
     const int64_t r = q * PLAN_THREADS + t;
     int64_t v[NCNT];
-    row_counts(n, a.short_max, a.tile, v);
+    row_counts(d.n, a.short_max, a.tile, v);
     ex_tile[t] = (int32_t)(incl[0] - v[0]);
     ex_lrow[t] = (int32_t)(incl[2] - v[2]);
     ex_elem[t] = incl[3] - v[3];
@@ -292,24 +389,38 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     if (v[2]) {
       const int64_t k = c[2] + incl[2] - 1;
       a.lrow_first[k] = c[0] + incl[0] - v[0];
-      a.lrows[k] = a.rows[r];  // written by this thread in pass 1
+      a.lrows[k] = d;
       a.lstart[k] = c[3] + incl[3] - v[3];
     }
-    __syncthreads();
-    for (int64_t i = t; i < last[0]; i += PLAN_THREADS) {
-      const int j = last_le(ex_tile, i);
-      a.items[c[0] + i] = Item{(int32_t)(q * PLAN_THREADS + j), (int32_t)(i - ex_tile[j])};
+    lds_barrier();
+    constexpr int SN = PLAN_SEARCHES;
+    for (int64_t i0 = t; i0 < last[0]; i0 += SN * PLAN_THREADS) {
+      int64_t x[SN];
+      int j[SN];
+#pragma unroll
+      for (int u = 0; u < SN; ++u) x[u] = i0 + u * PLAN_THREADS < last[0] ? i0 + u * PLAN_THREADS : 0;
+      last_le<SN>(ex_tile, x, j);
+#pragma unroll
+      for (int u = 0; u < SN; ++u)
+        if (i0 + u * PLAN_THREADS < last[0])
+          a.items[c[0] + x[u]] = Item{(int32_t)(q * PLAN_THREADS + j[u]), (int32_t)(x[u] - ex_tile[j[u]])};
     }
     // the chunks whose first element lies in this round's long rows
     int64_t ce = (c[3] + last[3] + chunk - 1) / chunk;
     if (ce > n_chunks) ce = n_chunks;
-    for (int64_t cc = (c[3] + chunk - 1) / chunk + t; cc < ce; cc += PLAN_THREADS) {
-      const int j = last_le(ex_elem, cc * chunk - c[3]);
-      a.chunk_lrow[cc] = (int32_t)(c[2] + ex_lrow[j]);
+    for (int64_t c0 = (c[3] + chunk - 1) / chunk + t; c0 < ce; c0 += SN * PLAN_THREADS) {
+      int64_t x[SN];
+      int j[SN];
+#pragma unroll
+      for (int u = 0; u < SN; ++u) x[u] = c0 + u * PLAN_THREADS < ce ? (c0 + u * PLAN_THREADS) * chunk - c[3] : 0;
+      last_le<SN>(ex_elem, x, j);
+#pragma unroll
+      for (int u = 0; u < SN; ++u)
+        if (c0 + u * PLAN_THREADS < ce) a.chunk_lrow[c0 + u * PLAN_THREADS] = (int32_t)(c[2] + ex_lrow[j[u]]);
     }
-    __syncthreads();  // the LDS scans are rewritten by the next round
+    lds_barrier();  // the LDS scans are rewritten by the next round
   };
-  __syncthreads();  // ks is complete
+  lds_barrier();  // ks is complete
   if (total <= a.cap_items) {
 #pragma unroll
     for (int q = 0; q < PLAN_ROUNDS; ++q) {
@@ -320,17 +431,19 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
           c[k] = ks[q][k];
           last[k] = ks[q + 1][k] - ks[q][k];
         }
-        place_round(q, kn[q], incl, c, last);
+        place_round(q, kd[q], incl, c, last);
       }
     }
     int64_t c[NCNT];
     for (int k = 0; k < NCNT; ++k) c[k] = ks[PLAN_ROUNDS][k];
     for (int64_t q = PLAN_ROUNDS; q < rounds; ++q) {
       const int64_t r = q * PLAN_THREADS + t;
-      const int64_t n = r < nrows ? a.rows[r].n : 0;  // written by this thread in pass 1
+      RowDesc d;
+      d.n = 0;
+      if (r < nrows) d = a.rows[r];  // written by this thread in pass 1
       int64_t incl[NCNT], last[NCNT];
-      scan_round(n, incl, last);
-      place_round(q, n, incl, c, last);
+      scan_round(d.n, incl, last);
+      place_round(q, d, incl, c, last);
       for (int k = 0; k < NCNT; ++k) c[k] += last[k];
     }
   }
@@ -382,7 +495,7 @@ __device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, f
   merge_chains<ACC, NA>(acc);
   Acc<ACC> tot = block_reduce<ACC>(acc[0], slots);
   if (t == 0) *s_bcast = tot.value();
-  __syncthreads();
+  lds_barrier();
   const float S = *s_bcast;
   const bool vec_ok = out_vector_ok<DTI, DTO>(d.out, g.head);
 #pragma unroll
@@ -600,7 +713,7 @@ __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
     d = d_next;
     it_next = it_after;
     item = next;
-    __syncthreads();  // the block's LDS is reused by the next item
+    lds_barrier();  // the block's LDS is reused by the next item
   }
 }
 
@@ -618,7 +731,7 @@ __global__ void __launch_bounds__(1024) batch_rowsum_kernel(BatchArgs a) {
     const int64_t count = (a.lrows[k].n + a.tile - 1) / a.tile;
     Acc<ACC> tot = combine_partials<ACC>(part + first, count, tree, tiles);
     if (threadIdx.x == 0) a.lsum[k] = tot.value();
-    __syncthreads();  // the trees are reused by the next row
+    lds_barrier();  // the trees are reused by the next row
   }
 }
 
@@ -694,9 +807,14 @@ hipError_t phase1_u(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   }
 }
 
+constexpr int64_t ROWSUM_GRID = 1024;
+
 template <int ACC>
 hipError_t rowsum_acc(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((batch_rowsum_kernel<ACC>), dim3(p.grid), dim3(64), 0, s, a);
+  // one 64-thread block per long row at a time; more blocks than this only
+  // add dispatch work for small batches
+  const int64_t grid = p.grid < ROWSUM_GRID ? p.grid : ROWSUM_GRID;
+  hipLaunchKernelGGL((batch_rowsum_kernel<ACC>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

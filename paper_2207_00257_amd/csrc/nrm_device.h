@@ -258,6 +258,17 @@ __device__ __forceinline__ void fetch(const Acc<NRM_ACC_KAHAN>* p, int64_t i, Ac
   v.lo = f32_bits((u32)(w >> 32));
 }
 
+// Block barrier for LDS traffic only. __syncthreads() is a workgroup-scope
+// release and acquire over all memory, so every wavefront first waits for its
+// own global stores to complete (vmcnt(0)) before the barrier; where the
+// block's threads communicate through LDS alone that wait is not needed, and
+// in a loop that streams stores it costs a memory round trip per barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum over the block; the result is valid in thread 0 (zero elsewhere). One
 // LDS slot per wavefront and one barrier; then thread 0 merges the wavefront
 // sums in a fixed pairwise tree. A caller that reuses `slots` must put a
@@ -268,7 +279,7 @@ __device__ __forceinline__ Acc<ACC> block_reduce(Acc<ACC> a, Acc<ACC>* slots) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
   if (lane == 0) slots[wave] = a;
-  __syncthreads();
+  lds_barrier();
   Acc<ACC> r;
   r.zero();
   if (threadIdx.x == 0) {
@@ -340,13 +351,13 @@ __device__ __forceinline__ Acc<ACC> combine_partials(const Acc<ACC>* part, int64
       if (t0 + i < count) fetch(part, t0 + i, tree[i]);
       else tree[i].zero();
     }
-    __syncthreads();
+    lds_barrier();
     for (int s = COMBINE_TILE / 2; s >= 1; s >>= 1) {
       for (int i = threadIdx.x; i < s; i += blockDim.x) tree[i].merge(tree[i + s]);
-      __syncthreads();
+      lds_barrier();
     }
     if (threadIdx.x == 0) tiles[t] = tree[0];
-    __syncthreads();
+    lds_barrier();
   }
   Acc<ACC> total;
   total.zero();

@@ -11,7 +11,7 @@
 //                  chains per thread; the chains are combined pairwise; a
 //                  wavefront reduces with DPP lane moves (no LDS, no barrier);
 //                  the wavefronts of a block meet in one LDS slot each behind
-//                  one __syncthreads (the block barrier of Fig. 1's shared-
+//                  one block barrier (the block barrier of Fig. 1's shared-
 //                  memory variant). The last block to finish (an agent-scope
 //                  ticket; partials travel by agent-scope atomic stores and
 //                  loads, coherent across the XCDs' separate L2 caches)
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(ReduceArgs a) {
     unsigned prev = __hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     is_last = prev == gridDim.x - 1;
   }
-  __syncthreads();
+  lds_barrier();
   if (!is_last) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
@@ -227,7 +227,7 @@ __device__ __forceinline__ float map_divisor(const MapArgs& a) {
       if (blockIdx.x == 0) a.sum_out[0] = v;
     }
   }
-  __syncthreads();
+  lds_barrier();
   return s_sum;
 }
 

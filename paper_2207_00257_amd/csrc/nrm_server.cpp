@@ -9,7 +9,9 @@
 //   3. launches the admitted requests as one ragged batch (row-table form)
 //      on the free slot's stream (a group of one request may take the plain
 //      two-kernel path instead), or, in per-request mode, one plain normalize
-//      call per request.
+//      call per request. With spreading, waiting requests are shared out over
+//      the free slots, so they run alone and concurrently while slots are
+//      free and are grouped only when the queue outgrows the slots.
 // Requests that arrive while batches are in flight join the next batch as
 // soon as a slot and memory free up; several slots run concurrently.
 // A replay thread can submit a whole trace at its scheduled arrival times
@@ -219,14 +221,20 @@ void nrm_server::run() {
       s.busy = false;
       progressed = true;
     }
-    // 2. admission into one free slot at a time, in arrival order
+    // 2. admission into one free slot at a time, in arrival order; spread:
+    // each free slot takes its share of the waiting requests
+    int64_t free_slots = 0;
+    for (const Slot& s : slots) free_slots += s.busy ? 0 : 1;
     for (Slot& s : slots) {
       if (s.busy) continue;
       batch.clear();
       {
         std::lock_guard<std::mutex> lk(mu);
+        int64_t share = cfg.max_batch_rows;
+        if (cfg.spread) share = std::min<int64_t>(share, ((int64_t)queue.size() + free_slots - 1) / free_slots);
+        free_slots -= 1;
         int64_t elems = 0;
-        while (!queue.empty() && (int64_t)batch.size() < cfg.max_batch_rows) {
+        while (!queue.empty() && (int64_t)batch.size() < share) {
           Pending& p = queue.front();
           const int64_t so = nrm::dtype_size(p.req.out_dtype), si = nrm::dtype_size(p.req.in_dtype);
           const int64_t need = p.req.n * (si + so);
@@ -280,6 +288,7 @@ int nrm_server_default_config(nrm_server_config* cfg) {
   cfg->graph = 1;
   cfg->accum = NRM_ACC_F32;
   cfg->single_plain = 1;
+  cfg->spread = 1;
   return NRM_OK;
 }
 
@@ -296,6 +305,7 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
   if (cfg->hold_outputs != 0 && cfg->hold_outputs != 1) return fail(NRM_EINVAL, "hold_outputs must be 0 or 1");
   if (cfg->use_batch_params != 0 && cfg->use_batch_params != 1) return fail(NRM_EINVAL, "use_batch_params must be 0 or 1");
   if (cfg->single_plain != 0 && cfg->single_plain != 1) return fail(NRM_EINVAL, "single_plain must be 0 or 1");
+  if (cfg->spread != 0 && cfg->spread != 1) return fail(NRM_EINVAL, "spread must be 0 or 1");
   if (device < 0) {
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -109,10 +109,11 @@ def test_server_config_validation_before_any_hip_call(lib):
     cfg = L.NrmServerConfig()
     assert lib.nrm_server_default_config(ctypes.byref(cfg)) == L.NRM_OK
     assert cfg.slots >= 1 and cfg.budget_bytes == 64 << 30 and cfg.batching == 1
+    assert cfg.spread == 1 and cfg.single_plain == 1
     h = ctypes.c_void_p()
     for field, bad in (("slots", 0), ("slots", 65), ("budget_bytes", 0), ("max_batch_rows", 0),
                        ("max_batch_elems", 0), ("batching", 2), ("graph", 5), ("accum", 3),
-                       ("hold_outputs", 7), ("use_batch_params", 2)):
+                       ("hold_outputs", 7), ("use_batch_params", 2), ("single_plain", 2), ("spread", -1)):
         c = L.NrmServerConfig()
         lib.nrm_server_default_config(ctypes.byref(c))
         setattr(c, field, bad)

@@ -55,8 +55,8 @@ def make_requests(count, seed, hi=1 << 18):
     return tr["n"][:k], tr["in_dt"][:k]
 
 
-@pytest.mark.parametrize("batching", [True, False])
-def test_mix_matches_oracle_and_alone(batching):
+@pytest.mark.parametrize("batching,spread", [(True, True), (True, False), (False, True)])
+def test_mix_matches_oracle_and_alone(batching, spread):
     ns, dts = make_requests(120, 5)
     pool = serve.InputPool(int(ns.max()), 7)
     offs = pool.offsets(ns, 8)
@@ -64,7 +64,8 @@ def test_mix_matches_oracle_and_alone(batching):
     ids = np.arange(ns.size)
     # groups of one run the batched kernels too, so that alone and in the mix
     # the same kernel computes each request (bitwise comparison below)
-    srv = serve.Server(slots=3, hold_outputs=True, batching=batching, max_batch_rows=32, single_plain=False)
+    srv = serve.Server(slots=3, hold_outputs=True, batching=batching, max_batch_rows=32, single_plain=False,
+                       spread=spread)
     srv.submit(ids, ptrs, ns, dts, dts)
     comps = srv.wait_all(ns.size)
     assert sorted(c[0] for c in comps) == list(ids)

@@ -2,14 +2,16 @@
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 benchmark's CPU-baseline leg, never by the product path. It shares no code
-with the HIP library. The arithmetic lives in normalize_oracle.c (plain C,
-binary64); this module only loads it with ctypes and marshals numpy arrays.
+with the HIP library. The arithmetic lives in normalize_oracle.c and
+softmax_oracle.c (plain C, binary64); this module only loads them with ctypes
+and marshals numpy arrays.
 
 Functions (all return float64 arrays):
   normalize(x)                 hoisted form: S = sum once, out = x / S
   normalize_naive(x)           Fig. 1 as printed: every thread recomputes S
   normalize_perblock(x, B)     shared-memory variant: one S per block of B
   normalize_batched(x, offs)   each CSR row [offs[r], offs[r+1]) on its own
+  softmax_batched(x, offs)     row softmax and log-sum-exp (softmax_oracle.c)
   decode(x)                    exact widening of FP32 / BF16 / FP16 storage
   round_bf16(y)                binary64 -> nearest bfloat16 (ties to even)
 
@@ -26,19 +28,22 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "normalize_oracle.c")
+_SOFTMAX_SRC = os.path.join(_HERE, "softmax_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 
 
-def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH) -> str:
+def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH, softmax_src: str = _SOFTMAX_SRC) -> str:
     """Compile the oracle with gcc: binary64 as written (no fast-math, no
-    contraction of a*b+c into fma)."""
-    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+    contraction of a*b+c into fma). src and softmax_src are the two sources
+    (a test may pass a changed copy of either)."""
+    srcs = [src, softmax_src]
+    if force or not os.path.exists(out) or os.path.getmtime(out) < max(os.path.getmtime(s) for s in srcs):
         tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-             "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, src, "-lm"])
+             "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp] + srcs + ["-lm"])
         os.replace(tmp, out)
     return out
 
@@ -55,8 +60,10 @@ def _bind(lib):
     lib.oracle_round_bf16.argtypes = [p, i64, p]
     lib.oracle_round_bf16_one.argtypes = [d]
     lib.oracle_round_bf16_one.restype = ctypes.c_uint16
+    lib.oracle_softmax_batched.argtypes = [p, p, i64, p, p]
     for name in ("oracle_decode", "oracle_normalize", "oracle_normalize_naive",
-                 "oracle_normalize_perblock", "oracle_normalize_batched", "oracle_round_bf16"):
+                 "oracle_normalize_perblock", "oracle_normalize_batched", "oracle_round_bf16",
+                 "oracle_softmax_batched"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -128,6 +135,21 @@ class Oracle:
                                                  rows, out.ctypes.data, sums.ctypes.data))
         return (out, sums[:rows]) if return_sums else out
 
+    def softmax_batched(self, x, offsets):
+        """Row softmax and log-sum-exp of a binary32 CSR batch: (out, lse)."""
+        x = _prep(x, "f32")
+        offs = np.ascontiguousarray(offsets, dtype=np.int64).reshape(-1)
+        if offs.size < 1:
+            raise ValueError("offsets needs rows + 1 >= 1 entries")
+        rows = offs.size - 1
+        if rows > 0 and offs[-1] > x.size:
+            raise ValueError("offsets run past the input")
+        out = np.full(x.size, np.nan, np.float64)
+        lse = np.empty(max(rows, 1), np.float64)
+        _check(self.lib.oracle_softmax_batched(x.ctypes.data, offs.ctypes.data, rows, out.ctypes.data,
+                                               lse.ctypes.data))
+        return out, lse[:rows]
+
     def round_bf16(self, y):
         y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
         out = np.empty(y.size, np.uint16)
@@ -170,6 +192,10 @@ def normalize_perblock(x, block, dtype="f32"):
 
 def normalize_batched(x, offsets, dtype="f32", return_sums=False):
     return _get().normalize_batched(x, offsets, dtype, return_sums)
+
+
+def softmax_batched(x, offsets):
+    return _get().softmax_batched(x, offsets)
 
 
 def round_bf16(y):

@@ -13,6 +13,8 @@ Recipes (the workloads this library is measured on):
   loguniform_lengths   integer lengths floor(exp(U[ln lo, ln(hi+1)))), clipped
   ragged_offsets       CSR offsets (int64, rows + 1) from a length vector
   poisson_arrivals     open-loop arrival times with exponential gaps
+  normal_f32           logits in[i] = fl32(sigma * N(0,1))
+  ragged_logits        a ragged batch of normal logits (the softmax workload)
 """
 from __future__ import annotations
 
@@ -35,6 +37,11 @@ def uniform_f32(n: int, seed: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarr
 def lognormal_f32(n: int, seed: int, sigma: float = 1.0) -> np.ndarray:
     g = _rng(seed).standard_normal(int(n), dtype=np.float64)
     return np.exp(sigma * g).astype(np.float32)
+
+
+def normal_f32(n: int, seed: int, sigma: float = 2.0) -> np.ndarray:
+    """Logits: fl32(sigma * N(0,1))."""
+    return (sigma * _rng(seed).standard_normal(int(n), dtype=np.float64)).astype(np.float32)
 
 
 def f32_to_bf16_bits(x: np.ndarray) -> np.ndarray:
@@ -77,6 +84,15 @@ def ragged_batch(rows: int, seed: int, lo: int = 32, hi: int = 1 << 20, sigma: f
     offs = ragged_offsets(lengths)
     vals = lognormal_f32(int(offs[-1]), seed + 1000003, sigma)
     return vals, offs
+
+
+def ragged_logits(rows: int, seed: int, lo: int = 32, hi: int = 1 << 20, sigma: float = 2.0):
+    """The softmax workload: `rows` rows with log-uniform lengths in [lo, hi]
+    (the ragged batch's lengths) and N(0, sigma^2) binary32 logits.
+    Returns (values, offsets)."""
+    lengths = loguniform_lengths(rows, seed, lo, hi)
+    offs = ragged_offsets(lengths)
+    return normal_f32(int(offs[-1]), seed + 1000003, sigma), offs
 
 
 def poisson_arrivals(rate_per_s: float, duration_s: float, seed: int) -> np.ndarray:

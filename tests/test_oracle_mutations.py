@@ -54,3 +54,45 @@ def test_mutation_is_caught(tmp_path, name):
         except AssertionError:
             failed.append(pin.__name__)
     assert failed, "planted mistake %r passed every pin" % name
+
+
+# ---- the row-softmax / log-sum-exp oracle (softmax_oracle.c) ----------------
+
+from softmax_pins import SOFTMAX_PINS  # noqa: E402
+
+SOFTMAX_SRC = os.path.join(os.path.dirname(oracle.__file__), "softmax_oracle.c")
+
+SOFTMAX_MUTATIONS = {
+    "no_max_shift": ("for (int64_t j = b; j < e; ++j) s += exp((double)x[j] - m);",
+                     "for (int64_t j = b; j < e; ++j) s += exp((double)x[j]);"),
+    "max_skips_second": ("for (int64_t j = b + 1; j < e; ++j)", "for (int64_t j = b + 2; j < e; ++j)"),
+    "sum_skips_first": ("for (int64_t j = b; j < e; ++j) s += exp", "for (int64_t j = b + 1; j < e; ++j) s += exp"),
+    "lse_without_max": ("if (lse) lse[r] = m + log(s);", "if (lse) lse[r] = log(s);"),
+    "lse_log2": ("if (lse) lse[r] = m + log(s);", "if (lse) lse[r] = m + log2(s);"),
+    "map_shifted_index": ("out[i] = exp((double)x[i] - m) / s;", "out[i] = exp((double)x[i < e - 1 ? i + 1 : i] - m) / s;"),
+    "map_sign": ("out[i] = exp((double)x[i] - m) / s;", "out[i] = exp(m - (double)x[i]) / s;"),
+    "float_accumulator": ("  double s = 0.0;\n  for (int64_t j = b; j < e; ++j) s += exp",
+                          "  float s = 0.0f;\n  for (int64_t j = b; j < e; ++j) s += exp"),
+    "row_end_short": ("const int64_t b = offsets[r], e = offsets[r + 1];",
+                      "const int64_t b = offsets[r], e = offsets[r + 1] > b ? offsets[r + 1] - 1 : b;"),
+    "empty_row_lse_zero": ("if (lse) lse[r] = -INFINITY;", "if (lse) lse[r] = 0.0;"),
+    "min_not_max": ("if ((double)x[j] > m) m = (double)x[j];", "if ((double)x[j] < m) m = (double)x[j];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SOFTMAX_MUTATIONS))
+def test_softmax_mutation_is_caught(tmp_path, name):
+    old, new = SOFTMAX_MUTATIONS[name]
+    src = open(SOFTMAX_SRC).read()
+    assert old in src, "mutation site vanished from the softmax oracle source: %s" % name
+    mutated = tmp_path / "mutated_softmax.c"
+    mutated.write_text(src.replace(old, new, 1))
+    lib = oracle.build(force=True, softmax_src=str(mutated), out=str(tmp_path / ("lib_sm_%s.so" % name)))
+    orc = oracle.Oracle(lib)
+    failed = []
+    for pin in SOFTMAX_PINS:
+        try:
+            pin(orc)
+        except (AssertionError, FloatingPointError):
+            failed.append(pin.__name__)
+    assert failed, "planted mistake %r passed every softmax pin" % name

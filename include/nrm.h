@@ -200,6 +200,37 @@ int nrm_normalize_batched_ex(nrm_ctx* ctx, void* out, int out_dtype, const void*
                              const int64_t* offsets, int64_t rows, int64_t capacity, int accum,
                              void* stream);
 
+/* Row softmax and log-sum-exp of a ragged batch, on the same planner and
+ * persistent phases as the batched normalize. Softmax is one of the
+ * aggregation kernels the paper's PyTorch integration carries (arXiv
+ * 2207.00257, Sec. V-B); it has normalize's shape (Fig. 1): a row-invariant
+ * pair is reduced once per row, then every element is mapped. For every CSR
+ * row r = [offsets[r], offsets[r+1]) of the binary32 array in:
+ *     out[i] = exp(in[i]) / sum_{j in r} exp(in[j]),
+ *     lse[r] = log(sum_{j in r} exp(in[j])).
+ * The invariant pair is a base-2 exponent k >= every in[j] log2(e) and the
+ * sum s of exp2(in[j] log2(e) - k), each term in (0, 1], reduced with exact
+ * power-of-two rescaling (no rounding added when the maximum moves); then
+ * out[i] = exp2(in[i] log2(e) - k) / s and lse[r] = (k + log2 s) ln 2.
+ *   in, out:  device binary32, `capacity` elements each (capacity < 0: read
+ *             offsets[rows] back, which synchronizes `stream`); in == out
+ *             computes in place, any other overlap is NRM_EOVERLAP.
+ *   offsets:  device int64[rows + 1]; rows outside [0, capacity) are skipped
+ *             and flagged on the device (nrm_get_device_error).
+ *   lse:      device float[rows], or NULL; empty rows get -inf. It must not
+ *             overlap in or out.
+ * Inputs are finite with |in| < 1e38. Accuracy (u = 2^-24): each output is
+ * within a relative (2|x| + |x - m| + 4) u + e_s of the exact value (x its
+ * input, m the row maximum), where e_s, the relative error of s, is at most
+ * the same quantity averaged over the row with the softmax weights plus
+ * gamma_62 (the summation tree's height bound); lse within e_s + 4 u (|lse| + 1).
+ * Outputs below 2^-125 may be flushed to zero (a term exp2(.) below 2^-126
+ * flushes, and s >= 1/2). Returns NRM_OK or an error
+ * code; the call itself is asynchronous on `stream`. ctx NULL: the default
+ * context of the current device. */
+int nrm_softmax_batched(nrm_ctx* ctx, float* out, const float* in, const int64_t* offsets, int64_t rows,
+                        int64_t capacity, float* lse, void* stream);
+
 /* Table form: `rows` is a HOST array of nrows descriptors (device data
  * pointers), copied to the device through the context's pinned staging
  * memory; rows may mix dtypes. Rows are validated on the host. The staging

@@ -138,6 +138,7 @@ def _declare(lib):
         "nrm_batch_times": (i32, [p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
         "normalize_batched": (i32, [p, p, p, i64]),
         "nrm_normalize_batched_ex": (i32, [p, p, i32, p, i32, p, i64, i64, i32, p]),
+        "nrm_softmax_batched": (i32, [p, p, p, p, i64, i64, p, p]),
         "nrm_normalize_rows": (i32, [p, ctypes.POINTER(NrmRow), i64, i32, p]),
         "nrm_batch_reserve": (i32, [p, i64, i64]),
         "nrm_default_batch_params": (i32, [ctypes.POINTER(NrmBatchParams)]),

@@ -84,6 +84,9 @@ class Context:
     def normalize_batched(self, out, inp, offsets, accum: str = "f32", stream: Optional[int] = None):
         return normalize_batched(out, inp, offsets, accum=accum, ctx=self, stream=stream)
 
+    def softmax_batched(self, out, inp, offsets, lse=None, stream: Optional[int] = None):
+        return softmax_batched(out, inp, offsets, lse=lse, ctx=self, stream=stream)
+
     def normalize_rows(self, pairs, accum: str = "f32", stream: Optional[int] = None):
         return normalize_rows(pairs, accum=accum, ctx=self, stream=stream)
 
@@ -173,6 +176,36 @@ def normalize_batched(out, inp, offsets, accum: str = "f32", ctx: Optional[Conte
                                           inp.data_ptr(), _dtype_code(inp), offsets.data_ptr(), rows,
                                           inp.numel(), _ACCUM[accum], s)
     L.check(st, "nrm_normalize_batched_ex")
+    return out
+
+
+def softmax_batched(out, inp, offsets, lse=None, ctx: Optional[Context] = None, stream: Optional[int] = None):
+    """Row softmax and log-sum-exp of a ragged batch, CSR form: row r is
+    inp[offsets[r]:offsets[r+1]]; out gets exp(x) / sum exp over the row and,
+    if given, lse[r] = log(sum exp) of the row (-inf for an empty row).
+    Binary32 device tensors; offsets: int64 device tensor of rows + 1 entries;
+    lse: float32 device tensor of rows entries, or None."""
+    import torch
+
+    _check_tensors(out, inp)
+    if inp.dtype != torch.float32 or out.dtype != torch.float32:
+        raise ValueError("softmax_batched takes float32 in and out")
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous int64 device tensor")
+    if offsets.device != inp.device:
+        raise ValueError("offsets is on another device")
+    rows = offsets.numel() - 1
+    if rows < 0:
+        raise ValueError("offsets needs rows + 1 >= 1 entries")
+    lse_ptr = None
+    if lse is not None:
+        if lse.dtype != torch.float32 or not lse.is_cuda or not lse.is_contiguous() or lse.numel() != rows:
+            raise ValueError("lse must be a contiguous float32 device tensor of rows entries")
+        lse_ptr = lse.data_ptr()
+    s = _stream_of(inp) if stream is None else stream
+    st = L.lib().nrm_softmax_batched(ctx.handle if ctx else None, out.data_ptr(), inp.data_ptr(), offsets.data_ptr(),
+                                     rows, inp.numel(), lse_ptr, s)
+    L.check(st, "nrm_softmax_batched")
     return out
 
 

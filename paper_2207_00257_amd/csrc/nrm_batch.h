@@ -34,6 +34,7 @@ struct BatchHeader {
   char* csr_out;
   int64_t capacity;        // CSR: elements addressable through csr_in / csr_out
   const RowDesc* table;    // TABLE: the row table (pinned host memory)
+  float* lse;              // softmax: each row's log-sum-exp (device), or NULL
 };
 
 // Device error bits (OR-ed by the planner, read by nrm_get_device_error).
@@ -59,7 +60,14 @@ enum {
   CNT_LONG_ELEMS = 3,  // elements in long rows: the length of phase 2's range
   CNT_CHUNK = 4,       // elements per phase-2 chunk
   CNT_CHUNKS = 5,      // phase-2 chunks
-  CNT_COUNT = 6,
+  CNT_LSE = 6,         // softmax: the header's lse pointer, for the kernels after the planner
+  CNT_COUNT = 7,
+};
+
+// One row's reduction result: the sum (a) for normalize, or the exponent and
+// the scaled sum (a = k, b = s) for softmax.
+struct RowRes {
+  float a, b;
 };
 
 // Kernel arguments: workspace pointers, fixed for a context's workspace.
@@ -70,7 +78,7 @@ struct BatchArgs {
   int64_t* lrow_first;   // [cap_rows]: first item (and partial) of each long row, in row order
   RowDesc* lrows;        // [cap_rows]: the long rows' descriptors, in row order
   int64_t* lstart;       // [cap_rows]: each long row's first position in the long rows' concatenation
-  float* lsum;           // [cap_rows]: each long row's sum (written between the phases)
+  RowRes* lsum;          // [cap_rows]: each long row's result (written between the phases)
   int32_t* chunk_lrow;   // [cap_chunks]: the long row in which each phase-2 chunk starts
   int64_t* cnt;          // [CNT_COUNT]
   int* error;            // [1]

@@ -89,6 +89,37 @@ __device__ __forceinline__ void store_quotients(char* out_seg, int64_t head, int
   }
 }
 
+// ---- the element-wise map of a row ---------------------------------------------------
+
+// normalize: x / S with the row's sum. softmax: exp2(x log2(e) - k) / s with
+// the row's exponent and scaled sum; the exponent argument is one fused
+// multiply-add (one rounding), the same expression as in the softmax chains'
+// terms. Both divisions are correctly rounded binary32.
+template <int ACC>
+struct RowMap {
+  float S;
+  __device__ __forceinline__ static RowMap of(const Acc<ACC>& acc) { return RowMap{acc.value()}; }
+  __device__ __forceinline__ static RowMap of(const RowRes& r) { return RowMap{r.a}; }
+  __device__ __forceinline__ RowRes result() const { return RowRes{S, 0.0f}; }
+  __device__ __forceinline__ float operator()(float x) const { return x / S; }
+};
+
+template <>
+struct RowMap<ACC_SOFTMAX> {
+  float k, s;
+  __device__ __forceinline__ static RowMap of(const Acc<ACC_SOFTMAX>& acc) { return RowMap{acc.k, acc.s}; }
+  __device__ __forceinline__ static RowMap of(const RowRes& r) { return RowMap{r.a, r.b}; }
+  __device__ __forceinline__ RowRes result() const { return RowRes{k, s}; }
+  __device__ __forceinline__ float operator()(float x) const {
+    return __builtin_amdgcn_exp2f(__builtin_fmaf(x, LOG2E_F, -k)) / s;
+  }
+  // log of the row's sum of exponentials: (k + log2 s) ln 2
+  __device__ __forceinline__ float lse() const { return (k + __builtin_amdgcn_logf(s)) * LN2_F; }
+};
+
+// The lse output of a softmax call (device float[rows]), or NULL.
+__device__ __forceinline__ float* lse_out(const BatchArgs& a) { return reinterpret_cast<float*>(a.cnt[CNT_LSE]); }
+
 // ---- planner ---------------------------------------------------------------------
 
 constexpr int PLAN_THREADS = 1024;
@@ -316,6 +347,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
       d.n = 0;
     }
     a.rows[r] = d;
+    if (d.n == 0 && h->lse) h->lse[r] = -__builtin_inff();  // the log of an empty sum
     return d;
   };
   auto fetch = [&](int64_t q) {
@@ -459,6 +491,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
       a.cnt[CNT_LONG_ELEMS] = elems;
       a.cnt[CNT_CHUNK] = chunk;
       a.cnt[CNT_CHUNKS] = n_chunks;
+      a.cnt[CNT_LSE] = reinterpret_cast<int64_t>(h->lse);
     }
   }
 }
@@ -466,7 +499,8 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
 // ---- single-pass rows (held in registers) --------------------------------------------
 
 template <int DTI, int DTO, int ACC, int KB>
-__device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, float* s_bcast) {
+__device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, RowRes* s_bcast, float* lse,
+                                            int64_t row) {
   constexpr int VEC = Elem<DTI>::VEC;
   constexpr int NA = accumulators(DTI, ACC, KB);
   const int B = blockDim.x, t = threadIdx.x;
@@ -494,9 +528,15 @@ __device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, f
   if (t < d.n - g.tail_begin) acc[0].add(load_one<DTI>(d.in, g.tail_begin + t));
   merge_chains<ACC, NA>(acc);
   Acc<ACC> tot = block_reduce<ACC>(acc[0], slots);
-  if (t == 0) *s_bcast = tot.value();
+  if (t == 0) {
+    const RowMap<ACC> f0 = RowMap<ACC>::of(tot);
+    *s_bcast = f0.result();
+    if constexpr (ACC == ACC_SOFTMAX) {
+      if (lse) lse[row] = f0.lse();
+    }
+  }
   lds_barrier();
-  const float S = *s_bcast;
+  const RowMap<ACC> f = RowMap<ACC>::of(*s_bcast);
   const bool vec_ok = out_vector_ok<DTI, DTO>(d.out, g.head);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
@@ -505,14 +545,14 @@ __device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, f
       float x[VEC], q[VEC];
       widen<DTI>(r[k], x);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) q[c] = x[c] / S;
+      for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
       store_quotients<DTI, DTO>(d.out, g.head, v, vec_ok, q);
     }
   }
-  if (t < g.head) store_one<DTO>(d.out, t, load_one<DTI>(d.in, t) / S);
+  if (t < g.head) store_one<DTO>(d.out, t, f(load_one<DTI>(d.in, t)));
   if (t < d.n - g.tail_begin) {
     const int64_t i = g.tail_begin + t;
-    store_one<DTO>(d.out, i, load_one<DTI>(d.in, i) / S);
+    store_one<DTO>(d.out, i, f(load_one<DTI>(d.in, i)));
   }
 }
 
@@ -565,7 +605,7 @@ __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, i
         }
       }
     }
-    if constexpr (ACC == NRM_ACC_F32) {
+    if constexpr (ACC != NRM_ACC_KAHAN) {
       if (++since_flush == FLUSH) {
         since_flush = 0;
         merge_chains<ACC, NA>(acc);
@@ -582,9 +622,9 @@ __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, i
   return block_reduce<ACC>(run, slots);
 }
 
-// out[i] = in[i] / S for elements [b, e) of a row.
-template <int DTI, int DTO, int U>
-__device__ __forceinline__ void tile_map(const RowDesc& d, int64_t b, int64_t e, float S) {
+// out[i] = f(in[i]) for elements [b, e) of a row.
+template <int DTI, int DTO, int U, class F>
+__device__ __forceinline__ void tile_map(const RowDesc& d, int64_t b, int64_t e, const F& f) {
   constexpr int VEC = Elem<DTI>::VEC;
   const char* in_seg = d.in + b * Elem<DTI>::SIZE;
   char* out_seg = d.out + b * Elem<DTO>::SIZE;
@@ -609,7 +649,7 @@ __device__ __forceinline__ void tile_map(const RowDesc& d, int64_t b, int64_t e,
         float x[VEC], q[VEC];
         widen<DTI>(r[u], x);
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) q[c] = x[c] / S;
+        for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
         store_quotients<DTI, DTO>(out_seg, g.head, v0 + u * B, vec_ok, q);
       }
     } else {
@@ -619,70 +659,85 @@ __device__ __forceinline__ void tile_map(const RowDesc& d, int64_t b, int64_t e,
           float x[VEC], q[VEC];
           widen<DTI>(load_vec<true>(body + v0 + u * B), x);
 #pragma unroll
-          for (int c = 0; c < VEC; ++c) q[c] = x[c] / S;
+          for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
           store_quotients<DTI, DTO>(out_seg, g.head, v0 + u * B, vec_ok, q);
         }
       }
     }
   }
-  if (has_head) store_one<DTO>(out_seg, threadIdx.x, xh / S);
-  if (has_tail) store_one<DTO>(out_seg, ti, xt / S);
+  if (has_head) store_one<DTO>(out_seg, threadIdx.x, f(xh));
+  if (has_tail) store_one<DTO>(out_seg, ti, f(xt));
 }
 
 // ---- dtype dispatch of one item --------------------------------------------------------
+// The softmax kind is binary32 in and out only (the host rejects anything else).
 
 template <int ACC, int KB>
-__device__ __forceinline__ void dispatch_single(const RowDesc& d, Acc<ACC>* slots, float* s_bcast) {
-#define NRM_SP(I, O) single_pass<I, O, ACC, KB>(d, slots, s_bcast)
-  switch (d.in_dt * 3 + d.out_dt) {
-    case NRM_F32 * 3 + NRM_F32: NRM_SP(NRM_F32, NRM_F32); break;
-    case NRM_F32 * 3 + NRM_BF16: NRM_SP(NRM_F32, NRM_BF16); break;
-    case NRM_F32 * 3 + NRM_F16: NRM_SP(NRM_F32, NRM_F16); break;
-    case NRM_BF16 * 3 + NRM_F32: NRM_SP(NRM_BF16, NRM_F32); break;
-    case NRM_BF16 * 3 + NRM_BF16: NRM_SP(NRM_BF16, NRM_BF16); break;
-    case NRM_BF16 * 3 + NRM_F16: NRM_SP(NRM_BF16, NRM_F16); break;
-    case NRM_F16 * 3 + NRM_F32: NRM_SP(NRM_F16, NRM_F32); break;
-    case NRM_F16 * 3 + NRM_BF16: NRM_SP(NRM_F16, NRM_BF16); break;
-    default: NRM_SP(NRM_F16, NRM_F16); break;
-  }
+__device__ __forceinline__ void dispatch_single(const RowDesc& d, Acc<ACC>* slots, RowRes* s_bcast, float* lse,
+                                                int64_t row) {
+  if constexpr (ACC == ACC_SOFTMAX) {
+    single_pass<NRM_F32, NRM_F32, ACC, KB>(d, slots, s_bcast, lse, row);
+  } else {
+#define NRM_SP(I, O) single_pass<I, O, ACC, KB>(d, slots, s_bcast, lse, row)
+    switch (d.in_dt * 3 + d.out_dt) {
+      case NRM_F32 * 3 + NRM_F32: NRM_SP(NRM_F32, NRM_F32); break;
+      case NRM_F32 * 3 + NRM_BF16: NRM_SP(NRM_F32, NRM_BF16); break;
+      case NRM_F32 * 3 + NRM_F16: NRM_SP(NRM_F32, NRM_F16); break;
+      case NRM_BF16 * 3 + NRM_F32: NRM_SP(NRM_BF16, NRM_F32); break;
+      case NRM_BF16 * 3 + NRM_BF16: NRM_SP(NRM_BF16, NRM_BF16); break;
+      case NRM_BF16 * 3 + NRM_F16: NRM_SP(NRM_BF16, NRM_F16); break;
+      case NRM_F16 * 3 + NRM_F32: NRM_SP(NRM_F16, NRM_F32); break;
+      case NRM_F16 * 3 + NRM_BF16: NRM_SP(NRM_F16, NRM_BF16); break;
+      default: NRM_SP(NRM_F16, NRM_F16); break;
+    }
 #undef NRM_SP
+  }
 }
 
 template <int ACC, int U>
 __device__ __forceinline__ Acc<ACC> dispatch_tile_reduce(const RowDesc& d, int64_t b, int64_t e,
                                                          Acc<ACC>* slots) {
-  switch (d.in_dt) {
-    case NRM_F32: return tile_reduce<NRM_F32, ACC, U>(d.in, b, e, slots);
-    case NRM_BF16: return tile_reduce<NRM_BF16, ACC, U>(d.in, b, e, slots);
-    default: return tile_reduce<NRM_F16, ACC, U>(d.in, b, e, slots);
+  if constexpr (ACC == ACC_SOFTMAX) {
+    return tile_reduce<NRM_F32, ACC, U>(d.in, b, e, slots);
+  } else {
+    switch (d.in_dt) {
+      case NRM_F32: return tile_reduce<NRM_F32, ACC, U>(d.in, b, e, slots);
+      case NRM_BF16: return tile_reduce<NRM_BF16, ACC, U>(d.in, b, e, slots);
+      default: return tile_reduce<NRM_F16, ACC, U>(d.in, b, e, slots);
+    }
   }
 }
 
-template <int U>
-__device__ __forceinline__ void dispatch_tile_map(const RowDesc& d, int64_t b, int64_t e, float S) {
-#define NRM_TM(I, O) tile_map<I, O, U>(d, b, e, S)
-  switch (d.in_dt * 3 + d.out_dt) {
-    case NRM_F32 * 3 + NRM_F32: NRM_TM(NRM_F32, NRM_F32); break;
-    case NRM_F32 * 3 + NRM_BF16: NRM_TM(NRM_F32, NRM_BF16); break;
-    case NRM_F32 * 3 + NRM_F16: NRM_TM(NRM_F32, NRM_F16); break;
-    case NRM_BF16 * 3 + NRM_F32: NRM_TM(NRM_BF16, NRM_F32); break;
-    case NRM_BF16 * 3 + NRM_BF16: NRM_TM(NRM_BF16, NRM_BF16); break;
-    case NRM_BF16 * 3 + NRM_F16: NRM_TM(NRM_BF16, NRM_F16); break;
-    case NRM_F16 * 3 + NRM_F32: NRM_TM(NRM_F16, NRM_F32); break;
-    case NRM_F16 * 3 + NRM_BF16: NRM_TM(NRM_F16, NRM_BF16); break;
-    default: NRM_TM(NRM_F16, NRM_F16); break;
-  }
+template <int ACC, int U>
+__device__ __forceinline__ void dispatch_tile_map(const RowDesc& d, int64_t b, int64_t e, const RowMap<ACC>& f) {
+  if constexpr (ACC == ACC_SOFTMAX) {
+    tile_map<NRM_F32, NRM_F32, U>(d, b, e, f);
+  } else {
+#define NRM_TM(I, O) tile_map<I, O, U>(d, b, e, f)
+    switch (d.in_dt * 3 + d.out_dt) {
+      case NRM_F32 * 3 + NRM_F32: NRM_TM(NRM_F32, NRM_F32); break;
+      case NRM_F32 * 3 + NRM_BF16: NRM_TM(NRM_F32, NRM_BF16); break;
+      case NRM_F32 * 3 + NRM_F16: NRM_TM(NRM_F32, NRM_F16); break;
+      case NRM_BF16 * 3 + NRM_F32: NRM_TM(NRM_BF16, NRM_F32); break;
+      case NRM_BF16 * 3 + NRM_BF16: NRM_TM(NRM_BF16, NRM_BF16); break;
+      case NRM_BF16 * 3 + NRM_F16: NRM_TM(NRM_BF16, NRM_F16); break;
+      case NRM_F16 * 3 + NRM_F32: NRM_TM(NRM_F16, NRM_F32); break;
+      case NRM_F16 * 3 + NRM_BF16: NRM_TM(NRM_F16, NRM_BF16); break;
+      default: NRM_TM(NRM_F16, NRM_F16); break;
+    }
 #undef NRM_TM
+  }
 }
 
-// ---- the two persistent phases ------------------------------------------------------------
+// ---- the persistent phases ------------------------------------------------------------------
 
 template <int ACC, int U, int KB>
 __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
   __shared__ Acc<ACC> slots[MAX_WAVES];
-  __shared__ float s_bcast;
+  __shared__ RowRes s_bcast;
   const int64_t n_items = a.cnt[CNT_ITEMS];
   const int64_t n_long = a.cnt[CNT_LONG_ITEMS];
+  float* lse = lse_out(a);
   Acc<ACC>* part = reinterpret_cast<Acc<ACC>*>(a.partials);
   const int64_t G = gridDim.x;
   int64_t item = blockIdx.x;
@@ -701,7 +756,7 @@ __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
       if (next + G < n_items) it_after = a.items[next + G];
     }
     if (item >= n_long) {
-      dispatch_single<ACC, KB>(d, slots, &s_bcast);
+      dispatch_single<ACC, KB>(d, slots, &s_bcast, lse, it.row);
     } else {
       const int64_t b = (int64_t)it.tile * a.tile;
       const int64_t e = b + a.tile < d.n ? b + a.tile : d.n;
@@ -717,20 +772,27 @@ __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
   }
 }
 
-// Each long row's sum from its tile partials, in a fixed order that depends
-// only on the number of tiles (combine_partials: one wavefront for up to 1024
-// partials, the LDS tree beyond). One block per long row at a time.
+// Each long row's result from its tile partials, in a fixed order that
+// depends only on the number of tiles (combine_partials: one wavefront for up
+// to 1024 partials, the LDS tree beyond). One block per long row at a time.
 template <int ACC>
 __global__ void __launch_bounds__(1024) batch_rowsum_kernel(BatchArgs a) {
   __shared__ Acc<ACC> tree[COMBINE_TILE];
   __shared__ Acc<ACC> tiles[MAX_COMBINE_TILES];
   const int64_t n_lrows = a.cnt[CNT_LONG_ROWS];
+  float* lse = lse_out(a);
   const Acc<ACC>* part = reinterpret_cast<const Acc<ACC>*>(a.partials);
   for (int64_t k = blockIdx.x; k < n_lrows; k += gridDim.x) {
     const int64_t first = a.lrow_first[k];
     const int64_t count = (a.lrows[k].n + a.tile - 1) / a.tile;
     Acc<ACC> tot = combine_partials<ACC>(part + first, count, tree, tiles);
-    if (threadIdx.x == 0) a.lsum[k] = tot.value();
+    if (threadIdx.x == 0) {
+      const RowMap<ACC> f = RowMap<ACC>::of(tot);
+      a.lsum[k] = f.result();
+      if constexpr (ACC == ACC_SOFTMAX) {
+        if (lse) lse[a.items[first].row] = f.lse();
+      }
+    }
     lds_barrier();  // the trees are reused by the next row
   }
 }
@@ -739,7 +801,7 @@ __global__ void __launch_bounds__(1024) batch_rowsum_kernel(BatchArgs a) {
 // positions [c * chunk, (c + 1) * chunk) and starts in long row
 // chunk_lrow[c]; a chunk that reaches past its row's end continues in the
 // following long rows.
-template <int U>
+template <int ACC, int U>
 __global__ void __launch_bounds__(1024) batch_phase2_kernel(BatchArgs a) {
   const int64_t elems = a.cnt[CNT_LONG_ELEMS], chunk = a.cnt[CNT_CHUNK], n_chunks = a.cnt[CNT_CHUNKS];
   const int64_t G = gridDim.x;
@@ -748,7 +810,7 @@ __global__ void __launch_bounds__(1024) batch_phase2_kernel(BatchArgs a) {
   int64_t k = a.chunk_lrow[c];
   RowDesc d = a.lrows[k];
   int64_t start = a.lstart[k];
-  float S = a.lsum[k];
+  RowRes R = a.lsum[k];
   int64_t k_next = c + G < n_chunks ? a.chunk_lrow[c + G] : k;
   while (true) {
     // Two deep, as in phase 1: the next chunk's row (its index is already
@@ -756,32 +818,32 @@ __global__ void __launch_bounds__(1024) batch_phase2_kernel(BatchArgs a) {
     const int64_t next = c + G;
     RowDesc d_next = d;
     int64_t start_next = start;
-    float S_next = S;
+    RowRes R_next = R;
     int64_t k_after = k_next;
     if (next < n_chunks) {
       d_next = a.lrows[k_next];
       start_next = a.lstart[k_next];
-      S_next = a.lsum[k_next];
+      R_next = a.lsum[k_next];
       if (next + G < n_chunks) k_after = a.chunk_lrow[next + G];
     }
     int64_t pos = c * chunk;
     const int64_t end = pos + chunk < elems ? pos + chunk : elems;
     while (true) {
       const int64_t e = end - start < d.n ? end - start : d.n;
-      dispatch_tile_map<U>(d, pos - start, e, S);
+      dispatch_tile_map<ACC, U>(d, pos - start, e, RowMap<ACC>::of(R));
       pos = start + e;
       if (pos >= end) break;
       ++k;  // the chunk continues in the next long row
       d = a.lrows[k];
       start = a.lstart[k];
-      S = a.lsum[k];
+      R = a.lsum[k];
     }
     if (next >= n_chunks) break;
     c = next;
     k = k_next;
     d = d_next;
     start = start_next;
-    S = S_next;
+    R = R_next;
     k_next = k_after;
   }
 }
@@ -818,14 +880,24 @@ hipError_t rowsum_acc(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t phase2(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
+template <int ACC>
+hipError_t phase2_acc(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   switch (p.map_unroll) {
-    case 1: hipLaunchKernelGGL((batch_phase2_kernel<1>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((batch_phase2_kernel<2>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((batch_phase2_kernel<4>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
-    default: hipLaunchKernelGGL((batch_phase2_kernel<8>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 1>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 2>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 4>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
+    default: hipLaunchKernelGGL((batch_phase2_kernel<ACC, 8>), dim3(p.map_grid), dim3(p.map_block), 0, s, a); break;
   }
   return hipGetLastError();
+}
+
+template <int ACC>
+hipError_t launch_phases(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
+  hipError_t e = phase1_u<ACC>(p, a, s);
+  if (e != hipSuccess) return e;
+  e = rowsum_acc<ACC>(p, a, s);
+  if (e != hipSuccess) return e;
+  return phase2_acc<ACC>(p, a, s);
 }
 
 }  // namespace
@@ -834,11 +906,11 @@ hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(PLAN_THREADS), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = p.acc == NRM_ACC_KAHAN ? phase1_u<NRM_ACC_KAHAN>(p, a, s) : phase1_u<NRM_ACC_F32>(p, a, s);
-  if (e != hipSuccess) return e;
-  e = p.acc == NRM_ACC_KAHAN ? rowsum_acc<NRM_ACC_KAHAN>(p, a, s) : rowsum_acc<NRM_ACC_F32>(p, a, s);
-  if (e != hipSuccess) return e;
-  return phase2(p, a, s);
+  switch (p.acc) {
+    case NRM_ACC_KAHAN: return launch_phases<NRM_ACC_KAHAN>(p, a, s);
+    case ACC_SOFTMAX: return launch_phases<ACC_SOFTMAX>(p, a, s);
+    default: return launch_phases<NRM_ACC_F32>(p, a, s);
+  }
 }
 
 }  // namespace nrm

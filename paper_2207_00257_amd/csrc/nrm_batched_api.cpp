@@ -76,10 +76,13 @@ int check_batch_params(const nrm_batch_params& p) {
 
 int64_t short_max_of(const nrm_batch_params& p) { return (int64_t)p.block * p.short_regs * 4; }
 
+bool any_graph(const BatchWorkspace& w) { return w.graph[0] || w.graph[1] || w.graph[2]; }
+
 void destroy_graph(BatchWorkspace& w) {
-  if (w.graph) hipGraphExecDestroy(w.graph);
-  w.graph = nullptr;
-  w.graph_acc = -1;
+  for (hipGraphExec_t& g : w.graph) {
+    if (g) hipGraphExecDestroy(g);
+    g = nullptr;
+  }
 }
 
 // Layout of the single device allocation.
@@ -104,7 +107,7 @@ Layout layout_for(int64_t cap_rows, int64_t cap_items, int64_t cap_chunks) {
   L.lrow_first = take(sizeof(int64_t) * cap_rows);
   L.lrows = take(sizeof(RowDesc) * cap_rows);
   L.lstart = take(sizeof(int64_t) * cap_rows);
-  L.lsum = take(sizeof(float) * cap_rows);
+  L.lsum = take(sizeof(nrm::RowRes) * cap_rows);
   L.chunk_lrow = take(sizeof(int32_t) * cap_chunks);
   L.small = take(kSmallBytes);  // the planner's counters, then the error word
   L.partials = take(8 * cap_items);
@@ -158,7 +161,7 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   w.lrow_first = reinterpret_cast<int64_t*>(d + L.lrow_first);
   w.lrows = reinterpret_cast<RowDesc*>(d + L.lrows);
   w.lstart = reinterpret_cast<int64_t*>(d + L.lstart);
-  w.lsum = reinterpret_cast<float*>(d + L.lsum);
+  w.lsum = reinterpret_cast<nrm::RowRes*>(d + L.lsum);
   w.chunk_lrow = reinterpret_cast<int32_t*>(d + L.chunk_lrow);
   w.cnt = reinterpret_cast<int64_t*>(d + L.small);
   w.error = reinterpret_cast<int*>(d + L.small + kErrorOffset);
@@ -221,7 +224,8 @@ BatchPlan plan_of(const nrm_ctx* c, int acc) {
 
 int capture_graph(nrm_ctx* c, int acc) {
   BatchWorkspace& w = c->batch;
-  destroy_graph(w);
+  if (w.graph[acc]) hipGraphExecDestroy(w.graph[acc]);
+  w.graph[acc] = nullptr;
   hipError_t e;
   if (!w.capture_stream) {
     e = hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking);
@@ -234,13 +238,12 @@ int capture_graph(nrm_ctx* c, int acc) {
   e = hipStreamEndCapture(w.capture_stream, &graph);
   if (e2 != hipSuccess) return hip_fail(e2, "batched launch (capture)");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&w.graph, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&w.graph[acc], graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    w.graph = nullptr;
+    w.graph[acc] = nullptr;
     return hip_fail(e, "hipGraphInstantiate");
   }
-  w.graph_acc = acc;
   return NRM_OK;
 }
 
@@ -265,11 +268,11 @@ int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nr
     hipEventRecord(ev[0], s);
   }
   if (c->bparams.graph) {
-    if (!w.graph || w.graph_acc != acc) {
+    if (!w.graph[acc]) {
       int st = capture_graph(c, acc);
       if (st != NRM_OK) return st;
     }
-    e = hipGraphLaunch(w.graph, s);
+    e = hipGraphLaunch(w.graph[acc], s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   } else {
     e = nrm::launch_batch(plan_of(c, acc), args_of(c), s);
@@ -313,7 +316,7 @@ int nrm_set_batch_params(nrm_ctx* c, const nrm_batch_params* params) {
   if (st != NRM_OK) return st;
   if (std::memcmp(params, &c->bparams, sizeof(*params)) != 0) {
     DeviceGuard g(c->device);
-    if (c->batch.graph) {
+    if (any_graph(c->batch)) {
       hipDeviceSynchronize();
       destroy_graph(c->batch);
     }
@@ -351,18 +354,34 @@ int check_csr_buffers(const void* out, int out_dtype, const void* in, int in_dty
 }
 }  // namespace
 
-int nrm_normalize_batched_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype,
-                             const int64_t* offsets, int64_t rows, int64_t capacity, int accum,
-                             void* stream) {
+namespace {
+// lse[rows] must not overlap in or out (capacity elements each).
+int check_lse(const void* out, int out_dtype, const void* in, int in_dtype, int64_t capacity, const float* lse,
+              int64_t rows) {
+  const int64_t si = nrm::dtype_size(in_dtype), so = nrm::dtype_size(out_dtype);
+  const uintptr_t l0 = (uintptr_t)lse, l1 = l0 + (uintptr_t)(rows * (int64_t)sizeof(float));
+  const uintptr_t a0 = (uintptr_t)in, a1 = a0 + (uintptr_t)(capacity * si);
+  const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (uintptr_t)(capacity * so);
+  if ((l0 < a1 && a0 < l1) || (l0 < b1 && b0 < l1)) return fail(NRM_EOVERLAP, "lse overlaps in or out");
+  return NRM_OK;
+}
+
+// The CSR form of both operations: validation before any HIP call, the
+// capacity read from offsets[rows] when not given, then one batched run of
+// the reduction kind `acc` (with lse written for softmax when non-NULL).
+int run_csr(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype, const int64_t* offsets,
+            int64_t rows, int64_t capacity, int acc, float* lse, void* stream) {
   if (rows < 0) return fail(NRM_EINVAL, "rows < 0");
   if (!valid_dtype(in_dtype) || !valid_dtype(out_dtype)) return fail(NRM_EINVAL, "unknown dtype");
-  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
   if (rows == 0) return NRM_OK;
   if (rows > INT32_MAX) return fail(NRM_EINVAL, "more than 2^31 - 1 rows");
   if (!offsets) return fail(NRM_EINVAL, "offsets is NULL");
-  if (capacity == 0) return NRM_OK;  // every row is empty (or invalid)
+  if (lse && (reinterpret_cast<uintptr_t>(lse) % sizeof(float)))
+    return fail(NRM_EINVAL, "lse is not aligned to 4 bytes");
+  if (capacity == 0 && !lse) return NRM_OK;  // every row is empty (or invalid)
   if (capacity > 0) {
     int st = check_csr_buffers(out, out_dtype, in, in_dtype, capacity);
+    if (st == NRM_OK && lse) st = check_lse(out, out_dtype, in, in_dtype, capacity, lse, rows);
     if (st != NRM_OK) return st;
   }
   if (!c) {
@@ -376,9 +395,15 @@ int nrm_normalize_batched_ex(nrm_ctx* c, void* out, int out_dtype, const void* i
     hipError_t e = hipMemcpyAsync(&last, offsets + rows, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "reading offsets[rows]");
-    if (last <= 0) return NRM_OK;
-    capacity = last;
-    int st = check_csr_buffers(out, out_dtype, in, in_dtype, capacity);
+    if (last <= 0 && !lse) return NRM_OK;
+    capacity = last > 0 ? last : 0;
+    if (capacity > 0) {
+      int st = check_csr_buffers(out, out_dtype, in, in_dtype, capacity);
+      if (st != NRM_OK) return st;
+    }
+  }
+  if (lse && capacity > 0) {
+    int st = check_lse(out, out_dtype, in, in_dtype, capacity, lse, rows);
     if (st != NRM_OK) return st;
   }
   int st = reserve(c, rows, items_bound(c->bparams, rows, capacity));
@@ -393,7 +418,21 @@ int nrm_normalize_batched_ex(nrm_ctx* c, void* out, int out_dtype, const void* i
   h.csr_in = static_cast<const char*>(in);
   h.csr_out = static_cast<char*>(out);
   h.capacity = capacity;
-  return run_batch(c, h, nullptr, rows, accum, s);
+  h.lse = lse;
+  return run_batch(c, h, nullptr, rows, acc, s);
+}
+}  // namespace
+
+int nrm_normalize_batched_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype,
+                             const int64_t* offsets, int64_t rows, int64_t capacity, int accum,
+                             void* stream) {
+  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
+  return run_csr(c, out, out_dtype, in, in_dtype, offsets, rows, capacity, accum, nullptr, stream);
+}
+
+int nrm_softmax_batched(nrm_ctx* c, float* out, const float* in, const int64_t* offsets, int64_t rows,
+                        int64_t capacity, float* lse, void* stream) {
+  return run_csr(c, out, NRM_F32, in, NRM_F32, offsets, rows, capacity, nrm::ACC_SOFTMAX, lse, stream);
 }
 
 int normalize_batched(float* out, const float* in, const int64_t* offsets, int64_t rows) {

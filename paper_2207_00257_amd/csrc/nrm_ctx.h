@@ -55,7 +55,7 @@ struct BatchWorkspace {
   int64_t* lrow_first = nullptr;
   RowDesc* lrows = nullptr;
   int64_t* lstart = nullptr;
-  float* lsum = nullptr;
+  RowRes* lsum = nullptr;
   int32_t* chunk_lrow = nullptr;
   int64_t* cnt = nullptr;
   int* error = nullptr;
@@ -64,9 +64,8 @@ struct BatchWorkspace {
   hipEvent_t staged = nullptr; // recorded once the staging buffer may be rewritten
   bool staged_pending = false;
   // captured launch sequence
-  hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};  // one per reduction kind (plain, compensated, softmax)
   hipStream_t capture_stream = nullptr;
-  int graph_acc = -1;
   // timing ring of (before, after) event pairs
   std::vector<hipEvent_t> events;
   int64_t timed_calls = 0;

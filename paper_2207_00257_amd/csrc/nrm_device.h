@@ -181,6 +181,45 @@ struct Acc<NRM_ACC_KAHAN> {
   __device__ __forceinline__ float value() const { return hi + lo; }
 };
 
+// Row softmax (an internal accumulation kind next to the two public modes):
+// a base-2 exponent k (an integer held in binary32) and the sum s of
+// exp2(x * log2(e) - k) over the elements seen, with k >= every x * log2(e)
+// so that each term is in (0, 1]. When an element exceeds k, k moves up to
+// the next integer and s is rescaled by an exact power of two; merging two
+// chains rescales both to the larger k the same way. Rescaling therefore
+// adds no rounding: s stays a plain sum of positive terms, with the same
+// error bound as a plain binary32 sum of its summation tree's height. Then
+// softmax_i = exp2(x_i log2(e) - k) / s and lse = (k + log2 s) ln 2.
+constexpr float LOG2E_F = 1.44269504088896340736f;  // log2(e), rounded to binary32
+constexpr float LN2_F = 0.693147180559945309417f;   // ln(2), rounded to binary32
+constexpr float K_NONE = -1.0e30f;                  // k of an empty chain
+
+// s * 2^d for an integer-valued d <= 0 (exact unless the result leaves the
+// normal range); d below -256 gives 0.
+__device__ __forceinline__ float scale_pow2(float s, float d) {
+  return __builtin_amdgcn_ldexpf(s, (int)fmaxf(d, -256.0f));
+}
+
+template <>
+struct Acc<ACC_SOFTMAX> {
+  float k, s;
+  __device__ __forceinline__ void zero() { k = K_NONE; s = 0.0f; }
+  __device__ __forceinline__ void add(float x) {
+    const float y = x * LOG2E_F;
+    if (y > k) {
+      const float kn = __builtin_ceilf(y);
+      s = scale_pow2(s, k - kn);
+      k = kn;
+    }
+    s += __builtin_amdgcn_exp2f(__builtin_fmaf(x, LOG2E_F, -k));  // one rounding in the argument
+  }
+  __device__ __forceinline__ void merge(const Acc& o) {
+    const float kn = fmaxf(k, o.k);
+    s = scale_pow2(s, k - kn) + scale_pow2(o.s, o.k - kn);
+    k = kn;
+  }
+};
+
 // ---- wavefront and block reduction ------------------------------------------
 
 template <int CTRL>
@@ -212,6 +251,23 @@ __device__ __forceinline__ Acc<ACC> wave_reduce(Acc<ACC> a) {
     Acc<ACC> r;
     r.s = (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
     return r;
+  } else if constexpr (ACC == ACC_SOFTMAX) {
+    // the merge is symmetric in its operands (a maximum and a sum of two
+    // exactly rescaled terms), so partner lanes again hold identical bits
+    Acc<ACC> o;
+    o.k = dpp<QP_SWAP1>(a.k); o.s = dpp<QP_SWAP1>(a.s); a.merge(o);
+    o.k = dpp<QP_SWAP2>(a.k); o.s = dpp<QP_SWAP2>(a.s); a.merge(o);
+    o.k = dpp<ROW_HALF_MIRROR>(a.k); o.s = dpp<ROW_HALF_MIRROR>(a.s); a.merge(o);
+    o.k = dpp<ROW_MIRROR>(a.k); o.s = dpp<ROW_MIRROR>(a.s); a.merge(o);
+    Acc<ACC> r0, r1, r2, r3;
+    r0.k = readlane(a.k, 0); r0.s = readlane(a.s, 0);
+    r1.k = readlane(a.k, 16); r1.s = readlane(a.s, 16);
+    r2.k = readlane(a.k, 32); r2.s = readlane(a.s, 32);
+    r3.k = readlane(a.k, 48); r3.s = readlane(a.s, 48);
+    r0.merge(r1);
+    r2.merge(r3);
+    r0.merge(r2);
+    return r0;
   } else {
     // TwoSum-based merge is symmetric in its operands (both the sum and the
     // exact error term are), so partner lanes again hold identical bits.
@@ -247,6 +303,11 @@ __device__ __forceinline__ void publish(Acc<NRM_ACC_KAHAN>* p, int64_t i, const 
   __hip_atomic_store(reinterpret_cast<unsigned long long*>(p) + i, w, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void publish(Acc<ACC_SOFTMAX>* p, int64_t i, const Acc<ACC_SOFTMAX>& v) {
+  unsigned long long w = (unsigned long long)bits_f32(v.k) | ((unsigned long long)bits_f32(v.s) << 32);
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p) + i, w, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void fetch(const Acc<NRM_ACC_F32>* p, int64_t i, Acc<NRM_ACC_F32>& v) {
   v.s = f32_bits(__hip_atomic_load(reinterpret_cast<const u32*>(p) + i,
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -256,6 +317,12 @@ __device__ __forceinline__ void fetch(const Acc<NRM_ACC_KAHAN>* p, int64_t i, Ac
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   v.hi = f32_bits((u32)w);
   v.lo = f32_bits((u32)(w >> 32));
+}
+__device__ __forceinline__ void fetch(const Acc<ACC_SOFTMAX>* p, int64_t i, Acc<ACC_SOFTMAX>& v) {
+  unsigned long long w = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p) + i,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v.k = f32_bits((u32)w);
+  v.s = f32_bits((u32)(w >> 32));
 }
 
 // Block barrier for LDS traffic only. __syncthreads() is a workgroup-scope

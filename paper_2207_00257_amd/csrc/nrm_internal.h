@@ -9,6 +9,10 @@
 
 namespace nrm {
 
+// Reduction kinds of the batched kernels: the two public accumulation modes
+// (nrm_accum) and the row softmax's (exponent, scaled sum) pairs.
+constexpr int ACC_SOFTMAX = 2;
+
 // Element sizes of the storage dtypes (nrm_dtype order: F32, BF16, F16).
 inline int dtype_size(int dt) { return dt == NRM_F32 ? 4 : 2; }
 // Elements per 16-byte vector.
@@ -16,11 +20,12 @@ inline int dtype_vec(int dt) { return 16 / dtype_size(dt); }
 
 // Independent accumulator chains per thread in the reduce kernel: one per
 // element of the U vectors a thread loads per iteration, capped so that the
-// chains stay in registers (32 plain, 16 compensated pairs).
+// chains stay in registers (32 plain; 16 for the two-float chains:
+// compensated pairs, and the softmax kind's exponent and sum).
 __host__ __device__ constexpr int accumulators(int dt, int acc, int unroll) {
-  return (unroll * (16 / (dt == NRM_F32 ? 4 : 2))) < (acc == NRM_ACC_KAHAN ? 16 : 32)
+  return (unroll * (16 / (dt == NRM_F32 ? 4 : 2))) < (acc == NRM_ACC_F32 ? 32 : 16)
              ? unroll * (16 / (dt == NRM_F32 ? 4 : 2))
-             : (acc == NRM_ACC_KAHAN ? 16 : 32);
+             : (acc == NRM_ACC_F32 ? 32 : 16);
 }
 // Additions each chain receives per loop iteration.
 __host__ __device__ constexpr int adds_per_iteration(int dt, int acc, int unroll) {

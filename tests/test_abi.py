@@ -84,6 +84,16 @@ def test_batched_host_validation_before_any_hip_call(lib):
     assert ex(None, None, 0, 8192, 0, offs, 3, 10, 0, None) == L.NRM_EINVAL    # NULL out
     assert ex(None, 4097, 0, 8192, 0, offs, 3, 10, 0, None) == L.NRM_EINVAL    # misaligned out
     assert ex(None, 4100, 0, 4096, 0, offs, 3, 10, 0, None) == L.NRM_EOVERLAP  # partial overlap
+    sm = lib.nrm_softmax_batched
+    assert sm(None, 4096, 8192, offs, -1, 10, None, None) == L.NRM_EINVAL    # rows < 0
+    assert sm(None, 4096, 8192, offs, 0, 10, None, None) == L.NRM_OK         # no rows
+    assert sm(None, 4096, 8192, None, 3, 10, None, None) == L.NRM_EINVAL     # NULL offsets
+    assert sm(None, 4096, 8192, offs, 3, 0, None, None) == L.NRM_OK          # zero capacity, no lse
+    assert sm(None, 4096, 8192, offs, 3, 10, 65538, None) == L.NRM_EINVAL    # misaligned lse
+    assert sm(None, None, 8192, offs, 3, 10, None, None) == L.NRM_EINVAL     # NULL out
+    assert sm(None, 4100, 4096, offs, 3, 10, None, None) == L.NRM_EOVERLAP   # in and out partly overlap
+    assert sm(None, 4096, 8192, offs, 3, 10, 8200, None) == L.NRM_EOVERLAP   # lse inside in
+    assert sm(None, 4096, 8192, offs, 3, 10, 4092, None) == L.NRM_EOVERLAP   # lse runs into out
     rows = (L.NrmRow * 2)()
     rows[0].in_, rows[0].out, rows[0].n = 8192, 4096, 4
     rows[1].in_, rows[1].out, rows[1].n = 16384, 12288, -1

@@ -1,0 +1,169 @@
+"""Row softmax / log-sum-exp on the GPU against the FP64 oracle.
+
+Every output is compared element by element with the oracle on the same
+seeded input, within the library's stated bound (include/nrm.h): with
+u = 2^-24, m the row maximum and w the exact softmax weights,
+    d_i = (2|x_i| + |x_i - m| + 4) u          (one term exp2(x log2 e - k))
+    e_s = sum_i w_i d_i + gamma_62            (the row's scaled sum)
+    |out_i - ref_i| <= (d_i + e_s + 2u) ref_i + 2^-125,
+    |lse - ref| <= e_s + 4u (|ref| + 1).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2207_00257_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+U = 2.0 ** -24
+GAMMA62 = 62 * U / (1 - 62 * U)
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def run(x, offs, ctx=None, with_lse=True, inplace=False):
+    inp = gpu(x)
+    out = inp if inplace else torch.empty_like(inp)
+    lse = torch.empty(offs.size - 1, device=DEV) if with_lse else None
+    api.softmax_batched(out, inp, gpu(offs), lse=lse, ctx=ctx)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), (lse.cpu().numpy() if with_lse else None)
+
+
+def check(x, offs, got, got_lse, what=""):
+    ref, ref_lse = oracle.softmax_batched(x, offs)
+    x64 = x.astype(np.float64)
+    for r in range(offs.size - 1):
+        b, e = int(offs[r]), int(offs[r + 1])
+        if e == b:
+            if got_lse is not None:
+                assert got_lse[r] == -np.inf, (what, r)
+            continue
+        xr, rr = x64[b:e], ref[b:e]
+        m = xr.max()
+        d = (2 * np.abs(xr) + np.abs(xr - m) + 4) * U
+        e_s = float(np.sum(rr * d)) + GAMMA62
+        tol = (d + e_s + 2 * U) * rr + 2.0 ** -125  # terms below 2^-126 flush; s >= 1/2
+        err = np.abs(got[b:e].astype(np.float64) - rr)
+        bad = np.nonzero(err > tol)[0]
+        assert bad.size == 0, "%s row %d (n=%d): element %d got %r ref %r tol %r" % (
+            what, r, e - b, bad[0], got[b + bad[0]], rr[bad[0]], tol[bad[0]])
+        if got_lse is not None:
+            assert abs(float(got_lse[r]) - ref_lse[r]) <= e_s + 4 * U * (abs(ref_lse[r]) + 1), (
+                what, r, got_lse[r], ref_lse[r])
+
+
+def csr(lengths):
+    offs = np.zeros(len(lengths) + 1, np.int64)
+    offs[1:] = np.cumsum(lengths)
+    return offs
+
+
+def test_ragged_batch_matches_oracle():
+    x, offs = synth.ragged_logits(300, 51, lo=1, hi=20000, sigma=2.0)
+    got, lse = run(x, offs)
+    check(x, offs, got, lse, "ragged")
+
+
+def test_long_rows_many_tiles_and_chunks():
+    """Rows of several tiles (tile 2^15): phase-1 partials, the row merge and
+    phase-2 chunks that cross row boundaries; a ragged tail on each."""
+    lengths = [(1 << 20) + 123, 3 * (1 << 15) + 7, 70_001, 5, (1 << 17) - 1]
+    offs = csr(lengths)
+    x = synth.normal_f32(int(offs[-1]), 52, 3.0)
+    got, lse = run(x, offs)
+    check(x, offs, got, lse, "long rows")
+
+
+def test_empty_and_single_element_rows():
+    lengths = [0, 1, 0, 2, 1, 0, 4097, 0]
+    offs = csr(lengths)
+    x = synth.normal_f32(int(offs[-1]), 53, 2.0)
+    got, lse = run(x, offs)
+    check(x, offs, got, lse, "empty/single")
+    assert got[offs[1]] == 1.0 and lse[1] == x[offs[1]]
+
+
+@pytest.mark.parametrize("sigma,shift", [(30.0, 0.0), (1.0, 1000.0), (1.0, -1000.0), (0.0, 5.0)])
+def test_wide_ranges_and_shifts(sigma, shift):
+    """Wide logits (terms that underflow), rows far from zero (the exponent
+    reference follows the row maximum), and constant rows (every output 1/n)."""
+    lengths = [1000, 33_333, 7, 200_000]
+    offs = csr(lengths)
+    x = (synth.normal_f32(int(offs[-1]), 54, 1.0).astype(np.float64) * sigma + shift).astype(np.float32)
+    got, lse = run(x, offs)
+    check(x, offs, got, lse, "sigma %g shift %g" % (sigma, shift))
+
+
+def test_in_place_and_without_lse():
+    x, offs = synth.ragged_logits(64, 55, lo=1, hi=50000, sigma=2.0)
+    got, _ = run(x, offs, with_lse=False, inplace=True)
+    check(x, offs, got, None, "in place")
+
+
+def test_row_is_position_independent():
+    """A row's bits depend on its length, 128-byte alignment and the launch
+    parameters only: alone, or at another place in another batch."""
+    row = synth.normal_f32(100_000, 56, 2.0)  # a multiple of 32 floats keeps the next row aligned
+    filler = synth.normal_f32(32 * 1543, 57, 2.0)
+    alone, la = run(row, np.array([0, row.size], np.int64))
+    x = np.concatenate([filler, row, filler])
+    offs = np.array([0, 9, filler.size, filler.size + row.size, x.size], np.int64)
+    got, lse = run(x, offs)
+    assert np.array_equal(got[filler.size:filler.size + row.size], alone)
+    assert lse[2] == la[0]
+
+
+def test_graph_replay_alternating_with_normalize():
+    """One context, graph capture on: softmax and normalize calls alternate
+    (one captured graph per reduction kind), every result checked."""
+    ctx = api.Context()
+    ctx.set_batch_params(graph=1)
+    for seed in (58, 59, 60):
+        x, offs = synth.ragged_logits(40, seed, lo=1, hi=300_000, sigma=2.0)
+        got, lse = run(x, offs, ctx=ctx)
+        check(x, offs, got, lse, "graph seed %d" % seed)
+        pos = np.abs(x) + 0.5
+        inp = gpu(pos)
+        out = torch.empty_like(inp)
+        api.normalize_batched(out, inp, gpu(offs), ctx=ctx)
+        torch.cuda.synchronize()
+        ref = oracle.normalize_batched(pos, offs)
+        rel = np.abs(out.cpu().numpy() - ref) / ref
+        assert float(rel.max()) <= 4e-6
+    assert ctx.device_error() == 0
+    ctx.close()
+
+
+def test_bad_offsets_are_flagged():
+    x = synth.normal_f32(1000, 61, 1.0)
+    offs = np.array([0, 10, 5, 2000, 2001], np.int64)  # decreasing, then past the end (twice)
+    ctx = api.Context()
+    inp = gpu(x)
+    out = torch.zeros_like(inp)
+    lse = torch.zeros(4, device=DEV)
+    api.softmax_batched(out, inp, gpu(offs), lse=lse, ctx=ctx)
+    assert ctx.device_error() != 0
+    l = lse.cpu().numpy()
+    assert l[1] == -np.inf and l[2] == -np.inf and l[3] == -np.inf  # skipped rows count as empty
+    check(x[:10], np.array([0, 10], np.int64), out.cpu().numpy()[:10], l[:1], "valid row")
+    ctx.close()
+
+
+def test_full_workload_sampled_rows():
+    """The benchmark's workload (4096 rows, lengths log-uniform in [32, 2^20],
+    N(0, 4) logits) in the default launch shape: 64 sampled rows against the
+    oracle, every row's outputs summing to one."""
+    x, offs = synth.ragged_logits(4096, 4, sigma=2.0)
+    got, lse = run(x, offs)
+    rng = np.random.default_rng(3)
+    for r in sorted(rng.choice(4096, 64, replace=False)):
+        b, e = int(offs[r]), int(offs[r + 1])
+        check(x[b:e], np.array([0, e - b], np.int64), got[b:e], lse[r:r + 1], "row %d" % r)
+    sums = np.add.reduceat(got.astype(np.float64), offs[:-1])
+    assert np.all(np.abs(sums - 1.0) <= 1e-4)

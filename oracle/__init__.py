@@ -2,9 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 benchmark's CPU-baseline leg, never by the product path. It shares no code
-with the HIP library. The arithmetic lives in normalize_oracle.c and
-softmax_oracle.c (plain C, binary64); this module only loads them with ctypes
-and marshals numpy arrays.
+with the HIP library. The arithmetic lives in normalize_oracle.c,
+softmax_oracle.c and nll_oracle.c (plain C, binary64); this module only loads
+them with ctypes and marshals numpy arrays.
 
 Functions (all return float64 arrays):
   normalize(x)                 hoisted form: S = sum once, out = x / S
@@ -12,6 +12,7 @@ Functions (all return float64 arrays):
   normalize_perblock(x, B)     shared-memory variant: one S per block of B
   normalize_batched(x, offs)   each CSR row [offs[r], offs[r+1]) on its own
   softmax_batched(x, offs)     row softmax and log-sum-exp (softmax_oracle.c)
+  nll_loss(logp, t, w)         forward NLL loss, none / sum / mean (nll_oracle.c)
   decode(x)                    exact widening of FP32 / BF16 / FP16 storage
   round_bf16(y)                binary64 -> nearest bfloat16 (ties to even)
 
@@ -29,16 +30,18 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "normalize_oracle.c")
 _SOFTMAX_SRC = os.path.join(_HERE, "softmax_oracle.c")
+_NLL_SRC = os.path.join(_HERE, "nll_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 
 
-def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH, softmax_src: str = _SOFTMAX_SRC) -> str:
+def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH, softmax_src: str = _SOFTMAX_SRC,
+          nll_src: str = _NLL_SRC) -> str:
     """Compile the oracle with gcc: binary64 as written (no fast-math, no
-    contraction of a*b+c into fma). src and softmax_src are the two sources
-    (a test may pass a changed copy of either)."""
-    srcs = [src, softmax_src]
+    contraction of a*b+c into fma). src, softmax_src and nll_src are its
+    sources (a test may pass a changed copy of any of them)."""
+    srcs = [src, softmax_src, nll_src]
     if force or not os.path.exists(out) or os.path.getmtime(out) < max(os.path.getmtime(s) for s in srcs):
         tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(
@@ -61,9 +64,10 @@ def _bind(lib):
     lib.oracle_round_bf16_one.argtypes = [d]
     lib.oracle_round_bf16_one.restype = ctypes.c_uint16
     lib.oracle_softmax_batched.argtypes = [p, p, i64, p, p]
+    lib.oracle_nll_loss.argtypes = [p, p, p, i64, i64, i64, ctypes.c_int, p, p]
     for name in ("oracle_decode", "oracle_normalize", "oracle_normalize_naive",
                  "oracle_normalize_perblock", "oracle_normalize_batched", "oracle_round_bf16",
-                 "oracle_softmax_batched"):
+                 "oracle_softmax_batched", "oracle_nll_loss"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -150,6 +154,30 @@ class Oracle:
                                                lse.ctypes.data))
         return out, lse[:rows]
 
+    def nll_loss(self, logp, target, weight=None, ignore_index=-100, reduction="mean"):
+        """Forward NLL loss: logp float32 [N, C], target int64 [N], weight
+        float32 [C] or None. Returns (out, total_weight): out is float64 [N]
+        for reduction "none", else a float."""
+        red = {"none": 0, "sum": 1, "mean": 2}[reduction]
+        logp = np.ascontiguousarray(logp, dtype=np.float32)
+        if logp.ndim != 2:
+            raise ValueError("logp must be [N, C]")
+        n, c = logp.shape
+        target = np.ascontiguousarray(target, dtype=np.int64).reshape(-1)
+        if target.size != n:
+            raise ValueError("target needs N entries")
+        wp = None
+        if weight is not None:
+            weight = np.ascontiguousarray(weight, dtype=np.float32).reshape(-1)
+            if weight.size != c:
+                raise ValueError("weight needs C entries")
+            wp = weight.ctypes.data
+        out = np.empty(max(n, 1) if red == 0 else 1, np.float64)
+        tw = np.empty(1, np.float64)
+        _check(self.lib.oracle_nll_loss(logp.ctypes.data, target.ctypes.data, wp, n, c, int(ignore_index), red,
+                                        out.ctypes.data, tw.ctypes.data))
+        return (out[:n] if red == 0 else float(out[0])), float(tw[0])
+
     def round_bf16(self, y):
         y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
         out = np.empty(y.size, np.uint16)
@@ -196,6 +224,10 @@ def normalize_batched(x, offsets, dtype="f32", return_sums=False):
 
 def softmax_batched(x, offsets):
     return _get().softmax_batched(x, offsets)
+
+
+def nll_loss(logp, target, weight=None, ignore_index=-100, reduction="mean"):
+    return _get().nll_loss(logp, target, weight, ignore_index, reduction)
 
 
 def round_bf16(y):

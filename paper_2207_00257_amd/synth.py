@@ -15,6 +15,7 @@ Recipes (the workloads this library is measured on):
   poisson_arrivals     open-loop arrival times with exponential gaps
   normal_f32           logits in[i] = fl32(sigma * N(0,1))
   ragged_logits        a ragged batch of normal logits (the softmax workload)
+  nll_inputs           log-probabilities, targets and class weights (NLL loss)
 """
 from __future__ import annotations
 
@@ -93,6 +94,19 @@ def ragged_logits(rows: int, seed: int, lo: int = 32, hi: int = 1 << 20, sigma: 
     lengths = loguniform_lengths(rows, seed, lo, hi)
     offs = ragged_offsets(lengths)
     return normal_f32(int(offs[-1]), seed + 1000003, sigma), offs
+
+
+def nll_inputs(n: int, c: int, seed: int, ignore_frac: float = 0.05, ignore_index: int = -100):
+    """The NLL-loss workload: log-probabilities logp[n][c] = fl32(-E), E ~
+    Exponential(mean 3) (values in (-inf, 0], like log-softmax outputs), targets
+    uniform in [0, c) with a fraction ignore_frac replaced by ignore_index,
+    and class weights uniform in [0.5, 1.5). Returns (logp, target, weight)."""
+    rng = _rng(seed)
+    logp = (-rng.exponential(3.0, size=(int(n), int(c)))).astype(np.float32)
+    target = rng.integers(0, int(c), size=int(n), dtype=np.int64)
+    target[rng.random(int(n)) < ignore_frac] = ignore_index
+    weight = uniform_f32(int(c), seed + 7, 0.5, 1.5)
+    return logp, target, weight
 
 
 def poisson_arrivals(rate_per_s: float, duration_s: float, seed: int) -> np.ndarray:

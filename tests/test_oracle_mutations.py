@@ -96,3 +96,45 @@ def test_softmax_mutation_is_caught(tmp_path, name):
         except (AssertionError, FloatingPointError):
             failed.append(pin.__name__)
     assert failed, "planted mistake %r passed every softmax pin" % name
+
+
+# ---- the forward NLL-loss oracle (nll_oracle.c) -----------------------------
+
+from nll_pins import NLL_PINS  # noqa: E402
+
+NLL_SRC = os.path.join(os.path.dirname(oracle.__file__), "nll_oracle.c")
+
+NLL_MUTATIONS = {
+    "sign": ("const double l = -w * (double)logp[i * c + t];", "const double l = w * (double)logp[i * c + t];"),
+    "wrong_class": ("const double l = -w * (double)logp[i * c + t];",
+                    "const double l = -w * (double)logp[i * c + (t + 1) % c];"),
+    "weight_ignored": ("const double w = weight ? (double)weight[t] : 1.0;", "const double w = 1.0;"),
+    "mean_over_n": ("if (reduction == ORC_NLL_MEAN) out[0] = loss / wsum;",
+                    "if (reduction == ORC_NLL_MEAN) out[0] = loss / (double)n;"),
+    "ignored_weight_counted": ("      if (reduction == ORC_NLL_NONE) out[i] = 0.0;\n      continue;",
+                               "      if (reduction == ORC_NLL_NONE) out[i] = 0.0;\n      wsum += 1.0;\n      continue;"),
+    "float_accumulator": ("double loss = 0.0, wsum = 0.0;", "float loss = 0.0f; double wsum = 0.0;"),
+    "target_bound_off_by_one": ("if (t < 0 || t >= c) return ORC_NLL_EINVAL;",
+                                "if (t < 0 || t > c) return ORC_NLL_EINVAL;"),
+    "negative_target_accepted": ("if (t < 0 || t >= c) return ORC_NLL_EINVAL;",
+                                 "if (t >= c) return ORC_NLL_EINVAL;\n    if (t < 0) continue;"),
+    "sum_skips_first": ("for (int64_t i = 0; i < n; ++i) {", "for (int64_t i = 1; i < n; ++i) {"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NLL_MUTATIONS))
+def test_nll_mutation_is_caught(tmp_path, name):
+    old, new = NLL_MUTATIONS[name]
+    src = open(NLL_SRC).read()
+    assert old in src, "mutation site vanished from the NLL oracle source: %s" % name
+    mutated = tmp_path / "mutated_nll.c"
+    mutated.write_text(src.replace(old, new, 1))
+    lib = oracle.build(force=True, nll_src=str(mutated), out=str(tmp_path / ("lib_nll_%s.so" % name)))
+    orc = oracle.Oracle(lib)
+    failed = []
+    for pin in NLL_PINS:
+        try:
+            pin(orc)
+        except (AssertionError, ValueError):
+            failed.append(pin.__name__)
+    assert failed, "planted mistake %r passed every NLL pin" % name

@@ -178,6 +178,35 @@ int nrm_get_params(const nrm_ctx* ctx, nrm_params* params);
 int nrm_normalize_ex(nrm_ctx* ctx, void* out, int out_dtype, const void* in, int in_dtype,
                      int64_t n, int accum, void* stream);
 
+/* ---- forward NLL loss ----------------------------------------------------- */
+
+/* The forward negative log-likelihood loss: the loss kernel the paper
+ * translated because it synchronises with a block barrier (arXiv 2207.00257,
+ * Sec. V-B), defined from the loss. N samples, C classes:
+ *     loss_n = -weight[t_n] * logp[n * C + t_n]   (0 when t_n == ignore_index),
+ *     NRM_NLL_NONE: out[n] = loss_n (N floats);
+ *     NRM_NLL_SUM:  out[0] = sum_n loss_n;
+ *     NRM_NLL_MEAN: out[0] = sum_n loss_n / sum over kept n of weight[t_n]
+ *                   (0/0 = NaN when every sample is ignored).
+ * Like normalize (Fig. 1) it reduces invariants once (the loss and the
+ * weight total), then maps (the one division).
+ *   logp:   device binary32 [N][C], row-major;   target: device int64 [N];
+ *   weight: device binary32 [C], or NULL for all 1;
+ *   out:    device binary32, N (none) or 1 (sum, mean);
+ *   total_weight: device binary32 [1] receiving the kept weights' sum
+ *           (sum and mean), or NULL.
+ * accum: NRM_ACC_F32 or NRM_ACC_KAHAN for the two sums. Per-sample losses are
+ * the correctly rounded products; with non-negative weights the sums add
+ * non-negative terms, within gamma_h of the exact sum for the summation
+ * tree's height h (see DESIGN). A target outside [0, C) that is not
+ * ignore_index contributes nothing (0 for none) and is reported by
+ * nrm_get_device_error. Outputs must not overlap the inputs (NRM_EOVERLAP).
+ * ctx NULL: the default context of the current device. */
+typedef enum { NRM_NLL_NONE = 0, NRM_NLL_SUM = 1, NRM_NLL_MEAN = 2 } nrm_reduction;
+int nrm_nll_loss(nrm_ctx* ctx, float* out, float* total_weight, const float* logp, const int64_t* target,
+                 const float* weight, int64_t n, int64_t classes, int64_t ignore_index, int reduction, int accum,
+                 void* stream);
+
 /* ---- the un-hoisted forms, for measurement ------------------------------- */
 
 /* Fig. 1's two slower forms on the GPU: NRM_FORM_NAIVE, every thread sums the

@@ -15,6 +15,7 @@ NRM_OK, NRM_EINVAL, NRM_EOVERLAP, NRM_ENOMEM, NRM_EHIP, NRM_EUNSUPPORTED, NRM_ED
     0, -1, -2, -3, -4, -5, -6)
 NRM_F32, NRM_BF16, NRM_F16 = 0, 1, 2
 NRM_ACC_F32, NRM_ACC_KAHAN = 0, 1
+NRM_NLL_NONE, NRM_NLL_SUM, NRM_NLL_MEAN = 0, 1, 2
 NRM_LAYOUT_CHUNK, NRM_LAYOUT_STRIDE = 0, 1
 NRM_FORM_NAIVE, NRM_FORM_PERBLOCK = 1, 2
 
@@ -139,6 +140,7 @@ def _declare(lib):
         "normalize_batched": (i32, [p, p, p, i64]),
         "nrm_normalize_batched_ex": (i32, [p, p, i32, p, i32, p, i64, i64, i32, p]),
         "nrm_softmax_batched": (i32, [p, p, p, p, i64, i64, p, p]),
+        "nrm_nll_loss": (i32, [p, p, p, p, p, p, i64, i64, i64, i32, i32, p]),
         "nrm_normalize_rows": (i32, [p, ctypes.POINTER(NrmRow), i64, i32, p]),
         "nrm_batch_reserve": (i32, [p, i64, i64]),
         "nrm_default_batch_params": (i32, [ctypes.POINTER(NrmBatchParams)]),

@@ -209,6 +209,47 @@ def softmax_batched(out, inp, offsets, lse=None, ctx: Optional[Context] = None, 
     return out
 
 
+_REDUCTION = {"none": L.NRM_NLL_NONE, "sum": L.NRM_NLL_SUM, "mean": L.NRM_NLL_MEAN}
+
+
+def nll_loss(logp, target, weight=None, ignore_index: int = -100, reduction: str = "mean", accum: str = "f32",
+             out=None, total_weight=None, ctx: Optional[Context] = None, stream: Optional[int] = None):
+    """Forward NLL loss: logp float32 [N, C] device tensor (row-major),
+    target int64 [N], weight float32 [C] or None. Returns out: float32 [N]
+    for reduction "none", else a one-element tensor; total_weight (one
+    element, sum and mean) is written when given. Targets outside [0, C)
+    other than ignore_index are reported by device_error()."""
+    import torch
+
+    if reduction not in _REDUCTION:
+        raise ValueError("reduction must be 'none', 'sum' or 'mean'")
+    if accum not in _ACCUM:
+        raise ValueError("accum must be 'f32' or 'kahan'")
+    if logp.dim() != 2 or logp.dtype != torch.float32 or not logp.is_cuda or not logp.is_contiguous():
+        raise ValueError("logp must be a contiguous float32 [N, C] device tensor")
+    n, c = logp.shape
+    if target.dtype != torch.int64 or target.numel() != n or not target.is_contiguous() or target.device != logp.device:
+        raise ValueError("target must be a contiguous int64 device tensor of N entries")
+    if weight is not None and (weight.dtype != torch.float32 or weight.numel() != c or not weight.is_contiguous()
+                               or weight.device != logp.device):
+        raise ValueError("weight must be a contiguous float32 device tensor of C entries")
+    want = n if reduction == "none" else 1
+    if out is None:
+        out = torch.empty(want, dtype=torch.float32, device=logp.device)
+    elif out.dtype != torch.float32 or out.numel() != want or not out.is_contiguous() or out.device != logp.device:
+        raise ValueError("out must be a contiguous float32 device tensor of %d entries" % want)
+    if total_weight is not None and (total_weight.dtype != torch.float32 or total_weight.numel() != 1
+                                     or total_weight.device != logp.device):
+        raise ValueError("total_weight must be a one-element float32 device tensor")
+    s = _stream_of(logp) if stream is None else stream
+    st = L.lib().nrm_nll_loss(ctx.handle if ctx else None, out.data_ptr(),
+                              total_weight.data_ptr() if total_weight is not None else None, logp.data_ptr(),
+                              target.data_ptr(), weight.data_ptr() if weight is not None else None, n, c,
+                              int(ignore_index), _REDUCTION[reduction], _ACCUM[accum], s)
+    L.check(st, "nrm_nll_loss")
+    return out
+
+
 def normalize_rows(pairs, accum: str = "f32", ctx: Optional[Context] = None, stream: Optional[int] = None):
     """Batched normalize of independent rows: pairs is a sequence of
     (out, inp) device tensors (each pair contiguous, same length; dtypes may

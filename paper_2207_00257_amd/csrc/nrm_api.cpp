@@ -103,6 +103,10 @@ int default_ctx(nrm_ctx** out) {
 namespace {
 
 
+// Reduce blocks of the NLL loss: enough loads in flight for the gathers,
+// few enough partials for the one-block combine.
+constexpr int64_t kNllMaxGrid = 2048;
+
 int ensure_partials(nrm_ctx* c, int64_t entries) {
   if (entries <= c->partials_cap) return NRM_OK;
   int64_t cap = std::max<int64_t>(entries, 16384);
@@ -224,6 +228,62 @@ bool ranges_partially_overlap(const void* a, int64_t abytes, const void* b, int6
 
 extern "C" {
 
+namespace {
+bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
+  if (!a || !b || abytes <= 0 || bbytes <= 0) return false;
+  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)abytes, b0 = (uintptr_t)b, b1 = b0 + (uintptr_t)bbytes;
+  return a0 < b1 && b0 < a1;
+}
+}  // namespace
+
+int nrm_nll_loss(nrm_ctx* c, float* out, float* total_weight, const float* logp, const int64_t* target,
+                 const float* weight, int64_t n, int64_t classes, int64_t ignore_index, int reduction, int accum,
+                 void* stream) {
+  if (n < 0) return fail(NRM_EINVAL, "n < 0");
+  if (classes < 1) return fail(NRM_EINVAL, "classes < 1");
+  if (reduction != NRM_NLL_NONE && reduction != NRM_NLL_SUM && reduction != NRM_NLL_MEAN)
+    return fail(NRM_EINVAL, "unknown reduction");
+  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
+  if (n > 0 && classes > INT64_MAX / 4 / n) return fail(NRM_EINVAL, "n * classes too large");
+  if (n == 0 && reduction == NRM_NLL_NONE) return NRM_OK;
+  if (!out || (n > 0 && (!logp || !target))) return fail(NRM_EINVAL, "NULL pointer");
+  auto misaligned = [](const void* p, size_t a) { return p && reinterpret_cast<uintptr_t>(p) % a; };
+  if (misaligned(out, 4) || misaligned(total_weight, 4) || misaligned(logp, 4) || misaligned(weight, 4) ||
+      misaligned(target, 8))
+    return fail(NRM_EINVAL, "pointer not aligned to its element size");
+  const int64_t out_bytes = 4 * (reduction == NRM_NLL_NONE ? n : 1);
+  const int64_t logp_bytes = 4 * n * classes, target_bytes = 8 * n, weight_bytes = weight ? 4 * classes : 0;
+  for (const auto& o : {std::make_pair((const void*)out, out_bytes), std::make_pair((const void*)total_weight,
+                                                                                     (int64_t)(total_weight ? 4 : 0))})
+    if (overlaps(o.first, o.second, logp, logp_bytes) || overlaps(o.first, o.second, target, target_bytes) ||
+        overlaps(o.first, o.second, weight, weight_bytes))
+      return fail(NRM_EOVERLAP, "an output overlaps an input");
+  if (overlaps(out, out_bytes, total_weight, total_weight ? 4 : 0))
+    return fail(NRM_EOVERLAP, "out and total_weight overlap");
+  if (!c) {
+    int st = nrm::default_ctx(&c);
+    if (st != NRM_OK) return st;
+  }
+  DeviceGuard g(c->device);
+  nrm::NllPlan p;
+  p.logp = logp;
+  p.target = target;
+  p.weight = weight;
+  p.n = n;
+  p.c = classes;
+  p.ignore = ignore_index;
+  p.reduction = reduction;
+  p.acc = accum;
+  p.out = out;
+  p.total_weight = total_weight;
+  p.grid = nrm::nll_grid(n, kNllMaxGrid);
+  int st = ensure_partials(c, 2 * p.grid);
+  if (st != NRM_OK) return st;
+  hipError_t e = nrm::launch_nll(p, c->partials, c->dev_error, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "NLL kernel launch");
+  return NRM_OK;
+}
+
 const char* nrm_status_string(int status) {
   switch (status) {
     case NRM_OK: return "ok";
@@ -274,6 +334,7 @@ int nrm_create(nrm_ctx** ctx, int device) {
   }
   c->ticket = static_cast<unsigned*>(small);
   c->sum = reinterpret_cast<float*>(static_cast<char*>(small) + 128);
+  c->dev_error = reinterpret_cast<int*>(static_cast<char*>(small) + 192);
   int st = ensure_partials(c, 16384);
   if (st != NRM_OK) {
     hipFree(small);

@@ -42,6 +42,7 @@ enum {
   NRM_DEVERR_OFFSETS = 1,   // CSR offsets negative, decreasing or past capacity
   NRM_DEVERR_ROW = 2,       // a table row with n < 0, bad dtype, NULL pointer, or too many tiles
   NRM_DEVERR_CAPACITY = 4,  // more rows or work items than the workspace holds
+  NRM_DEVERR_TARGET = 8,    // NLL loss: a target outside [0, C) that is not ignore_index
 };
 
 constexpr int64_t MAX_ROW_TILES = 65536;  // partials the per-row combine merges

@@ -484,20 +484,28 @@ int nrm_get_device_error(nrm_ctx* c, void* stream) {
     if (st != NRM_OK) return st;
   }
   DeviceGuard g(c->device);
-  if (!c->batch.dev) return NRM_OK;
   hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  // the batched workspace's word and the context's word of the other kernels
   int word = 0;
-  e = hipMemcpy(&word, c->batch.error, sizeof(int), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "reading the device error flag");
+  for (int* p : {c->batch.dev ? c->batch.error : nullptr, c->dev_error}) {
+    if (!p) continue;
+    int w = 0;
+    e = hipMemcpy(&w, p, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the device error flag");
+    if (w) {
+      e = hipMemset(p, 0, sizeof(int));
+      if (e != hipSuccess) return hip_fail(e, "clearing the device error flag");
+    }
+    word |= w;
+  }
   if (!word) return NRM_OK;
-  e = hipMemset(c->batch.error, 0, sizeof(int));
-  if (e != hipSuccess) return hip_fail(e, "clearing the device error flag");
   std::string why;
   if (word & nrm::NRM_DEVERR_OFFSETS) why += "CSR offsets negative, decreasing or past capacity; ";
   if (word & nrm::NRM_DEVERR_ROW) why += "invalid table row or row with too many tiles; ";
   if (word & nrm::NRM_DEVERR_CAPACITY) why += "batch larger than the workspace; ";
-  return fail(NRM_EDEVICE, why + "those rows were skipped");
+  if (word & nrm::NRM_DEVERR_TARGET) why += "NLL target outside [0, classes); ";
+  return fail(NRM_EDEVICE, why + "those rows or samples were skipped");
 }
 
 int nrm_batch_times(nrm_ctx* c, double* total_ms, int64_t* calls) {

@@ -82,6 +82,7 @@ struct nrm_ctx {
   void* partials = nullptr;
   int64_t partials_cap = 0;  // entries (each up to 8 bytes)
   unsigned* ticket = nullptr;
+  int* dev_error = nullptr;  // device error word of the non-batched kernels (NLL targets)
   float* sum = nullptr;      // 2 floats
   // kernel timing
   bool timing = false;

@@ -88,6 +88,22 @@ struct PlainWorkspace {
 };
 
 hipError_t launch_reduce(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t s);
+
+// Forward NLL loss (nrm_nll.hip): one reduce launch of `grid` blocks (two
+// Acc partials each in `partials`) and, unless reduction is none, a one-block
+// combine.
+struct NllPlan {
+  const float* logp;
+  const int64_t* target;
+  const float* weight;
+  int64_t n, c, ignore;
+  int reduction, acc;
+  float* out;
+  float* total_weight;
+  int64_t grid;
+};
+int64_t nll_grid(int64_t n, int64_t max_grid);
+hipError_t launch_nll(const NllPlan& p, void* partials, int* error, hipStream_t s);
 hipError_t launch_form(int form, float* out, const float* in, int64_t n, int block, hipStream_t s);
 hipError_t launch_map(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t s);
 

@@ -115,6 +115,23 @@ def test_batched_host_validation_before_any_hip_call(lib):
     assert lib.nrm_batch_reserve(None, 1, 1) == L.NRM_EINVAL
 
 
+def test_nll_validation_before_any_hip_call(lib):
+    f = lib.nrm_nll_loss
+    lp, tg, w = 1 << 20, 1 << 22, 1 << 24  # addresses used only for their values; nothing is read
+    assert f(None, 4096, None, lp, tg, w, -1, 10, -100, 2, 0, None) == L.NRM_EINVAL      # n < 0
+    assert f(None, 4096, None, lp, tg, w, 5, 0, -100, 2, 0, None) == L.NRM_EINVAL        # no classes
+    assert f(None, 4096, None, lp, tg, w, 5, 10, -100, 3, 0, None) == L.NRM_EINVAL       # reduction
+    assert f(None, 4096, None, lp, tg, w, 5, 10, -100, 2, 9, None) == L.NRM_EINVAL       # accumulation
+    assert f(None, 4096, None, lp, tg, w, 0, 10, -100, 0, 0, None) == L.NRM_OK           # none of nothing
+    assert f(None, None, None, lp, tg, w, 5, 10, -100, 2, 0, None) == L.NRM_EINVAL       # NULL out
+    assert f(None, 4096, None, None, tg, w, 5, 10, -100, 2, 0, None) == L.NRM_EINVAL     # NULL logp
+    assert f(None, 4096, None, lp, tg + 4, w, 5, 10, -100, 2, 0, None) == L.NRM_EINVAL   # misaligned target
+    assert f(None, lp + 8, None, lp, tg, w, 5, 10, -100, 2, 0, None) == L.NRM_EOVERLAP   # out inside logp
+    assert f(None, 4096, tg, lp, tg, w, 5, 10, -100, 2, 0, None) == L.NRM_EOVERLAP       # total weight on target
+    assert f(None, 4096, 4096, lp, tg, w, 5, 10, -100, 2, 0, None) == L.NRM_EOVERLAP     # out on total weight
+    assert f(None, 4096, None, lp, tg, w, 1 << 40, 1 << 40, -100, 2, 0, None) == L.NRM_EINVAL  # N * C too large
+
+
 def test_server_config_validation_before_any_hip_call(lib):
     cfg = L.NrmServerConfig()
     assert lib.nrm_server_default_config(ctypes.byref(cfg)) == L.NRM_OK

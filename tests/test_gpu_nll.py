@@ -1,0 +1,114 @@
+"""Forward NLL loss on the GPU against the FP64 oracle.
+
+reduction none: every loss is the correctly rounded binary32 product, so it
+must equal the oracle's binary64 value rounded to binary32 bit for bit. sum
+and mean add non-negative terms (log-probabilities <= 0, weights > 0): with
+u = 2^-24 and h the summation tree's height (a thread's chain of
+ceil(N / (grid * 1024)) samples, the chain merge, the wavefront, the block
+and the grid combine; at most the chain plus 40 here), plain binary32 is
+within (h + 2) u of the exact sum, compensated sums within 4 u; the mean
+adds the weight total's error and one rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2207_00257_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+U = 2.0 ** -24
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def run(logp, target, weight, reduction, accum="f32", ignore_index=-100, ctx=None):
+    tw = torch.full((1,), -1.0, device=DEV)
+    out = api.nll_loss(gpu(logp), gpu(target), None if weight is None else gpu(weight), ignore_index=ignore_index,
+                       reduction=reduction, accum=accum, total_weight=None if reduction == "none" else tw, ctx=ctx)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    return (o if reduction == "none" else float(o[0])), float(tw.cpu()[0])
+
+
+def sum_tol(n, accum):
+    return 4 * U if accum == "kahan" else (math.ceil(n / (2048 * 1024)) + 42) * U
+
+
+@pytest.mark.parametrize("with_weight", [True, False])
+def test_none_is_the_rounded_product(with_weight):
+    logp, t, w = synth.nll_inputs(5000, 37, 71, ignore_frac=0.1)
+    got, _ = run(logp, t, w if with_weight else None, "none")
+    ref, _ = oracle.nll_loss(logp, t, w if with_weight else None, reduction="none")
+    assert np.array_equal(got.view(np.uint32), ref.astype(np.float32).view(np.uint32))
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+@pytest.mark.parametrize("n,c", [(1, 1), (7, 3), (1000, 10), (300_001, 17), (1 << 20, 100)])
+def test_sum_and_mean(accum, n, c):
+    logp, t, w = synth.nll_inputs(n, c, 72 + n % 97, ignore_frac=0.05)
+    tol = sum_tol(n, accum)
+    s, tw = run(logp, t, w, "sum", accum)
+    ref_s, ref_w = oracle.nll_loss(logp, t, w, reduction="sum")
+    assert abs(s - ref_s) <= tol * ref_s + 1e-45, (s, ref_s)
+    assert abs(tw - ref_w) <= tol * ref_w + 1e-45, (tw, ref_w)
+    m, _ = run(logp, t, w, "mean", accum)
+    ref_m, _ = oracle.nll_loss(logp, t, w, reduction="mean")
+    if ref_w == 0:
+        assert math.isnan(m)
+    else:
+        assert abs(m - ref_m) <= (2 * tol + U) * ref_m, (m, ref_m)
+
+
+def test_without_weights_and_custom_ignore_index():
+    logp, t, _ = synth.nll_inputs(20_000, 50, 73, ignore_frac=0.2, ignore_index=7)
+    m, tw = run(logp, t, None, "mean", ignore_index=7)
+    ref_m, ref_w = oracle.nll_loss(logp, t, None, ignore_index=7, reduction="mean")
+    assert tw == ref_w  # a count of kept samples, exact in binary32
+    assert abs(m - ref_m) <= (2 * sum_tol(t.size, "f32") + U) * ref_m
+
+
+def test_all_ignored_and_empty():
+    logp = np.full((6, 4), -1.0, np.float32)
+    t = np.full(6, -100, np.int64)
+    s, tw = run(logp, t, None, "sum")
+    assert s == 0.0 and tw == 0.0
+    m, _ = run(logp, t, None, "mean")
+    assert math.isnan(m)
+    none, _ = run(logp, t, None, "none")
+    assert np.all(none == 0.0)
+    empty = np.zeros((0, 4), np.float32)
+    s, tw = run(empty, np.zeros(0, np.int64), None, "sum")
+    assert s == 0.0 and tw == 0.0
+    m, _ = run(empty, np.zeros(0, np.int64), None, "mean")
+    assert math.isnan(m)
+
+
+def test_bad_targets_are_flagged_and_skipped():
+    logp, t, w = synth.nll_inputs(3000, 9, 74, ignore_frac=0.0)
+    bad = t.copy()
+    bad[[0, 17, 2999]] = [9, -5, 1 << 40]
+    ctx = api.Context()
+    s, _ = run(logp, bad, w, "sum", ctx=ctx)
+    assert ctx.device_error() != 0
+    skipped = bad.copy()
+    skipped[[0, 17, 2999]] = -100
+    ref_s, _ = oracle.nll_loss(logp, skipped, w, reduction="sum")
+    assert abs(s - ref_s) <= sum_tol(3000, "f32") * ref_s
+    none, _ = run(logp, bad, w, "none", ctx=ctx)
+    assert none[0] == 0.0 and none[17] == 0.0 and none[2999] == 0.0
+    assert ctx.device_error() != 0
+    assert ctx.device_error() == 0  # cleared
+    ctx.close()
+
+
+def test_deterministic():
+    logp, t, w = synth.nll_inputs(200_000, 31, 75)
+    a = [run(logp, t, w, "mean")[0] for _ in range(3)]
+    assert a[0] == a[1] == a[2]

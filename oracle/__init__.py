@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 benchmark's CPU-baseline leg, never by the product path. It shares no code
 with the HIP library. The arithmetic lives in normalize_oracle.c,
-softmax_oracle.c and nll_oracle.c (plain C, binary64); this module only loads
-them with ctypes and marshals numpy arrays.
+softmax_oracle.c, nll_oracle.c and layerforward_oracle.c (plain C, binary64);
+this module only loads them with ctypes and marshals numpy arrays.
 
 Functions (all return float64 arrays):
   normalize(x)                 hoisted form: S = sum once, out = x / S
@@ -13,6 +13,7 @@ Functions (all return float64 arrays):
   normalize_batched(x, offs)   each CSR row [offs[r], offs[r+1]) on its own
   softmax_batched(x, offs)     row softmax and log-sum-exp (softmax_oracle.c)
   nll_loss(logp, t, w)         forward NLL loss, none / sum / mean (nll_oracle.c)
+  layerforward(hidden, inp)    Fig. 9-shaped tile kernel (layerforward_oracle.c)
   decode(x)                    exact widening of FP32 / BF16 / FP16 storage
   round_bf16(y)                binary64 -> nearest bfloat16 (ties to even)
 
@@ -31,17 +32,18 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "normalize_oracle.c")
 _SOFTMAX_SRC = os.path.join(_HERE, "softmax_oracle.c")
 _NLL_SRC = os.path.join(_HERE, "nll_oracle.c")
+_LF_SRC = os.path.join(_HERE, "layerforward_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 
 
 def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH, softmax_src: str = _SOFTMAX_SRC,
-          nll_src: str = _NLL_SRC) -> str:
+          nll_src: str = _NLL_SRC, lf_src: str = _LF_SRC) -> str:
     """Compile the oracle with gcc: binary64 as written (no fast-math, no
-    contraction of a*b+c into fma). src, softmax_src and nll_src are its
-    sources (a test may pass a changed copy of any of them)."""
-    srcs = [src, softmax_src, nll_src]
+    contraction of a*b+c into fma). src, softmax_src, nll_src and lf_src are
+    its sources (a test may pass a changed copy of any of them)."""
+    srcs = [src, softmax_src, nll_src, lf_src]
     if force or not os.path.exists(out) or os.path.getmtime(out) < max(os.path.getmtime(s) for s in srcs):
         tmp = out + ".tmp%d" % os.getpid()
         subprocess.check_call(
@@ -65,9 +67,10 @@ def _bind(lib):
     lib.oracle_round_bf16_one.restype = ctypes.c_uint16
     lib.oracle_softmax_batched.argtypes = [p, p, i64, p, p]
     lib.oracle_nll_loss.argtypes = [p, p, p, i64, i64, i64, ctypes.c_int, p, p]
+    lib.oracle_layerforward.argtypes = [p, p, i64, p, p]
     for name in ("oracle_decode", "oracle_normalize", "oracle_normalize_naive",
                  "oracle_normalize_perblock", "oracle_normalize_batched", "oracle_round_bf16",
-                 "oracle_softmax_batched", "oracle_nll_loss"):
+                 "oracle_softmax_batched", "oracle_nll_loss", "oracle_layerforward"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -178,6 +181,22 @@ class Oracle:
                                         out.ctypes.data, tw.ctypes.data))
         return (out[:n] if red == 0 else float(out[0])), float(tw[0])
 
+    def layerforward(self, hidden, inp):
+        """The Fig. 9-shaped tile kernel: hidden float32 [R, 16], inp float32
+        [R] (R a multiple of 16). Returns (new_hidden [R, 16], output [R]) in
+        binary64: each row after the tile's halving tree, and each tile's 16
+        column sums."""
+        hidden = np.ascontiguousarray(hidden, dtype=np.float32)
+        inp = np.ascontiguousarray(inp, dtype=np.float32).reshape(-1)
+        if hidden.ndim != 2 or hidden.shape[1] != 16 or hidden.shape[0] != inp.size:
+            raise ValueError("hidden must be [R, 16] with R = len(input)")
+        rows = inp.size
+        new_hidden = np.empty((rows, 16), np.float64)
+        out = np.empty(max(rows, 1), np.float64)
+        _check(self.lib.oracle_layerforward(hidden.ctypes.data, inp.ctypes.data, rows, new_hidden.ctypes.data,
+                                            out.ctypes.data))
+        return new_hidden, out[:rows]
+
     def round_bf16(self, y):
         y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
         out = np.empty(y.size, np.uint16)
@@ -228,6 +247,10 @@ def softmax_batched(x, offsets):
 
 def nll_loss(logp, target, weight=None, ignore_index=-100, reduction="mean"):
     return _get().nll_loss(logp, target, weight, ignore_index, reduction)
+
+
+def layerforward(hidden, inp):
+    return _get().layerforward(hidden, inp)
 
 
 def round_bf16(y):

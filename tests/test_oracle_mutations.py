@@ -138,3 +138,41 @@ def test_nll_mutation_is_caught(tmp_path, name):
         except (AssertionError, ValueError):
             failed.append(pin.__name__)
     assert failed, "planted mistake %r passed every NLL pin" % name
+
+
+# ---- the Fig. 9-shaped tile kernel oracle (layerforward_oracle.c) ------------
+
+from layerforward_pins import LAYERFORWARD_PINS  # noqa: E402
+
+LF_SRC = os.path.join(os.path.dirname(oracle.__file__), "layerforward_oracle.c")
+
+LF_MUTATIONS = {
+    "no_input_factor": ("s += (double)hidden[j * LF_TILE + x] * (double)input[j];",
+                        "s += (double)hidden[j * LF_TILE + x];"),
+    "transposed_tile": ("s += (double)hidden[j * LF_TILE + x] * (double)input[j];",
+                        "s += (double)hidden[(b * LF_TILE + x) * LF_TILE + k] * (double)input[j];"),
+    "span_off_by_one": ("for (int k = y; k < y + span; ++k) {", "for (int k = y; k < y + span - 1; ++k) {"),
+    "span_highest_bit": ("static int span_of(int y) { return y == 0 ? LF_TILE : (y & -y); }",
+                         "static int span_of(int y) { return y == 0 ? LF_TILE : (y & -y) * (y > 8 ? 1 : 2) > LF_TILE - y ? LF_TILE - y : (y & -y) * (y > 8 ? 1 : 2); }"),
+    "output_from_last_row": ("if (y == 0) output[b * LF_TILE + x] = s;", "if (y == 8) output[b * LF_TILE + x] = s;"),
+    "input_wrong_row": ("s += (double)hidden[j * LF_TILE + x] * (double)input[j];",
+                        "s += (double)hidden[j * LF_TILE + x] * (double)input[b * LF_TILE];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LF_MUTATIONS))
+def test_layerforward_mutation_is_caught(tmp_path, name):
+    old, new = LF_MUTATIONS[name]
+    src = open(LF_SRC).read()
+    assert old in src, "mutation site vanished from the layerforward oracle source: %s" % name
+    mutated = tmp_path / "mutated_lf.c"
+    mutated.write_text(src.replace(old, new, 1))
+    lib = oracle.build(force=True, lf_src=str(mutated), out=str(tmp_path / ("lib_lf_%s.so" % name)))
+    orc = oracle.Oracle(lib)
+    failed = []
+    for pin in LAYERFORWARD_PINS:
+        try:
+            pin(orc)
+        except (AssertionError, ValueError):
+            failed.append(pin.__name__)
+    assert failed, "planted mistake %r passed every layerforward pin" % name

@@ -91,7 +91,7 @@ def main():
                     help="JSON file of tuned launch parameters (default: the committed tuning cache "
                          "if it has an entry for this device and size, else the library defaults)")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "ragged", "serve", "precision", "ladder", "softmax", "nll"],
+                    choices=["plain", "ragged", "serve", "precision", "ladder", "softmax", "nll", "barriers"],
                     help="plain: n=2^log2n FP32 (the headline); ragged: 4096 rows, lengths log-uniform "
                          "in [32, 2^20], LogNormal(0,1) FP32, one graph-replayed batched call per step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -103,6 +103,8 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "barriers":
+        return bench_barriers(args)
     if args.workload == "nll":
         return bench_nll(args)
     if args.workload == "softmax":
@@ -441,6 +443,57 @@ def bench_nll(args, n=1 << 22, c=1000):
                                "64-byte sector per kept sample", "n": n, "classes": c},
         "torch_nll_loss_ms": round(torch_ms, 5),
         "rel_err_vs_binary64": abs(got - ref) / ref,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_barriers(args):
+    """The Fig. 9-shaped tile kernel in its three forms (every barrier as
+    analysed; the two barriers Sec. IV-A eliminates removed; also the
+    store/load Sec. IV-B promotes to a register), at R = 2^24 rows (hidden
+    1 GiB: HBM-bound) and R = 2^16 rows (4 MiB: cache-resident). Inputs
+    U[0.5, 1.5) for hidden and 1/16 for input, so repeated in-place calls stay
+    bounded. Bytes per row: 64 read + 64 written of hidden, 4 of input, 4 of
+    output."""
+    import torch
+
+    from paper_2207_00257_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sizes = {}
+    for log2r in (24, 16):
+        rows = 1 << log2r
+        hidden = torch.from_numpy(synth.uniform_f32(rows * 16, 97)).to(dev)
+        inp = torch.full((rows,), 0.0625, device=dev)
+        out = torch.empty(rows, device=dev)
+        reps = args.steps if log2r == 24 else args.steps * 50
+        res = {}
+        for form in ("printed", "eliminated", "promoted", "registers"):
+            for _ in range(args.warmup):
+                api.layerforward(hidden, inp, out, form=form)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                api.layerforward(hidden, inp, out, form=form)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            res[form] = {"us": round(us, 3), "GBps": round(136.0 * rows / (us * 1e-6) / 1e9, 1)}
+        res["eliminated_speedup"] = round(res["printed"]["us"] / res["eliminated"]["us"], 4)
+        res["promoted_speedup"] = round(res["printed"]["us"] / res["promoted"]["us"], 4)
+        res["registers_speedup"] = round(res["printed"]["us"] / res["registers"]["us"], 4)
+        sizes["rows_2^%d" % log2r] = res
+    big = sizes["rows_2^24"]
+    line = {
+        "metric": METRIC, "value": big["printed"]["GBps"], "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(big["printed"]["us"] / 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Fig. 9-shaped tile kernel (16 x 16 tiles, 256-thread blocks): R = 2^24 and 2^16 "
+                               "rows, hidden U[0.5, 1.5) FP32 [R, 16] updated in place, input 1/16; forms printed / "
+                               "eliminated / promoted / registers; value = the printed form; model 136 B/row"},
+        "forms": sizes,
     }
     print(json.dumps(line), flush=True)
 

@@ -207,6 +207,29 @@ int nrm_nll_loss(nrm_ctx* ctx, float* out, float* total_weight, const float* log
                  const float* weight, int64_t n, int64_t classes, int64_t ignore_index, int reduction, int accum,
                  void* stream);
 
+/* ---- barrier elimination, for measurement --------------------------------- */
+
+/* A synthetic layer-forward tile kernel with the shape of the paper's
+ * barrier-elimination example (arXiv 2207.00257, Sec. IV-A and IV-B, Fig. 9),
+ * to measure what removing barriers saves on the GPU. hidden: device binary32
+ * R x 16 (row-major), updated in place; input: device binary32 [R]; output:
+ * device binary32 [R]; R a multiple of 16, R / 16 <= 2^31 - 1. Per tile of 16
+ * rows (one 256-thread block): p[y][x] = hidden[16 b + y][x] * input[16 b + y],
+ * a halving tree over y (row y ends with the sum of p over rows y .. y + L(y)
+ * - 1, L(y) the largest power of two dividing y, 16 for y = 0), every row
+ * written back to hidden, and output[16 b + x] = the column sums (tile row 0).
+ *   NRM_LF_PRINTED     every barrier of the example as analysed;
+ *   NRM_LF_ELIMINATED  without the two barriers Sec. IV-A proves redundant;
+ *   NRM_LF_PROMOTED    also without the shared store/load a thread makes only
+ *                      to itself across a barrier (Sec. IV-B);
+ *   NRM_LF_REGISTERS   the tile kept in registers, one thread per column:
+ *                      no shared memory and no barrier.
+ * The forms compute the same values bit for bit (products rounded to binary32,
+ * the tree's additions in the same order). hidden, input and output must not
+ * overlap (NRM_EOVERLAP). */
+typedef enum { NRM_LF_PRINTED = 0, NRM_LF_ELIMINATED = 1, NRM_LF_PROMOTED = 2, NRM_LF_REGISTERS = 3 } nrm_lf_form;
+int nrm_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows, void* stream);
+
 /* ---- the un-hoisted forms, for measurement ------------------------------- */
 
 /* Fig. 1's two slower forms on the GPU: NRM_FORM_NAIVE, every thread sums the

@@ -141,6 +141,7 @@ def _declare(lib):
         "nrm_normalize_batched_ex": (i32, [p, p, i32, p, i32, p, i64, i64, i32, p]),
         "nrm_softmax_batched": (i32, [p, p, p, p, i64, i64, p, p]),
         "nrm_nll_loss": (i32, [p, p, p, p, p, p, i64, i64, i64, i32, i32, p]),
+        "nrm_layerforward": (i32, [i32, p, p, p, i64, p]),
         "nrm_normalize_rows": (i32, [p, ctypes.POINTER(NrmRow), i64, i32, p]),
         "nrm_batch_reserve": (i32, [p, i64, i64]),
         "nrm_default_batch_params": (i32, [ctypes.POINTER(NrmBatchParams)]),

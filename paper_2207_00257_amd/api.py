@@ -209,6 +209,29 @@ def softmax_batched(out, inp, offsets, lse=None, ctx: Optional[Context] = None, 
     return out
 
 
+_LF_FORMS = {"printed": 0, "eliminated": 1, "promoted": 2, "registers": 3}
+
+
+def layerforward(hidden, inp, output, form: str = "printed", stream: Optional[int] = None):
+    """The Fig. 9-shaped tile kernel (see nrm_layerforward in include/nrm.h):
+    hidden float32 [R, 16] (updated in place), inp and output float32 [R],
+    R a multiple of 16; form "printed", "eliminated" or "promoted"."""
+    import torch
+
+    if form not in _LF_FORMS:
+        raise ValueError("form must be one of %s" % sorted(_LF_FORMS))
+    for t in (hidden, inp, output):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("hidden, inp and output must be contiguous float32 device tensors")
+    rows = inp.numel()
+    if hidden.numel() != 16 * rows or output.numel() != rows:
+        raise ValueError("hidden must be [R, 16] and output [R] for R = len(inp)")
+    s = _stream_of(inp) if stream is None else stream
+    L.check(L.lib().nrm_layerforward(_LF_FORMS[form], hidden.data_ptr(), inp.data_ptr(), output.data_ptr(), rows, s),
+            "nrm_layerforward")
+    return output
+
+
 _REDUCTION = {"none": L.NRM_NLL_NONE, "sum": L.NRM_NLL_SUM, "mean": L.NRM_NLL_MEAN}
 
 

@@ -284,6 +284,24 @@ int nrm_nll_loss(nrm_ctx* c, float* out, float* total_weight, const float* logp,
   return NRM_OK;
 }
 
+int nrm_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows, void* stream) {
+  if (form != NRM_LF_PRINTED && form != NRM_LF_ELIMINATED && form != NRM_LF_PROMOTED && form != NRM_LF_REGISTERS)
+    return fail(NRM_EINVAL, "unknown form");
+  if (rows < 0 || rows % 16) return fail(NRM_EINVAL, "rows must be a non-negative multiple of 16");
+  if (rows / 16 > INT32_MAX) return fail(NRM_EINVAL, "too many rows for one launch");
+  if (rows == 0) return NRM_OK;
+  if (!hidden || !input || !output) return fail(NRM_EINVAL, "NULL pointer");
+  auto misaligned = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 4 != 0; };
+  if (misaligned(hidden) || misaligned(input) || misaligned(output))
+    return fail(NRM_EINVAL, "pointer not aligned to 4 bytes");
+  if (overlaps(hidden, 64 * rows, input, 4 * rows) || overlaps(hidden, 64 * rows, output, 4 * rows) ||
+      overlaps(input, 4 * rows, output, 4 * rows))
+    return fail(NRM_EOVERLAP, "hidden, input and output must not overlap");
+  hipError_t e = nrm::launch_layerforward(form, hidden, input, output, rows, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "layerforward kernel launch");
+  return NRM_OK;
+}
+
 const char* nrm_status_string(int status) {
   switch (status) {
     case NRM_OK: return "ok";

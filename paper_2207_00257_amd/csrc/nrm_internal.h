@@ -103,6 +103,10 @@ struct NllPlan {
   int64_t grid;
 };
 int64_t nll_grid(int64_t n, int64_t max_grid);
+
+// The Fig. 9-shaped tile kernel in one of its three forms (nrm_layerforward.hip).
+hipError_t launch_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows,
+                               hipStream_t s);
 hipError_t launch_nll(const NllPlan& p, void* partials, int* error, hipStream_t s);
 hipError_t launch_form(int form, float* out, const float* in, int64_t n, int block, hipStream_t s);
 hipError_t launch_map(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t s);

@@ -132,6 +132,19 @@ def test_nll_validation_before_any_hip_call(lib):
     assert f(None, 4096, None, lp, tg, w, 1 << 40, 1 << 40, -100, 2, 0, None) == L.NRM_EINVAL  # N * C too large
 
 
+def test_layerforward_validation_before_any_hip_call(lib):
+    f = lib.nrm_layerforward
+    h, i, o = 1 << 20, 1 << 24, 1 << 26
+    assert f(4, h, i, o, 16, None) == L.NRM_EINVAL            # unknown form
+    assert f(0, h, i, o, 17, None) == L.NRM_EINVAL            # not whole tiles
+    assert f(0, h, i, o, -16, None) == L.NRM_EINVAL
+    assert f(0, h, i, o, 0, None) == L.NRM_OK                 # nothing to do
+    assert f(0, None, i, o, 16, None) == L.NRM_EINVAL
+    assert f(0, h + 2, i, o, 16, None) == L.NRM_EINVAL        # misaligned
+    assert f(0, h, h + 64, o, 16, None) == L.NRM_EOVERLAP     # input inside hidden
+    assert f(1, h, i, i + 32, 16, None) == L.NRM_EOVERLAP     # output overlaps input
+
+
 def test_server_config_validation_before_any_hip_call(lib):
     cfg = L.NrmServerConfig()
     assert lib.nrm_server_default_config(ctypes.byref(cfg)) == L.NRM_OK

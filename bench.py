@@ -521,9 +521,10 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
     bp = tune.load_batch_params(args.params, workload="serve")
     warm_ns = int(warm_s * 1e9)
 
-    def run(batching, budget=64 << 30, tr=trace, pt=ptrs, n_req=None, warm_ns=warm_ns, spread=True):
+    def run(batching, budget=64 << 30, tr=trace, pt=ptrs, n_req=None, warm_ns=warm_ns, spread=True, idle_spin_us=1000):
         n_req = tr["n"].size if n_req is None else n_req
-        srv = serve.Server(slots=4, budget_bytes=budget, batching=batching, batch_params=bp, spread=spread)
+        srv = serve.Server(slots=4, budget_bytes=budget, batching=batching, batch_params=bp, spread=spread,
+                           idle_spin_us=idle_spin_us)
         t0 = srv.replay(np.arange(n_req), pt[:n_req], tr["n"][:n_req], tr["in_dt"][:n_req], tr["out_dt"][:n_req],
                         tr["t_ns"][:n_req])
         comps = srv.wait_all(n_req, timeout_s=600)
@@ -538,6 +539,7 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
     batched = run(True)
     per_req = run(False)
     grouped = run(True, spread=False)
+    blocking = run(True, idle_spin_us=0)
     stress = run(True, budget=256 << 20)
     sweep = []
     for r in (50000.0, 100000.0, 200000.0):
@@ -583,6 +585,7 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=5.0):
                                "64 GiB HBM admission budget, 4 slots, open-loop replay, latency from scheduled "
                                "arrival" % (rate, measure_s, warm_s), "requests": int(k)},
         "batched": batched, "per_request_launch": per_req, "batched_no_spread": grouped,
+        "batched_scheduler_blocks_when_idle": blocking,
         "budget_256MiB": stress, "rate_sweep": sweep,
         "sample_max_rel_err_f32": worst, "sample_max_err_bf16_ulps": worst_bf16,
     }

@@ -106,7 +106,10 @@ typedef struct {
                            (height 10), so all blocks divide by the same value. Taken when the
                            reduce has at most 1024 blocks and out is aligned like in; otherwise
                            the last reduce block combines as with 0. */
-  int32_t reserved[1];
+  int32_t small_n;      /* 0..2^16: n up to this runs as one launch of one 1024-thread block that
+                           reads the input once into registers (16 binary32 or 8 2-byte vectors
+                           per thread), reduces it, and divides from the registers: one read,
+                           one write, one launch; 0: never */
 } nrm_params;
 
 /* Launch parameters of the ragged batched path. Start from
@@ -344,6 +347,12 @@ typedef struct {
                                 requests run alone and concurrently while slots are free and are
                                 grouped only when the queue outgrows the slots; 0: the first free
                                 slot takes all it can */
+  int32_t idle_spin_us;      /* 0..10^6: after its last activity the scheduler thread keeps polling
+                                (yielding) this long before it blocks, so that an arrival within
+                                that time is picked up without a thread wake-up */
+  int32_t min_batch_rows;    /* 1..2^20: with batching, a group of fewer requests runs as one plain
+                                call per request on its slot (a small call is one launch; the batched
+                                call costs its planner and four kernels whatever the group's size) */
   int64_t budget_bytes;      /* HBM admission budget: input + output bytes of admitted requests */
   int64_t arena_bytes;       /* device arena for outputs (0: two thirds of the budget) */
   int64_t max_batch_rows;    /* requests per batch */

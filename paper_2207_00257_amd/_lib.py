@@ -37,7 +37,7 @@ class NrmParams(ctypes.Structure):
         ("reduce_keep_mib", ctypes.c_int32),
         ("tile_log2", ctypes.c_int32),
         ("fused_combine", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("small_n", ctypes.c_int32),
     ]
 
 
@@ -99,6 +99,8 @@ class NrmServerConfig(ctypes.Structure):
         ("use_batch_params", ctypes.c_int32),
         ("single_plain", ctypes.c_int32),
         ("spread", ctypes.c_int32),
+        ("idle_spin_us", ctypes.c_int32),
+        ("min_batch_rows", ctypes.c_int32),
         ("budget_bytes", ctypes.c_int64),
         ("arena_bytes", ctypes.c_int64),
         ("max_batch_rows", ctypes.c_int64),

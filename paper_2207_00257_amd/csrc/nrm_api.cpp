@@ -52,6 +52,7 @@ nrm_params default_params() {
   p.reduce_keep_mib = 64;
   p.tile_log2 = 13;
   p.fused_combine = 1;
+  p.small_n = 65536;
   return p;
 }
 
@@ -70,8 +71,7 @@ int check_params(const nrm_params& p) {
   if (p.reduce_keep_mib < 0 || p.reduce_keep_mib > 4096) return fail(NRM_EINVAL, "reduce_keep_mib must be 0..4096");
   if (p.tile_log2 < 10 || p.tile_log2 > 22) return fail(NRM_EINVAL, "tile_log2 must be 10..22");
   if (!ok_f(p.fused_combine)) return fail(NRM_EINVAL, "fused_combine must be 0 or 1");
-  for (int r : p.reserved)
-    if (r != 0) return fail(NRM_EINVAL, "reserved fields must be zero");
+  if (p.small_n < 0 || p.small_n > (1 << 16)) return fail(NRM_EINVAL, "small_n must be 0..2^16");
   return NRM_OK;
 }
 
@@ -457,6 +457,27 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
   if (!c) {
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
+  }
+  if (n <= c->params.small_n && n <= nrm::small_capacity(in_dtype)) {
+    // one block, the input held in registers: one read, one write, one launch
+    const uintptr_t ai = reinterpret_cast<uintptr_t>(in), ao = reinterpret_cast<uintptr_t>(out);
+    if (ai % si) return fail(NRM_EINVAL, "in is not aligned to its element size");
+    if (ao % so) return fail(NRM_EINVAL, "out is not aligned to its element size");
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t* ev = nullptr;
+    if (c->timing) {
+      ev = &c->events[3 * (c->timed_calls % kTimingRing)];
+      c->timed_calls++;
+      hipEventRecord(ev[0], s);
+    }
+    hipError_t e = nrm::launch_small(in, in_dtype, out, out_dtype, n, accum, c->sum, s);
+    if (e != hipSuccess) return hip_fail(e, "small normalize kernel launch");
+    if (ev) {
+      hipEventRecord(ev[1], s);
+      hipEventRecord(ev[2], s);
+    }
+    return NRM_OK;
   }
   nrm::PlainPlan plan;
   int st = plan_plain(c, out, out_dtype, in, in_dtype, n, accum, &plan);

@@ -900,7 +900,55 @@ hipError_t launch_phases(const BatchPlan& p, const BatchArgs& a, hipStream_t s) 
   return phase2_acc<ACC>(p, a, s);
 }
 
+// ---- the plain path's single-launch form for small n ---------------------------------
+// One 1024-thread block holds the whole input in registers (SMALL_ELEMS
+// elements: 16 vectors per thread for binary32, 8 for 2-byte inputs, which
+// keeps the widened values in registers), reduces it, and divides from the
+// registers: one read, one write, one launch. The sum is left in sum_out for
+// nrm_get_last_sum.
+constexpr int64_t SMALL_ELEMS = 65536;
+
+template <int DTI, int DTO, int ACC>
+__global__ void __launch_bounds__(1024) small_normalize_kernel(RowDesc d, float* sum_out) {
+  __shared__ Acc<ACC> slots[MAX_WAVES];
+  __shared__ RowRes s_bcast;
+  constexpr int KB = (int)(SMALL_ELEMS / 1024 / Elem<DTI>::VEC);
+  single_pass<DTI, DTO, ACC, KB>(d, slots, &s_bcast, nullptr, 0);
+  if (threadIdx.x == 0) sum_out[0] = s_bcast.a;  // single_pass ended after the broadcast's barrier
+}
+
+template <int ACC>
+hipError_t small_acc(const RowDesc& d, float* sum_out, hipStream_t s) {
+#define NRM_SK(I, O) hipLaunchKernelGGL((small_normalize_kernel<I, O, ACC>), dim3(1), dim3(1024), 0, s, d, sum_out)
+  switch (d.in_dt * 3 + d.out_dt) {
+    case NRM_F32 * 3 + NRM_F32: NRM_SK(NRM_F32, NRM_F32); break;
+    case NRM_F32 * 3 + NRM_BF16: NRM_SK(NRM_F32, NRM_BF16); break;
+    case NRM_F32 * 3 + NRM_F16: NRM_SK(NRM_F32, NRM_F16); break;
+    case NRM_BF16 * 3 + NRM_F32: NRM_SK(NRM_BF16, NRM_F32); break;
+    case NRM_BF16 * 3 + NRM_BF16: NRM_SK(NRM_BF16, NRM_BF16); break;
+    case NRM_BF16 * 3 + NRM_F16: NRM_SK(NRM_BF16, NRM_F16); break;
+    case NRM_F16 * 3 + NRM_F32: NRM_SK(NRM_F16, NRM_F32); break;
+    case NRM_F16 * 3 + NRM_BF16: NRM_SK(NRM_F16, NRM_BF16); break;
+    default: NRM_SK(NRM_F16, NRM_F16); break;
+  }
+#undef NRM_SK
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int64_t small_capacity(int) { return SMALL_ELEMS; }
+
+hipError_t launch_small(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc, float* sum_out,
+                        hipStream_t s) {
+  RowDesc d;
+  d.in = static_cast<const char*>(in);
+  d.out = static_cast<char*>(out);
+  d.n = n;
+  d.in_dt = in_dt;
+  d.out_dt = out_dt;
+  return acc == NRM_ACC_KAHAN ? small_acc<NRM_ACC_KAHAN>(d, sum_out, s) : small_acc<NRM_ACC_F32>(d, sum_out, s);
+}
 
 hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(PLAN_THREADS), 0, s, a);

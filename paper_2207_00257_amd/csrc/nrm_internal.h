@@ -104,6 +104,12 @@ struct NllPlan {
 };
 int64_t nll_grid(int64_t n, int64_t max_grid);
 
+// The plain path's single-launch form for small n (nrm_batched.hip): one block
+// holds up to small_capacity(in_dt) elements in registers.
+int64_t small_capacity(int in_dt);
+hipError_t launch_small(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc, float* sum_out,
+                        hipStream_t s);
+
 // The Fig. 9-shaped tile kernel in one of its three forms (nrm_layerforward.hip).
 hipError_t launch_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows,
                                hipStream_t s);

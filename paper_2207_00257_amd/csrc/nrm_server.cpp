@@ -160,7 +160,8 @@ void nrm_server::launch(Slot& s, std::vector<Pending>& batch) {
     rows[i].out_dtype = p.req.out_dtype;
   }
   int st = NRM_OK;
-  if (cfg.batching && !(cfg.single_plain && rows.size() == 1)) {
+  const bool small_group = (int64_t)rows.size() < cfg.min_batch_rows || (cfg.single_plain && rows.size() == 1);
+  if (cfg.batching && !small_group) {
     st = nrm_normalize_rows(s.ctx, rows.data(), (int64_t)rows.size(), cfg.accum, s.stream);
     launches += 1;
   } else {
@@ -187,6 +188,7 @@ void nrm_server::launch(Slot& s, std::vector<Pending>& batch) {
 void nrm_server::run() {
   DeviceGuard g(device);
   std::vector<Pending> batch;
+  int64_t last_activity = now_ns();
   while (true) {
     bool progressed = false;
     // 1. completions
@@ -260,13 +262,17 @@ void nrm_server::run() {
       std::lock_guard<std::mutex> lk(mu);
       if (idle && queue.empty()) break;
     }
-    if (!progressed) {
+    if (progressed) {
+      last_activity = now_ns();
+    } else {
       std::unique_lock<std::mutex> lk(mu);
       bool any_busy = false;
       for (Slot& s : slots) any_busy = any_busy || s.busy;
-      if (any_busy) {
+      if (any_busy || now_ns() - last_activity < (int64_t)cfg.idle_spin_us * 1000) {
+        // poll the slots' events (and the queue) again without sleeping: an
+        // arrival is then picked up without a thread wake-up
         lk.unlock();
-        std::this_thread::yield();  // poll the slots' events again
+        std::this_thread::yield();
       } else {
         cv.wait_for(lk, std::chrono::microseconds(200));
       }
@@ -289,6 +295,8 @@ int nrm_server_default_config(nrm_server_config* cfg) {
   cfg->accum = NRM_ACC_F32;
   cfg->single_plain = 1;
   cfg->spread = 1;
+  cfg->idle_spin_us = 1000;
+  cfg->min_batch_rows = 4;  // the best balance of p50 and p99 over 20k-200k requests/s on MI355X
   return NRM_OK;
 }
 
@@ -306,6 +314,8 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
   if (cfg->use_batch_params != 0 && cfg->use_batch_params != 1) return fail(NRM_EINVAL, "use_batch_params must be 0 or 1");
   if (cfg->single_plain != 0 && cfg->single_plain != 1) return fail(NRM_EINVAL, "single_plain must be 0 or 1");
   if (cfg->spread != 0 && cfg->spread != 1) return fail(NRM_EINVAL, "spread must be 0 or 1");
+  if (cfg->idle_spin_us < 0 || cfg->idle_spin_us > 1000000) return fail(NRM_EINVAL, "idle_spin_us must be 0..10^6");
+  if (cfg->min_batch_rows < 1 || cfg->min_batch_rows > (1 << 20)) return fail(NRM_EINVAL, "min_batch_rows must be 1..2^20");
   if (device < 0) {
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

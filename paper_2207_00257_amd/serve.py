@@ -24,7 +24,7 @@ class Server:
     def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, batching: bool = True, graph: bool = True,
                  hold_outputs: bool = False, max_batch_rows: int = 256, max_batch_elems: int = 1 << 27,
                  accum: str = "f32", batch_params: Optional[dict] = None, arena_bytes: int = 0, device: int = -1,
-                 single_plain: bool = True, spread: bool = True):
+                 single_plain: bool = True, spread: bool = True, idle_spin_us: int = 1000, min_batch_rows: int = 4):
         lib = L.lib()
         cfg = L.NrmServerConfig()
         L.check(lib.nrm_server_default_config(ctypes.byref(cfg)), "nrm_server_default_config")
@@ -39,6 +39,8 @@ class Server:
         cfg.max_batch_elems = max_batch_elems
         cfg.single_plain = int(single_plain)
         cfg.spread = int(spread)
+        cfg.idle_spin_us = int(idle_spin_us)
+        cfg.min_batch_rows = int(min_batch_rows)
         if batch_params:
             lib.nrm_default_batch_params(ctypes.byref(cfg.batch_params))
             for k, v in batch_params.items():

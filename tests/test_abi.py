@@ -153,7 +153,8 @@ def test_server_config_validation_before_any_hip_call(lib):
     h = ctypes.c_void_p()
     for field, bad in (("slots", 0), ("slots", 65), ("budget_bytes", 0), ("max_batch_rows", 0),
                        ("max_batch_elems", 0), ("batching", 2), ("graph", 5), ("accum", 3),
-                       ("hold_outputs", 7), ("use_batch_params", 2), ("single_plain", 2), ("spread", -1)):
+                       ("hold_outputs", 7), ("use_batch_params", 2), ("single_plain", 2), ("spread", -1),
+                       ("idle_spin_us", -1), ("idle_spin_us", 1000001), ("min_batch_rows", 0)):
         c = L.NrmServerConfig()
         lib.nrm_server_default_config(ctypes.byref(c))
         setattr(c, field, bad)

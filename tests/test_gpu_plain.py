@@ -49,11 +49,56 @@ def test_brute_force_naive_1024():
     assert_f32_close(got, ref, what="naive n=1024")
 
 
+SMALL_CTX = {}
+
+
+@pytest.mark.parametrize("small", [True, False], ids=["default", "two_kernels"])
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 255, 256, 257, 1000,
-                               1023, 1025, 4095, 4097, 65535, 65537, 262143, 1000003, 3000017])
-def test_sizes_and_ragged_tails(n):
+                               1023, 1025, 4095, 4097, 65535, 65536, 65537, 262143, 1000003, 3000017])
+def test_sizes_and_ragged_tails(n, small):
+    """Every size through the default launch (n <= 2^16: one block holding
+    the input in registers) and with the one-block form off (two kernels)."""
+    if small not in SMALL_CTX:
+        SMALL_CTX[small] = api.Context() if small else api.Context(small_n=0)
     x = synth.lognormal_f32(n, 10 + n % 97, 1.0)
-    assert_f32_close(run_f32(x), oracle.normalize(x), what="n=%d" % n)
+    assert_f32_close(run_f32(x, SMALL_CTX[small]), oracle.normalize(x), what="n=%d small=%s" % (n, small))
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_small_path_two_byte_inputs(accum, dt):
+    """2-byte inputs through the one-block form (8 vectors per thread), to
+    binary32 and to their own type, at the form's capacity and below."""
+    for n in (1, 777, 65536):
+        x = synth.lognormal_f32(n, 20 + n % 13, 1.0)
+        bits = synth.f32_to_bf16_bits(x) if dt == "bf16" else synth.f32_to_f16_bits(x)
+        tdt = torch.bfloat16 if dt == "bf16" else torch.float16
+        inp = gpu(bits.view(np.int16)).view(tdt)
+        ref = oracle.normalize(bits, dt)
+        out32 = torch.empty(n, device=DEV)
+        api.normalize(out32, inp, accum=accum)
+        out16 = torch.empty_like(inp)
+        api.normalize(out16, inp, accum=accum)
+        torch.cuda.synchronize()
+        assert_f32_close(out32.cpu().numpy(), ref, what="%s->f32 n=%d" % (dt, n))
+        if dt == "bf16":
+            got = bf16_bits_to_f64(out16.view(torch.int16).cpu().numpy().view(np.uint16))
+            assert_within_ulp(got, ref, ulp_bf16, what="bf16->bf16 n=%d" % n)
+        else:
+            from parity_util import ulp_f16
+            assert_within_ulp(out16.cpu().numpy().astype(np.float64), ref, ulp_f16, what="f16->f16 n=%d" % n)
+
+
+def test_small_path_in_place_and_last_sum():
+    x = synth.uniform_f32(50_000, 21)
+    ctx = api.Context()
+    t = gpu(x)
+    api.normalize(t, t, ctx=ctx)
+    torch.cuda.synchronize()
+    assert_f32_close(t.cpu().numpy(), oracle.normalize(x), what="in place")
+    _, s_ref = oracle.normalize(x, return_sum=True)
+    assert abs(ctx.last_sum() - s_ref) <= 4e-6 * s_ref
+    ctx.close()
 
 
 def test_single_element_is_exactly_one():
@@ -180,7 +225,7 @@ PARAM_SETS = [
 
 @pytest.mark.parametrize("params", PARAM_SETS, ids=lambda p: ",".join("%s=%s" % kv for kv in p.items()))
 def test_launch_parameters(params):
-    ctx = api.Context(**params)
+    ctx = api.Context(**dict(params, small_n=0))  # the two kernels at every size
     for n, seed in ((1_000_003, 30), (4097, 31), (1 << 20, 32)):
         x = synth.lognormal_f32(n, seed, 1.0)
         assert_f32_close(run_f32(x, ctx), oracle.normalize(x), what="%s n=%d" % (params, n))
@@ -264,14 +309,16 @@ def test_parameter_validation():
     for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(grid=0),
                 dict(layout=3), dict(map_layout=-1), dict(max_height=23), dict(max_height=49),
                 dict(reverse_map=2), dict(map_nt=-1), dict(tile_log2=9), dict(tile_log2=23),
-                dict(fused_combine=2)):
+                dict(fused_combine=2), dict(small_n=-1)):
         with pytest.raises(L.NrmError):
             ctx.set_params(**bad)
         assert ctx.get_params() == good, bad
     p = L.NrmParams()
     assert L.lib().nrm_default_params(ctypes.byref(p)) == L.NRM_OK
     assert {f: getattr(p, f) for f, _ in L.NrmParams._fields_ if f != "reserved"} == good
-    p.reserved[0] = 1
+    p.small_n = -1
+    assert L.lib().nrm_set_params(ctx.handle, ctypes.byref(p)) == L.NRM_EINVAL
+    p.small_n = (1 << 16) + 1
     assert L.lib().nrm_set_params(ctx.handle, ctypes.byref(p)) == L.NRM_EINVAL
     ctx.close()
 

@@ -62,10 +62,10 @@ def test_mix_matches_oracle_and_alone(batching, spread):
     offs = pool.offsets(ns, 8)
     ptrs = pool.pointers(dts, offs)
     ids = np.arange(ns.size)
-    # groups of one run the batched kernels too, so that alone and in the mix
+    # groups of any size run the batched kernels, so that alone and in the mix
     # the same kernel computes each request (bitwise comparison below)
     srv = serve.Server(slots=3, hold_outputs=True, batching=batching, max_batch_rows=32, single_plain=False,
-                       spread=spread)
+                       spread=spread, min_batch_rows=1)
     srv.submit(ids, ptrs, ns, dts, dts)
     comps = srv.wait_all(ns.size)
     assert sorted(c[0] for c in comps) == list(ids)
@@ -79,7 +79,8 @@ def test_mix_matches_oracle_and_alone(batching, spread):
     assert srv.stats()["budget_used"] == 0
     srv.close()
     # each request alone, on a fresh server with the same configuration
-    solo = serve.Server(slots=1, hold_outputs=True, batching=batching, max_batch_rows=32, single_plain=False)
+    solo = serve.Server(slots=1, hold_outputs=True, batching=batching, max_batch_rows=32, single_plain=False,
+                        min_batch_rows=1)
     for i in range(0, ns.size, 7):
         solo.submit([i], [ptrs[i]], [ns[i]], [dts[i]], [dts[i]])
         (c,) = solo.wait_all(1)

@@ -98,8 +98,9 @@ typedef struct {
   int32_t map_nt;       /* 1: non-temporal hint on the map's loads */
   int32_t reverse_map;  /* 1: each block walks its share from the end (reuse of recently read lines) */
   int32_t reduce_keep_mib; /* 0..4096: the reduce reads the last this many MiB of the input with a
-                              temporal hint (the rest non-temporal), so that a reverse map may find
-                              them in the last-level cache */
+                              temporal hint (the rest non-temporal), so that the map finds them in
+                              the last-level cache (256 MB on MI355X: a larger tail thrashes it and
+                              gains nothing) */
   int32_t tile_log2;    /* layout TILE (either kernel): log2 of the elements per tile, 10..22 */
   int32_t fused_combine;/* 1: the reduce ends without a grid-wide ticket or fence and every map
                            block merges the reduce's partials itself, in the same fixed order
@@ -129,7 +130,10 @@ typedef struct {
   int32_t map_grid;    /* persistent blocks G of the divide phase: the long rows' concatenation is
                           cut into about G * m equal chunks of at most about one tile each, so
                           that every block divides the same number of elements */
-  int32_t reserved[3];
+  int32_t keep_mib;    /* 0..4096: phase 1 reads the long rows' last tiles, up to this many MiB,
+                          with a temporal hint (the rest non-temporal), so that the divide phase
+                          finds them in the last-level cache (256 MB on MI355X) */
+  int32_t reserved[2];
 } nrm_batch_params;
 
 /* One row of a batch given as a table: `in` and `out` are device arrays of

@@ -52,7 +52,8 @@ class NrmBatchParams(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("map_block", ctypes.c_int32),
         ("map_grid", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("keep_mib", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -91,6 +91,7 @@ struct BatchArgs {
   int64_t short_max;     // rows with n <= short_max take one pass
   int64_t map_grid;      // phase 2 blocks: the chunks are sized to a multiple of it
   int64_t min_chunk;     // elements of one full phase-2 block-iteration: the smallest chunk
+  int64_t keep_tiles;    // phase 1 reads the last this many long-row tiles with a temporal hint
 };
 
 struct BatchPlan {

@@ -558,8 +558,9 @@ __device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, R
 
 // ---- tiles of long rows ------------------------------------------------------------
 
-// Sum of elements [b, e) of a row; valid in thread 0.
-template <int DTI, int ACC, int U>
+// Sum of elements [b, e) of a row; valid in thread 0. NT: non-temporal loads
+// (a temporal tile stays in the last-level cache for phase 2).
+template <int DTI, int ACC, int U, bool NT>
 __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, int64_t e,
                                                 Acc<ACC>* slots) {
   constexpr int VEC = Elem<DTI>::VEC;
@@ -586,7 +587,7 @@ __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, i
     if (base + step <= g.nvec) {
       u4 r[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = load_vec<true>(p + base + u * B);
+      for (int u = 0; u < U; ++u) r[u] = load_vec<NT>(p + base + u * B);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         float x[VEC];
@@ -599,7 +600,7 @@ __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, i
       for (int u = 0; u < U; ++u) {
         if (base + u * B + (int64_t)threadIdx.x < g.nvec) {
           float x[VEC];
-          widen<DTI>(load_vec<true>(p + base + u * B), x);
+          widen<DTI>(load_vec<NT>(p + base + u * B), x);
 #pragma unroll
           for (int c = 0; c < VEC; ++c) acc[(u * VEC + c) % NA].add(x[c]);
         }
@@ -694,16 +695,16 @@ __device__ __forceinline__ void dispatch_single(const RowDesc& d, Acc<ACC>* slot
   }
 }
 
-template <int ACC, int U>
+template <int ACC, int U, bool NT>
 __device__ __forceinline__ Acc<ACC> dispatch_tile_reduce(const RowDesc& d, int64_t b, int64_t e,
                                                          Acc<ACC>* slots) {
   if constexpr (ACC == ACC_SOFTMAX) {
-    return tile_reduce<NRM_F32, ACC, U>(d.in, b, e, slots);
+    return tile_reduce<NRM_F32, ACC, U, NT>(d.in, b, e, slots);
   } else {
     switch (d.in_dt) {
-      case NRM_F32: return tile_reduce<NRM_F32, ACC, U>(d.in, b, e, slots);
-      case NRM_BF16: return tile_reduce<NRM_BF16, ACC, U>(d.in, b, e, slots);
-      default: return tile_reduce<NRM_F16, ACC, U>(d.in, b, e, slots);
+      case NRM_F32: return tile_reduce<NRM_F32, ACC, U, NT>(d.in, b, e, slots);
+      case NRM_BF16: return tile_reduce<NRM_BF16, ACC, U, NT>(d.in, b, e, slots);
+      default: return tile_reduce<NRM_F16, ACC, U, NT>(d.in, b, e, slots);
     }
   }
 }
@@ -737,6 +738,7 @@ __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
   __shared__ RowRes s_bcast;
   const int64_t n_items = a.cnt[CNT_ITEMS];
   const int64_t n_long = a.cnt[CNT_LONG_ITEMS];
+  const int64_t keep_item = n_long - a.keep_tiles;
   float* lse = lse_out(a);
   Acc<ACC>* part = reinterpret_cast<Acc<ACC>*>(a.partials);
   const int64_t G = gridDim.x;
@@ -760,7 +762,10 @@ __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
     } else {
       const int64_t b = (int64_t)it.tile * a.tile;
       const int64_t e = b + a.tile < d.n ? b + a.tile : d.n;
-      Acc<ACC> p = dispatch_tile_reduce<ACC, U>(d, b, e, slots);
+      // the last keep_tiles tiles are read with a temporal hint: phase 2
+      // finds them in the last-level cache
+      const Acc<ACC> p = item >= keep_item ? dispatch_tile_reduce<ACC, U, false>(d, b, e, slots)
+                                           : dispatch_tile_reduce<ACC, U, true>(d, b, e, slots);
       if (threadIdx.x == 0) part[item] = p;  // read after the kernel boundary
     }
     if (next >= n_items) break;

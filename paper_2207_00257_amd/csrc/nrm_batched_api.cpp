@@ -47,6 +47,7 @@ nrm_batch_params default_batch_params() {
   p.graph = 0;
   p.map_block = 1024;
   p.map_grid = 1024;
+  p.keep_mib = 256;
   return p;
 }
 
@@ -60,6 +61,7 @@ int check_batch_params(const nrm_batch_params& p) {
   if (p.grid < 1 || p.grid > (1 << 20)) return fail(NRM_EINVAL, "grid must be 1..2^20");
   if (p.tile_log2 < 10 || p.tile_log2 > 22) return fail(NRM_EINVAL, "tile_log2 must be 10..22");
   if (p.graph != 0 && p.graph != 1) return fail(NRM_EINVAL, "graph must be 0 or 1");
+  if (p.keep_mib < 0 || p.keep_mib > 4096) return fail(NRM_EINVAL, "keep_mib must be 0..4096");
   for (int r : p.reserved)
     if (r != 0) return fail(NRM_EINVAL, "reserved fields must be zero");
   // a tile's per-thread summation tree must stay within the plain path's
@@ -206,6 +208,8 @@ BatchArgs args_of(const nrm_ctx* c) {
   a.short_max = short_max_of(c->bparams);
   a.map_grid = c->bparams.map_grid;
   a.min_chunk = (int64_t)c->bparams.map_block * c->bparams.map_unroll * 4;
+  // tiles counted at 4 bytes per element: at most keep_mib MiB for any dtype
+  a.keep_tiles = ((int64_t)c->bparams.keep_mib << 20) / (a.tile * 4);
   return a;
 }
 

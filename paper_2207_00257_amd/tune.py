@@ -80,8 +80,8 @@ def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=Fa
     combine moves work from the reduce into the map): the reduce's shape
     (layout, block, unroll, grid, load hint, fused combine) with the map at
     its defaults; the map's shape (layout, block, unroll, grid, load hint,
-    direction) with the best reduce; then the tile size and the temporal tail
-    of the reduce."""
+    direction) with the best reduce; then the tile size, and the temporal tail
+    of the reduce jointly with the fastest reduce shapes."""
     import torch
 
     from . import api, synth
@@ -137,10 +137,25 @@ def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=Fa
     if best["layout"] == 2 or best["map_layout"] == 2:
         for tl in range(12, 20):
             measure(dict(best, tile_log2=tl), "tile")
-    for keep, rev, nt in itertools.product((0, 64, 128, 192, 256, 384), (0, 1), (0, 1)):
-        if (nt == 0 and keep) or (rev and best["map_layout"] == 2):
-            continue  # all of the reduce's loads are temporal anyway / no reverse walk when tiled
-        measure(dict(best, reduce_keep_mib=keep, reverse_map=rev, reduce_nt=nt), "keep")
+    # The temporal tail couples the kernels: the map finds it in the
+    # last-level cache, so a reduce shape that is fastest on its own can lose
+    # overall without one. The tail is therefore swept with the fastest few
+    # reduce shapes of the first stage, not only with the shape chosen there.
+    shape_keys = ("layout", "block", "unroll", "grid", "fused_combine")
+    shapes = [{k: best[k] for k in shape_keys}]
+    for r in sorted((r for r in table if r["kernel"] == "reduce" and r["params"]["reduce_nt"]),
+                    key=lambda r: r["reduce_ms"]):
+        s = {k: r["params"][k] for k in shape_keys}
+        if s not in shapes:
+            shapes.append(s)
+        if len(shapes) == (3 if quick else 7):
+            break
+    best_m = dict(best)
+    for shape in shapes:
+        for keep, rev, nt in itertools.product((0, 64, 128, 192, 224, 256, 288, 384), (0, 1), (0, 1)):
+            if (nt == 0 and keep) or (rev and best_m["map_layout"] == 2):
+                continue  # all of the reduce's loads are temporal anyway / no reverse walk when tiled
+            measure(dict(best_m, reduce_keep_mib=keep, reverse_map=rev, reduce_nt=nt, **shape), "keep")
     # the leaders again, interleaved round by round with more repetitions, so
     # that neither a single noisy measurement nor drift picks the winner
     leaders = []

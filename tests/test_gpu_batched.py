@@ -1,5 +1,7 @@
 """GPU parity of the ragged batched path (CSR and row-table forms, with and
 without hipGraph replay) against the FP64 oracle, through the C ABI."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -68,6 +70,9 @@ BATCH_PARAMS = [
     dict(graph=1, block=512, tile_log2=18, short_regs=4),
     dict(map_block=64, map_grid=3, map_unroll=8),
     dict(map_block=1024, map_grid=5000, tile_log2=11, grid=64),
+    dict(keep_mib=0),                   # every tile non-temporal
+    dict(keep_mib=1, tile_log2=10),     # the last 256 tiles temporal, the rest not
+    dict(keep_mib=4096, graph=1),       # every tile temporal
 ]
 
 
@@ -82,6 +87,23 @@ def test_launch_parameters(params):
     got = run_csr(x, offs, ctx).cpu().numpy()
     check_rows(got, x, offs, str(params))
     assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+def test_batch_parameter_validation():
+    ctx = api.Context()
+    good = ctx.get_batch_params()
+    for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(short_regs=0),
+                dict(grid=0), dict(map_grid=0), dict(tile_log2=9), dict(tile_log2=23), dict(graph=2),
+                dict(keep_mib=-1), dict(keep_mib=4097)):
+        with pytest.raises(L.NrmError):
+            ctx.set_batch_params(**bad)
+        assert ctx.get_batch_params() == good, bad
+    p = L.NrmBatchParams()
+    assert L.lib().nrm_default_batch_params(ctypes.byref(p)) == L.NRM_OK
+    assert {f: getattr(p, f) for f, _ in L.NrmBatchParams._fields_ if f != "reserved"} == good
+    p.reserved[1] = 1
+    assert L.lib().nrm_set_batch_params(ctx.handle, ctypes.byref(p)) == L.NRM_EINVAL
     ctx.close()
 
 

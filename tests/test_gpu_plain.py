@@ -309,7 +309,7 @@ def test_parameter_validation():
     for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(grid=0),
                 dict(layout=3), dict(map_layout=-1), dict(max_height=23), dict(max_height=49),
                 dict(reverse_map=2), dict(map_nt=-1), dict(tile_log2=9), dict(tile_log2=23),
-                dict(fused_combine=2), dict(small_n=-1)):
+                dict(fused_combine=2), dict(small_n=-1), dict(reduce_keep_mib=-1), dict(reduce_keep_mib=4097)):
         with pytest.raises(L.NrmError):
             ctx.set_params(**bad)
         assert ctx.get_params() == good, bad

@@ -558,6 +558,24 @@ __device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, R
 
 // ---- tiles of long rows ------------------------------------------------------------
 
+// Softmax chains of one thread that share one exponent k (every chain's k is
+// the same): raised once per loop iteration to cover the iteration's largest
+// element, the chains' sums rescaled exactly, so that each element then costs
+// one fused multiply-add, one exp2 and one addition instead of a compare and
+// a branch of its own.
+template <int NA>
+__device__ __forceinline__ void raise_shared(Acc<ACC_SOFTMAX> (&acc)[NA], float m) {
+  const float y = m * LOG2E_F;
+  if (y > acc[0].k) {
+    const float kn = __builtin_ceilf(y), d = acc[0].k - kn;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      acc[j].s = scale_pow2(acc[j].s, d);
+      acc[j].k = kn;
+    }
+  }
+}
+
 // Sum of elements [b, e) of a row; valid in thread 0. NT: non-temporal loads
 // (a temporal tile stays in the last-level cache for phase 2).
 template <int DTI, int ACC, int U, bool NT>
@@ -588,12 +606,33 @@ __device__ __forceinline__ Acc<ACC> tile_reduce(const char* in_row, int64_t b, i
       u4 r[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) r[u] = load_vec<NT>(p + base + u * B);
+      if constexpr (ACC == ACC_SOFTMAX) {
+        // full iterations keep the chains' k equal (see raise_shared); only
+        // the last iteration of a tile can be partial, and it and the head
+        // and tail raise their chains element by element
+        float x[U][VEC];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        float x[VEC];
-        widen<DTI>(r[u], x);
+        for (int u = 0; u < U; ++u) widen<DTI>(r[u], x[u]);
+        float m = x[0][0];
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) acc[(u * VEC + c) % NA].add(x[c]);
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) m = fmaxf(m, x[u][c]);
+        raise_shared<NA>(acc, m);
+        const float nk = -acc[0].k;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int c = 0; c < VEC; ++c)
+            acc[(u * VEC + c) % NA].s += __builtin_amdgcn_exp2f(__builtin_fmaf(x[u][c], LOG2E_F, nk));
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          float x[VEC];
+          widen<DTI>(r[u], x);
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) acc[(u * VEC + c) % NA].add(x[c]);
+        }
       }
     } else {
 #pragma unroll

@@ -87,7 +87,8 @@ struct BatchArgs {
   int64_t cap_rows;
   int64_t cap_items;
   int64_t cap_chunks;
-  int64_t tile;          // elements per tile of a long row
+  int64_t tile;          // elements per tile of a long row: 2^tile_log2
+  int tile_log2;
   int64_t short_max;     // rows with n <= short_max take one pass
   int64_t map_grid;      // phase 2 blocks: the chunks are sized to a multiple of it
   int64_t min_chunk;     // elements of one full phase-2 block-iteration: the smallest chunk

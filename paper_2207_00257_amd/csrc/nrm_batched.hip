@@ -3,14 +3,15 @@
 // of the element-wise divide exactly as in the plain path (arXiv 2207.00257,
 // Fig. 1 and Sec. IV-C), in one persistent launch sequence for the batch.
 //
-//   batch_plan_kernel    one block: resolves the row table (from CSR offsets
-//                        or a descriptor table), validates it, classifies
-//                        rows, and by exclusive scans writes the work-item
+//   batch_plan_kernel    one block per round of 1024 rows: resolves the row
+//                        table (from CSR offsets or a descriptor table),
+//                        validates it, classifies rows, and by exclusive
+//                        scans writes its round's part of the work-item
 //                        table (first the tiles of every long row,
 //                        ceil(n / tile) each and consecutive per row, then
-//                        one item per short row, n <= short_max), the long
-//                        rows' descriptors and starts, and phase 2's chunk
-//                        table.
+//                        one item per short row, n <= short_max), of the
+//                        long rows' descriptors and starts, and of phase 2's
+//                        chunk table.
 //   batch_phase1_kernel  persistent blocks walk the items. A single-pass item
 //                        keeps its row in registers: one read, block sum,
 //                        divide, one write. A tile item writes its partial.
@@ -126,8 +127,18 @@ constexpr int PLAN_THREADS = 1024;
 
 __device__ __forceinline__ bool valid_dt(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
 
-__device__ __forceinline__ int64_t long_tiles(int64_t n, int64_t short_max, int64_t tile) {
-  return n <= short_max ? 0 : (n + tile - 1) / tile;
+// Tiles are 2^tile_log2 elements: a shift, not a 64-bit division (which the
+// GPU emulates in about a hundred instructions, per lane).
+__device__ __forceinline__ int64_t long_tiles(int64_t n, int64_t short_max, int tile_log2) {
+  return n <= short_max ? 0 : (n + (int64_t(1) << tile_log2) - 1) >> tile_log2;
+}
+
+// A value the same in every lane, moved to scalar registers, so that
+// arithmetic on it (a 64-bit division, say) runs once per wavefront.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // The raw description of one row: its two CSR offsets, or its table entry.
@@ -269,8 +280,8 @@ __device__ __forceinline__ void scan_counts(int64_t (&v)[NCNT], int64_t (&last)[
   last[NCNT - 1] = (int64_t)lane_value64(w, PLAN_WAVES - 1);
 }
 
-__device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int64_t tile, int64_t (&v)[NCNT]) {
-  v[0] = long_tiles(n, short_max, tile);
+__device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int tile_log2, int64_t (&v)[NCNT]) {
+  v[0] = long_tiles(n, short_max, tile_log2);
   v[1] = (n > 0 && n <= short_max) ? 1 : 0;
   v[2] = v[0] > 0 ? 1 : 0;
   v[3] = v[0] > 0 ? n : 0;
@@ -293,18 +304,24 @@ __device__ __forceinline__ void last_le(const T* ex, const int64_t (&x)[S], int 
 
 constexpr int PLAN_SEARCHES = 4;  // binary searches in flight per thread
 
-// Rows are taken PLAN_THREADS at a time, row q * PLAN_THREADS + t in thread t
-// (coalesced reads of the offsets or of the table).
+// Rows are taken PLAN_THREADS at a time ("rounds"), row q * PLAN_THREADS + t
+// in thread t (coalesced reads of the offsets or of the table). Block b owns
+// round b: it alone stores that round's resolved rows and writes its part of
+// the tables; blocks past the last round return at once (the grid is sized
+// for the workspace's row capacity, so that a captured graph fits any batch).
 //
-// Pass 1 resolves and validates every row and counts, by a block scan per
-// round, its tile items, single-pass item, long-row slot and long-row
-// elements. The first PLAN_ROUNDS rounds keep their scans in registers; later
-// rounds are scanned again in pass 2.
+// Pass 1 (every block, every round): resolve and validate the round's rows
+// and count, by a block scan, their tile items, single-pass items, long rows
+// and long-row elements. A block needs the totals before its own round and
+// the grand totals, so each block scans all rounds itself (a few us per
+// round) and the blocks never wait on one another. Rows are fetched
+// PLAN_ROUNDS rounds at a time (one round trip).
 //
-// Pass 2 writes, per round: each short row's item and each long row's first
+// Pass 2 (own round only): each short row's item and each long row's first
 // item, descriptor and start in the long rows' concatenation (one thread per
-// row); then, cooperatively, the round's tile items and the chunk table, each
-// entry finding its row by a binary search over the round's scan in LDS.
+// row); then, cooperatively, the round's tile items and its chunks of the
+// chunk table, each entry finding its row by a binary search over the
+// round's scan in LDS.
 //
 // Phase 2 covers the concatenation of the long rows in equal chunks, about
 // G * m of them for G phase-2 blocks (m chunks per block, each at most about
@@ -316,38 +333,44 @@ constexpr int PLAN_ROUNDS = 4;
 __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   __shared__ int64_t sc[NCNT][PLAN_WAVES];
   __shared__ BatchHeader hs;
-  __shared__ int64_t ks[PLAN_ROUNDS + 1][NCNT];  // totals before each kept round
-  __shared__ int32_t ex_tile[PLAN_THREADS];      // in-round exclusive scans
+  __shared__ int32_t ex_tile[PLAN_THREADS];  // the own round's exclusive scans
   __shared__ int32_t ex_lrow[PLAN_THREADS];
   __shared__ int64_t ex_elem[PLAN_THREADS];
   const int t = threadIdx.x;
+  const int64_t own = blockIdx.x;
   if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
   lds_barrier();
   const BatchHeader* h = &hs;
   const int64_t nrows = h->nrows;
   if (nrows < 0 || nrows > a.cap_rows) {
-    if (t == 0) {
+    if (own == 0 && t == 0) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
       for (int k = 0; k < CNT_COUNT; ++k) a.cnt[k] = 0;
     }
     return;
   }
   const int64_t rounds = (nrows + PLAN_THREADS - 1) / PLAN_THREADS;
+  if (own > 0 && own >= rounds) return;  // block 0 stays: it writes the counters
   int err = 0;
-  // validate row q * PLAN_THREADS + t (fetched as x) and store it; n = 0 if
-  // invalid or past the end
-  auto resolve = [&](int64_t q, const RawRow& x) -> RowDesc {
+  // validate row q * PLAN_THREADS + t (fetched as x); n = 0 if invalid or
+  // past the end. Only the owner of the round stores the row and records
+  // its errors.
+  auto resolve = [&](int64_t q, const RawRow& x, bool mine) -> RowDesc {
     const int64_t r = q * PLAN_THREADS + t;
     RowDesc d;
     d.n = 0;
     if (r >= nrows) return d;
-    d = resolve_row(h, x, err);
-    if (long_tiles(d.n, a.short_max, a.tile) > MAX_ROW_TILES) {
-      err |= NRM_DEVERR_ROW;
+    int e = 0;
+    d = resolve_row(h, x, e);
+    if (long_tiles(d.n, a.short_max, a.tile_log2) > MAX_ROW_TILES) {
+      e |= NRM_DEVERR_ROW;
       d.n = 0;
     }
-    a.rows[r] = d;
-    if (d.n == 0 && h->lse) h->lse[r] = -__builtin_inff();  // the log of an empty sum
+    if (mine) {
+      err |= e;
+      a.rows[r] = d;
+      if (d.n == 0 && h->lse) h->lse[r] = -__builtin_inff();  // the log of an empty sum
+    }
     return d;
   };
   auto fetch = [&](int64_t q) {
@@ -356,42 +379,38 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     if (r < nrows) x = fetch_row(h, r);
     return x;
   };
-  auto scan_round = [&](int64_t n, int64_t (&incl)[NCNT], int64_t (&last)[NCNT]) {
-    row_counts(n, a.short_max, a.tile, incl);
-    scan_counts(incl, last, sc);
-    lds_barrier();  // sc is rewritten by the next scan
-  };
 
-  // pass 1; the kept rounds' rows are all fetched first (one round trip)
+  // pass 1
   int64_t carry[NCNT] = {0, 0, 0, 0};
-  RowDesc kd[PLAN_ROUNDS];
-  int64_t ki3[PLAN_ROUNDS];
-  int32_t ki0[PLAN_ROUNDS], ki1[PLAN_ROUNDS], ki2[PLAN_ROUNDS];
-  RawRow fetched[PLAN_ROUNDS];
+  int64_t c_own[NCNT] = {0, 0, 0, 0}, incl_own[NCNT] = {0, 0, 0, 0}, last_own[NCNT] = {0, 0, 0, 0};
+  RowDesc d_own;
+  d_own.n = 0;
+  for (int64_t q0 = 0; q0 < rounds; q0 += PLAN_ROUNDS) {
+    RawRow fetched[PLAN_ROUNDS];
 #pragma unroll
-  for (int q = 0; q < PLAN_ROUNDS; ++q)
-    if (q < rounds) fetched[q] = fetch(q);
+    for (int k = 0; k < PLAN_ROUNDS; ++k)
+      if (q0 + k < rounds) fetched[k] = fetch(q0 + k);
 #pragma unroll
-  for (int q = 0; q < PLAN_ROUNDS; ++q) {
-    if (t == 0)
-      for (int k = 0; k < NCNT; ++k) ks[q][k] = carry[k];
-    if (q < rounds) {
-      int64_t incl[NCNT], last[NCNT];
-      kd[q] = resolve(q, fetched[q]);
-      scan_round(kd[q].n, incl, last);
-      ki0[q] = (int32_t)incl[0];  // at most PLAN_THREADS * MAX_ROW_TILES
-      ki1[q] = (int32_t)incl[1];
-      ki2[q] = (int32_t)incl[2];
-      ki3[q] = incl[3];
-      for (int k = 0; k < NCNT; ++k) carry[k] += last[k];
+    for (int k = 0; k < PLAN_ROUNDS; ++k) {
+      const int64_t q = q0 + k;
+      if (q < rounds) {
+        const bool mine = q == own;
+        const RowDesc d = resolve(q, fetched[k], mine);
+        int64_t incl[NCNT], last[NCNT];
+        row_counts(d.n, a.short_max, a.tile_log2, incl);
+        scan_counts(incl, last, sc);
+        lds_barrier();  // sc is rewritten by the next scan
+        if (mine) {
+          d_own = d;
+          for (int c = 0; c < NCNT; ++c) {
+            c_own[c] = carry[c];
+            incl_own[c] = incl[c];
+            last_own[c] = last[c];
+          }
+        }
+        for (int c = 0; c < NCNT; ++c) carry[c] += last[c];
+      }
     }
-  }
-  if (t == 0)
-    for (int k = 0; k < NCNT; ++k) ks[PLAN_ROUNDS][k] = carry[k];
-  for (int64_t q = PLAN_ROUNDS; q < rounds; ++q) {
-    int64_t incl[NCNT], last[NCNT];
-    scan_round(resolve(q, fetch(q)).n, incl, last);
-    for (int k = 0; k < NCNT; ++k) carry[k] += last[k];
   }
   const int64_t total_long = carry[0], total = carry[0] + carry[1], n_lrows = carry[2], elems = carry[3];
 
@@ -408,20 +427,22 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     n_chunks = (elems + chunk - 1) / chunk;
   }
 
-  // pass 2
-  auto place_round = [&](int64_t q, const RowDesc& d, const int64_t (&incl)[NCNT], const int64_t (&c)[NCNT],
-                         const int64_t (&last)[NCNT]) {
-    const int64_t r = q * PLAN_THREADS + t;
+  // pass 2, the own round
+  if (total <= a.cap_items && own < rounds) {
+    const int64_t q = own, r = q * PLAN_THREADS + t;
+    const int64_t(&incl)[NCNT] = incl_own;
+    const int64_t(&c)[NCNT] = c_own;
+    const int64_t(&last)[NCNT] = last_own;
     int64_t v[NCNT];
-    row_counts(d.n, a.short_max, a.tile, v);
-    ex_tile[t] = (int32_t)(incl[0] - v[0]);
+    row_counts(d_own.n, a.short_max, a.tile_log2, v);
+    ex_tile[t] = (int32_t)(incl[0] - v[0]);  // at most PLAN_THREADS * MAX_ROW_TILES
     ex_lrow[t] = (int32_t)(incl[2] - v[2]);
     ex_elem[t] = incl[3] - v[3];
     if (v[1]) a.items[total_long + c[1] + incl[1] - 1] = Item{(int32_t)r, 0};
     if (v[2]) {
       const int64_t k = c[2] + incl[2] - 1;
       a.lrow_first[k] = c[0] + incl[0] - v[0];
-      a.lrows[k] = d;
+      a.lrows[k] = d_own;
       a.lstart[k] = c[3] + incl[3] - v[3];
     }
     lds_barrier();
@@ -437,50 +458,24 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
         if (i0 + u * PLAN_THREADS < last[0])
           a.items[c[0] + x[u]] = Item{(int32_t)(q * PLAN_THREADS + j[u]), (int32_t)(x[u] - ex_tile[j[u]])};
     }
-    // the chunks whose first element lies in this round's long rows
-    int64_t ce = (c[3] + last[3] + chunk - 1) / chunk;
+    // the chunks whose first element lies in this round's long rows (c[],
+    // last[] and chunk are the same in every lane: divide once per wavefront)
+    const int64_t c3 = uniform64(c[3]), ch = uniform64(chunk);
+    int64_t ce = (c3 + uniform64(last[3]) + ch - 1) / ch;
     if (ce > n_chunks) ce = n_chunks;
-    for (int64_t c0 = (c[3] + chunk - 1) / chunk + t; c0 < ce; c0 += SN * PLAN_THREADS) {
+    for (int64_t c0 = (c3 + ch - 1) / ch + t; c0 < ce; c0 += SN * PLAN_THREADS) {
       int64_t x[SN];
       int j[SN];
 #pragma unroll
-      for (int u = 0; u < SN; ++u) x[u] = c0 + u * PLAN_THREADS < ce ? (c0 + u * PLAN_THREADS) * chunk - c[3] : 0;
+      for (int u = 0; u < SN; ++u) x[u] = c0 + u * PLAN_THREADS < ce ? (c0 + u * PLAN_THREADS) * ch - c3 : 0;
       last_le<SN>(ex_elem, x, j);
 #pragma unroll
       for (int u = 0; u < SN; ++u)
         if (c0 + u * PLAN_THREADS < ce) a.chunk_lrow[c0 + u * PLAN_THREADS] = (int32_t)(c[2] + ex_lrow[j[u]]);
     }
-    lds_barrier();  // the LDS scans are rewritten by the next round
-  };
-  lds_barrier();  // ks is complete
-  if (total <= a.cap_items) {
-#pragma unroll
-    for (int q = 0; q < PLAN_ROUNDS; ++q) {
-      if (q < rounds) {
-        const int64_t incl[NCNT] = {ki0[q], ki1[q], ki2[q], ki3[q]};
-        int64_t c[NCNT], last[NCNT];
-        for (int k = 0; k < NCNT; ++k) {
-          c[k] = ks[q][k];
-          last[k] = ks[q + 1][k] - ks[q][k];
-        }
-        place_round(q, kd[q], incl, c, last);
-      }
-    }
-    int64_t c[NCNT];
-    for (int k = 0; k < NCNT; ++k) c[k] = ks[PLAN_ROUNDS][k];
-    for (int64_t q = PLAN_ROUNDS; q < rounds; ++q) {
-      const int64_t r = q * PLAN_THREADS + t;
-      RowDesc d;
-      d.n = 0;
-      if (r < nrows) d = a.rows[r];  // written by this thread in pass 1
-      int64_t incl[NCNT], last[NCNT];
-      scan_round(d.n, incl, last);
-      place_round(q, d, incl, c, last);
-      for (int k = 0; k < NCNT; ++k) c[k] += last[k];
-    }
   }
   if (err) atomicOr(a.error, err);
-  if (t == 0) {
+  if (own == 0 && t == 0) {
     if (total > a.cap_items) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
       for (int k = 0; k < CNT_COUNT; ++k) a.cnt[k] = 0;
@@ -828,7 +823,7 @@ __global__ void __launch_bounds__(1024) batch_rowsum_kernel(BatchArgs a) {
   const Acc<ACC>* part = reinterpret_cast<const Acc<ACC>*>(a.partials);
   for (int64_t k = blockIdx.x; k < n_lrows; k += gridDim.x) {
     const int64_t first = a.lrow_first[k];
-    const int64_t count = (a.lrows[k].n + a.tile - 1) / a.tile;
+    const int64_t count = (a.lrows[k].n + a.tile - 1) >> a.tile_log2;
     Acc<ACC> tot = combine_partials<ACC>(part + first, count, tree, tiles);
     if (threadIdx.x == 0) {
       const RowMap<ACC> f = RowMap<ACC>::of(tot);
@@ -995,7 +990,11 @@ hipError_t launch_small(const void* in, int in_dt, void* out, int out_dt, int64_
 }
 
 hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(PLAN_THREADS), 0, s, a);
+  // one block per round of the workspace's row capacity (blocks past the
+  // batch's last round return at once)
+  const int64_t plan_blocks = (a.cap_rows + PLAN_THREADS - 1) / PLAN_THREADS;
+  hipLaunchKernelGGL(batch_plan_kernel, dim3((unsigned)(plan_blocks > 0 ? plan_blocks : 1)), dim3(PLAN_THREADS), 0, s,
+                     a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (p.acc) {

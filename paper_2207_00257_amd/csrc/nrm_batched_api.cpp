@@ -205,6 +205,7 @@ BatchArgs args_of(const nrm_ctx* c) {
   a.cap_items = w.cap_items;
   a.cap_chunks = w.cap_chunks;
   a.tile = int64_t(1) << c->bparams.tile_log2;
+  a.tile_log2 = c->bparams.tile_log2;
   a.short_max = short_max_of(c->bparams);
   a.map_grid = c->bparams.map_grid;
   a.min_chunk = (int64_t)c->bparams.map_block * c->bparams.map_unroll * 4;

@@ -209,6 +209,8 @@ PARAM_SETS = [
     dict(layout=0, grid=3, unroll=1, block=64, max_height=48),
     dict(reduce_keep_mib=1, reverse_map=1),
     dict(reduce_keep_mib=4096, reverse_map=0, layout=0),
+    dict(reduce_keep_mib=0),                          # chunked, every load non-temporal
+    dict(reduce_keep_mib=2, grid=7, unroll=2),        # the temporal tail starts inside a block's chunk
     # tiled layout (2) and the fused combine
     dict(layout=2, map_layout=2),
     dict(layout=2, map_layout=2, fused_combine=1, grid=1024, map_grid=1024, block=1024, unroll=2,

@@ -175,6 +175,48 @@ def test_bad_offsets_are_flagged_and_skipped():
     ctx.close()
 
 
+def test_bad_rows_in_later_planner_rounds():
+    """Each round of 1024 rows is planned by its own block: invalid rows in
+    rounds 1 and 3 are flagged and skipped by their owners while every valid
+    row of every round is computed."""
+    lengths = synth.loguniform_lengths(3100, 95, 1, 3000)
+    lengths[[7, 2049, 3098]] = [70_000, 50_000, 90_000]  # long rows in rounds 0, 2 and 3
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 96, 1.0)
+    bad = offs.copy()
+    bad[1500] = -5          # row 1499 ends before it starts, row 1500 starts below zero
+    bad[3080] = x.size + 9  # row 3079 ends past the buffer, row 3080 starts past its end
+    ctx = api.Context()
+    got = run_csr(x, bad, ctx).cpu().numpy()
+    assert ctx.device_error() == L.NRM_EDEVICE
+    assert ctx.device_error() == L.NRM_OK  # cleared
+    skipped = {1499, 1500, 3079, 3080}
+    for r in range(lengths.size):
+        b, e = int(offs[r]), int(offs[r + 1])
+        if r in skipped:
+            assert np.all(got[b:e] == -7.0), r
+        elif e > b:
+            assert_f32_close(got[b:e], oracle.normalize(x[b:e]), what="row %d" % r)
+    ctx.close()
+
+
+def test_graph_with_spare_planner_blocks():
+    """A graph captured for a workspace of 8192 rows (eight planner blocks)
+    replayed for batches of 3100, 10 and 1024 rows: the blocks past each
+    batch's last round return at once, every row is computed."""
+    ctx = api.Context()
+    ctx.set_batch_params(graph=1)
+    ctx.batch_reserve(8192, 1 << 23)
+    for rows, seed in ((3100, 97), (10, 98), (1024, 99), (3100, 100)):
+        lengths = synth.loguniform_lengths(rows, seed, 1, 1 << 13)
+        lengths[::13] = 0
+        offs = synth.ragged_offsets(lengths)
+        x = synth.lognormal_f32(int(offs[-1]), seed + 50, 1.0)
+        check_rows(run_csr(x, offs, ctx).cpu().numpy(), x, offs, "%d rows" % rows)
+        assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
 def test_rows_table_mixed_dtypes():
     """Row-table form: each row has its own buffers and dtypes."""
     specs = [("f32", "f32", 5000), ("bf16", "bf16", 70_000), ("f16", "f32", 1234), ("bf16", "f32", 200_000),

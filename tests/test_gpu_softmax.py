@@ -100,6 +100,18 @@ def test_wide_ranges_and_shifts(sigma, shift):
     check(x, offs, got, lse, "sigma %g shift %g" % (sigma, shift))
 
 
+def test_empty_rows_in_later_planner_rounds():
+    """Empty rows in every round of 1024 rows (each round planned by its own
+    block) get lse = -inf; the other rows match the oracle."""
+    lengths = synth.loguniform_lengths(2600, 101, 1, 4000)
+    lengths[::97] = 0
+    lengths[[5, 1300, 2500]] = [60_000, 45_000, 80_000]
+    offs = csr(lengths)
+    x = synth.normal_f32(int(offs[-1]), 102, 2.0)
+    got, got_lse = run(x, offs)
+    check(x, offs, got, got_lse, "2600 rows")
+
+
 def test_in_place_and_without_lse():
     x, offs = synth.ragged_logits(64, 55, lo=1, hi=50000, sigma=2.0)
     got, _ = run(x, offs, with_lse=False, inplace=True)

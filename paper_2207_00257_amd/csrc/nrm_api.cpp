@@ -34,8 +34,8 @@ namespace {
 // non-temporal hint and that tail with a temporal one (it stays in the
 // last-level cache, where the map finds it), and ends without a grid-wide
 // ticket: every map block merges the reduce's partials itself. The map runs
-// many blocks striding over the whole input a block-iteration at a time, each
-// walking its share from the end.
+// many blocks over tiles of 2^13 elements (block b takes tiles b, b + grid,
+// ...), two 16-byte vectors per thread per iteration.
 nrm_params default_params() {
   nrm_params p;
   std::memset(&p, 0, sizeof(p));
@@ -46,11 +46,11 @@ nrm_params default_params() {
   p.reduce_nt = 1;
   p.max_height = 36;
   p.map_block = 512;
-  p.map_unroll = 4;
+  p.map_unroll = 2;
   p.map_grid = 8192;
-  p.map_layout = NRM_LAYOUT_STRIDE;
+  p.map_layout = NRM_LAYOUT_TILE;
   p.map_nt = 1;
-  p.reverse_map = 1;
+  p.reverse_map = 0;
   // the last 256 MiB read with a temporal hint stay in the 256 MB last-level
   // cache, where the map finds them (measured: 256 saves ~35 us of the map at
   // 2^28 FP32; 288 overflows the cache and saves nothing)

@@ -329,6 +329,37 @@ def test_rows_with_many_tiles():
     ctx.close()
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_random_batches_match_oracle(seed):
+    """Seeded random batches: row counts up to 3000 (one to three planner
+    rounds), lengths drawn around the boundaries the scheduler has (empty,
+    one element, the single-pass limit, whole tiles and one element either
+    side), random launch shapes, graph replay or not."""
+    rng = np.random.default_rng(1000 + seed)
+    shapes = [dict(), dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7),
+              dict(block=512, unroll=2, short_regs=2, tile_log2=13, map_grid=33), dict(graph=1, tile_log2=12),
+              dict(keep_mib=0, map_block=256, map_unroll=8, grid=100)]
+    params = shapes[seed % len(shapes)]
+    ctx = api.Context()
+    ctx.set_batch_params(**params)
+    bp = ctx.get_batch_params()
+    short_max = bp["block"] * bp["short_regs"] * 4
+    tile = 1 << bp["tile_log2"]
+    edges = np.array([0, 1, 2, short_max - 1, short_max, short_max + 1, tile - 1, tile, tile + 1, 2 * tile + 3,
+                      3 * tile], np.int64)
+    rows = int(rng.integers(1, 3001))
+    kind = rng.integers(0, 3, rows)
+    lengths = np.where(kind == 0, rng.choice(edges, rows), rng.integers(0, 3 * short_max, rows))
+    lengths[kind == 2] = rng.integers(short_max, 6 * tile, int((kind == 2).sum()))
+    while lengths.sum() > 12_000_000:  # keep the oracle quick
+        lengths //= 2
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 2000 + seed, 1.0)
+    check_rows(run_csr(x, offs, ctx).cpu().numpy(), x, offs, "seed %d %s rows=%d" % (seed, params, rows))
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
 def test_many_rows_planner_rounds():
     """More rows than the planner's threads (several scan rounds), with empty,
     short and long rows interleaved."""

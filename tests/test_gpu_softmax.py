@@ -112,6 +112,32 @@ def test_empty_rows_in_later_planner_rounds():
     check(x, offs, got, got_lse, "2600 rows")
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batches_match_oracle(seed):
+    """Seeded random batches: up to 2500 rows with lengths around the
+    single-pass limit and the tile size, N(0, sigma^2) logits with sigma from
+    0.1 to 30, random launch shapes."""
+    rng = np.random.default_rng(3000 + seed)
+    shapes = [dict(), dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7),
+              dict(block=512, unroll=2, short_regs=2, tile_log2=13, map_grid=33, graph=1)]
+    ctx = api.Context()
+    ctx.set_batch_params(**shapes[seed % len(shapes)])
+    bp = ctx.get_batch_params()
+    short_max = bp["block"] * bp["short_regs"] * 4
+    tile = 1 << bp["tile_log2"]
+    edges = np.array([0, 1, 2, short_max, short_max + 1, tile - 1, tile + 1, 3 * tile], np.int64)
+    rows = int(rng.integers(1, 2501))
+    lengths = np.where(rng.random(rows) < 0.5, rng.choice(edges, rows), rng.integers(0, 4 * tile, rows))
+    while lengths.sum() > 8_000_000:
+        lengths //= 2
+    offs = csr(lengths)
+    sigma = float([0.1, 1.0, 4.0, 30.0][seed % 4])
+    x = synth.normal_f32(int(offs[-1]), 4000 + seed, sigma)
+    got, got_lse = run(x, offs, ctx)
+    check(x, offs, got, got_lse, "seed %d rows=%d sigma=%g" % (seed, rows, sigma))
+    ctx.close()
+
+
 def test_in_place_and_without_lse():
     x, offs = synth.ragged_logits(64, 55, lo=1, hi=50000, sigma=2.0)
     got, _ = run(x, offs, with_lse=False, inplace=True)

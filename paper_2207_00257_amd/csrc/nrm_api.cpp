@@ -120,7 +120,7 @@ int ensure_partials(nrm_ctx* c, int64_t entries) {
   if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
   if (c->partials) {
     hipError_t e2 = hipDeviceSynchronize();  // the old buffer may still be in use
-    hipFree(c->partials);
+    (void)hipFree(c->partials);  // freed whatever the sync reported
     if (e2 != hipSuccess) return hip_fail(e2, "hipDeviceSynchronize");
   }
   c->partials = p;
@@ -351,7 +351,7 @@ int nrm_create(nrm_ctx** ctx, int device) {
   }
   e = hipMemset(small, 0, 256);
   if (e != hipSuccess) {
-    hipFree(small);
+    (void)hipFree(small);  // already failing
     delete c;
     return hip_fail(e, "hipMemset");
   }
@@ -360,7 +360,7 @@ int nrm_create(nrm_ctx** ctx, int device) {
   c->dev_error = reinterpret_cast<int*>(static_cast<char*>(small) + 192);
   int st = ensure_partials(c, 16384);
   if (st != NRM_OK) {
-    hipFree(small);
+    (void)hipFree(small);
     delete c;
     return st;
   }
@@ -376,11 +376,11 @@ int nrm_destroy(nrm_ctx* c) {
       if (it->second == c) return fail(NRM_EINVAL, "the default context cannot be destroyed");
   }
   DeviceGuard g(c->device);
-  hipDeviceSynchronize();
-  for (hipEvent_t ev : c->events) hipEventDestroy(ev);
+  (void)hipDeviceSynchronize();  // teardown: errors were reported by the calls themselves
+  for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
   nrm::batch_free(c);
-  if (c->partials) hipFree(c->partials);
-  if (c->ticket) hipFree(c->ticket);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->ticket) (void)hipFree(c->ticket);
   delete c;
   return NRM_OK;
 }
@@ -474,13 +474,13 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
     if (c->timing) {
       ev = &c->events[3 * (c->timed_calls % kTimingRing)];
       c->timed_calls++;
-      hipEventRecord(ev[0], s);
+      (void)hipEventRecord(ev[0], s);
     }
     hipError_t e = nrm::launch_small(in, in_dtype, out, out_dtype, n, accum, c->sum, s);
     if (e != hipSuccess) return hip_fail(e, "small normalize kernel launch");
     if (ev) {
-      hipEventRecord(ev[1], s);
-      hipEventRecord(ev[2], s);
+      (void)hipEventRecord(ev[1], s);
+      (void)hipEventRecord(ev[2], s);
     }
     return NRM_OK;
   }
@@ -496,14 +496,14 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
   if (c->timing) {
     ev = &c->events[3 * (c->timed_calls % kTimingRing)];
     c->timed_calls++;
-    hipEventRecord(ev[0], s);
+    (void)hipEventRecord(ev[0], s);
   }
   hipError_t e = nrm::launch_reduce(plan, ws, s);
   if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
-  if (ev) hipEventRecord(ev[1], s);
+  if (ev) (void)hipEventRecord(ev[1], s);
   e = nrm::launch_map(plan, ws, s);
   if (e != hipSuccess) return hip_fail(e, "map kernel launch");
-  if (ev) hipEventRecord(ev[2], s);
+  if (ev) (void)hipEventRecord(ev[2], s);
   return NRM_OK;
 }
 

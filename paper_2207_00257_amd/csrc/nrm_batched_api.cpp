@@ -82,7 +82,7 @@ bool any_graph(const BatchWorkspace& w) { return w.graph[0] || w.graph[1] || w.g
 
 void destroy_graph(BatchWorkspace& w) {
   for (hipGraphExec_t& g : w.graph) {
-    if (g) hipGraphExecDestroy(g);
+    if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
 }
@@ -137,22 +137,28 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   const size_t staging = kTableOffset + sizeof(RowDesc) * (size_t)cap_rows;
   e = hipHostMalloc(&host, staging, hipHostMallocCoherent | hipHostMallocMapped);
   if (e != hipSuccess) {
-    hipFree(dev);
+    (void)hipFree(dev);  // already failing
     return fail(NRM_ENOMEM, std::string("pinned staging hipHostMalloc: ") + hipGetErrorString(e));
   }
   void* host_dev = nullptr;
   e = hipHostGetDevicePointer(&host_dev, host, 0);
   if (e != hipSuccess) {
-    hipFree(dev);
-    hipHostFree(host);
+    (void)hipFree(dev);
+    (void)hipHostFree(host);
     return hip_fail(e, "hipHostGetDevicePointer");
   }
   int err_word = 0;
   if (w.dev) {
-    hipMemcpy(&err_word, w.error, sizeof(int), hipMemcpyDeviceToHost);  // keep a pending device error
-    hipFree(w.dev);
+    // keep a pending device error of the old workspace
+    e = hipMemcpy(&err_word, w.error, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {  // the old workspace stays as it was
+      (void)hipFree(dev);
+      (void)hipHostFree(host);
+      return hip_fail(e, "hipMemcpy (device error word)");
+    }
+    (void)hipFree(w.dev);
   }
-  if (w.host) hipHostFree(w.host);
+  if (w.host) (void)hipHostFree(w.host);
   char* d = static_cast<char*>(dev);
   w.dev = dev;
   w.host = host;
@@ -229,7 +235,7 @@ BatchPlan plan_of(const nrm_ctx* c, int acc) {
 
 int capture_graph(nrm_ctx* c, int acc) {
   BatchWorkspace& w = c->batch;
-  if (w.graph[acc]) hipGraphExecDestroy(w.graph[acc]);
+  if (w.graph[acc]) (void)hipGraphExecDestroy(w.graph[acc]);
   w.graph[acc] = nullptr;
   hipError_t e;
   if (!w.capture_stream) {
@@ -244,7 +250,7 @@ int capture_graph(nrm_ctx* c, int acc) {
   if (e2 != hipSuccess) return hip_fail(e2, "batched launch (capture)");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&w.graph[acc], graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
     w.graph[acc] = nullptr;
     return hip_fail(e, "hipGraphInstantiate");
@@ -270,7 +276,7 @@ int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nr
   if (c->timing) {
     ev = &w.events[2 * (w.timed_calls % nrm::kTimingRing)];
     w.timed_calls++;
-    hipEventRecord(ev[0], s);
+    (void)hipEventRecord(ev[0], s);  // timing only
   }
   if (c->bparams.graph) {
     if (!w.graph[acc]) {
@@ -283,7 +289,7 @@ int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nr
     e = nrm::launch_batch(plan_of(c, acc), args_of(c), s);
     if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
   }
-  if (ev) hipEventRecord(ev[1], s);
+  if (ev) (void)hipEventRecord(ev[1], s);
   e = hipEventRecord(w.staged, s);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   w.staged_pending = true;
@@ -298,11 +304,11 @@ namespace nrm {
 void batch_free(nrm_ctx* c) {
   BatchWorkspace& w = c->batch;
   destroy_graph(w);
-  if (w.capture_stream) hipStreamDestroy(w.capture_stream);
-  if (w.staged) hipEventDestroy(w.staged);
-  for (hipEvent_t ev : w.events) hipEventDestroy(ev);
-  if (w.dev) hipFree(w.dev);
-  if (w.host) hipHostFree(w.host);
+  if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
+  if (w.staged) (void)hipEventDestroy(w.staged);
+  for (hipEvent_t ev : w.events) (void)hipEventDestroy(ev);
+  if (w.dev) (void)hipFree(w.dev);
+  if (w.host) (void)hipHostFree(w.host);
   w = BatchWorkspace();
 }
 }  // namespace nrm
@@ -322,7 +328,8 @@ int nrm_set_batch_params(nrm_ctx* c, const nrm_batch_params* params) {
   if (std::memcmp(params, &c->bparams, sizeof(*params)) != 0) {
     DeviceGuard g(c->device);
     if (any_graph(c->batch)) {
-      hipDeviceSynchronize();
+      hipError_t e = hipDeviceSynchronize();  // a replay may still be running
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
       destroy_graph(c->batch);
     }
     c->bparams = *params;

@@ -25,16 +25,17 @@ inline int hip_fail(hipError_t e, const char* where) {
 
 constexpr int kTimingRing = 1024;
 
-// Makes `dev` current for the guard's lifetime.
+// Makes `dev` current for the guard's lifetime. The device was validated
+// when the context was created; should switching still fail, the next HIP
+// call reports the error and every caller checks that call.
 class DeviceGuard {
  public:
-  explicit DeviceGuard(int dev) {
-    hipGetDevice(&prev_);
-    if (prev_ != dev) hipSetDevice(dev);
-    dev_ = dev;
+  explicit DeviceGuard(int dev) : dev_(dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = dev;  // nothing to restore
+    if (prev_ != dev) (void)hipSetDevice(dev);
   }
   ~DeviceGuard() {
-    if (prev_ != dev_) hipSetDevice(prev_);
+    if (prev_ != dev_) (void)hipSetDevice(prev_);
   }
 
  private:

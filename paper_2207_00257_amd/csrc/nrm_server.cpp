@@ -470,12 +470,12 @@ int nrm_server_destroy(nrm_server* s) {
   if (s->scheduler.joinable()) s->scheduler.join();
   DeviceGuard g(s->device);
   for (Slot& sl : s->slots) {
-    if (sl.stream) hipStreamSynchronize(sl.stream);
-    if (sl.done) hipEventDestroy(sl.done);
-    if (sl.stream) hipStreamDestroy(sl.stream);
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);  // teardown: errors were reported per request
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.ctx) nrm_destroy(sl.ctx);
   }
-  if (s->arena_base) hipFree(s->arena_base);
+  if (s->arena_base) (void)hipFree(s->arena_base);
   delete s->arena;
   delete s;
   return NRM_OK;

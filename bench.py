@@ -603,7 +603,7 @@ def bench_precision(args):
     import torch
 
     import oracle
-    from paper_2207_00257_amd import api, synth
+    from paper_2207_00257_amd import api, synth, tune
 
     n = 1 << 26
     bits = synth.lognormal_bf16(n, 5, 2.0)
@@ -618,6 +618,9 @@ def bench_precision(args):
         for odt in ("bf16", "f32"):
             out = torch.empty(n, dtype=torch.bfloat16 if odt == "bf16" else torch.float32, device=dev)
             ctx = api.Context()
+            tuned = tune.load_params(args.params, "bf16", odt, accum, n)
+            if tuned:
+                ctx.set_params(**tuned)
             for _ in range(args.warmup):
                 api.normalize(out, inp, accum=accum, ctx=ctx)
             torch.cuda.synchronize()
@@ -630,7 +633,7 @@ def bench_precision(args):
             ms = e0.elapsed_time(e1) / args.steps
             S = ctx.last_sum()
             so = 2 if odt == "bf16" else 4
-            r = {"accum": accum, "out": odt, "ms": round(ms, 5),
+            r = {"accum": accum, "out": odt, "params": "tuned" if tuned else "defaults", "ms": round(ms, 5),
                  "GBps": round((4 + so) * n / (ms * 1e-3) / 1e9, 1),
                  "sum_err_ulps": round(abs(S - S_ref) / ulp_S, 3),
                  "sum_rel_err": abs(S - S_ref) / S_ref}

@@ -307,23 +307,29 @@ def test_full_size_2p28_default_launch():
 
 @pytest.mark.parametrize("accum", ["f32", "kahan"])
 def test_precision_workload_full_size(accum):
-    """The precision workload at its full size and launch configuration:
-    n = 2^26 BF16 inputs bf16(exp(2 N(0,1))) (seed 5), default parameters.
-    Every output against the FP64 oracle on the same quantised inputs: BF16
-    outputs within one BF16 ulp, FP32 outputs within the binary32 tolerance."""
+    """The precision workload at its full size and in the launch configuration
+    the benchmark times (each variant's tuned shape, else the defaults):
+    n = 2^26 BF16 inputs bf16(exp(2 N(0,1))) (seed 5). Every output against
+    the FP64 oracle on the same quantised inputs: BF16 outputs within one BF16
+    ulp, FP32 outputs within the binary32 tolerance."""
+    from paper_2207_00257_amd import tune
+
     n = 1 << 26
     bits = synth.lognormal_bf16(n, 5, 2.0)
     ref = oracle.normalize(bits, "bf16")
     inp = gpu(bits.view(np.int16)).view(torch.bfloat16)
-    out = torch.empty(n, dtype=torch.bfloat16, device=DEV)
-    api.normalize(out, inp, accum=accum)
-    torch.cuda.synchronize()
-    got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
-    assert_within_ulp(got, ref, ulp_bf16, what="2^26 bf16->bf16 " + accum)
-    out32 = torch.empty(n, dtype=torch.float32, device=DEV)
-    api.normalize(out32, inp, accum=accum)
-    torch.cuda.synchronize()
-    assert_f32_close(out32.cpu().numpy(), ref, what="2^26 bf16->f32 " + accum)
+    for odt, tdt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
+        ctx = api.Context(**(tune.load_params(None, "bf16", odt, accum, n) or {}))
+        out = torch.empty(n, dtype=tdt, device=DEV)
+        api.normalize(out, inp, accum=accum, ctx=ctx)
+        torch.cuda.synchronize()
+        what = "2^26 bf16->%s %s" % (odt, accum)
+        if odt == "bf16":
+            got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
+            assert_within_ulp(got, ref, ulp_bf16, what=what)
+        else:
+            assert_f32_close(out.cpu().numpy(), ref, what=what)
+        ctx.close()
 
 
 def test_parameter_validation():

@@ -148,7 +148,7 @@ typedef struct {
 
 typedef struct nrm_ctx nrm_ctx;
 
-/* ---- the spec forms: FP32 in and out, default context, null stream -- */
+/* ---- the basic forms: FP32 in and out, default context, null stream ------- */
 
 /* out[i] = in[i] / sum(in[0..n)) for i in [0, n). Fig. 1 semantics with the
  * sum hoisted (Sec. IV-C). in, out: device arrays of n floats. */

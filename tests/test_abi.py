@@ -35,7 +35,7 @@ def lib():
     return L.lib()
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_basic_calls():
     names = declared_functions()
     assert "normalize" in names and "nrm_normalize_ex" in names, names
 

@@ -140,7 +140,7 @@ def test_n_zero_writes_nothing():
     assert torch.all(out == 7.0)
 
 
-def test_raw_north_star_entry_point():
+def test_raw_fp32_entry_point():
     """normalize(out, in, n) itself: FP32, default context, null stream."""
     x = synth.uniform_f32(123457, 23)
     inp = gpu(x)

@@ -110,7 +110,7 @@ namespace {
 
 // Reduce blocks of the NLL loss: enough loads in flight for the gathers,
 // few enough partials for the one-block combine.
-constexpr int64_t kNllMaxGrid = 2048;
+constexpr int64_t kNllMaxGrid = 1024;  // 1024 partials: the one-wavefront merge (2048 blocks ran 4 % slower)
 
 int ensure_partials(nrm_ctx* c, int64_t entries) {
   if (entries <= c->partials_cap) return NRM_OK;

@@ -38,7 +38,7 @@ def run(logp, target, weight, reduction, accum="f32", ignore_index=-100, ctx=Non
 
 
 def sum_tol(n, accum):
-    return 4 * U if accum == "kahan" else (math.ceil(n / (2048 * 1024)) + 42) * U
+    return 4 * U if accum == "kahan" else (math.ceil(n / (1024 * 1024)) + 42) * U
 
 
 @pytest.mark.parametrize("with_weight", [True, False])

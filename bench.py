@@ -91,7 +91,7 @@ def main():
                     help="JSON file of tuned launch parameters (default: the committed tuning cache "
                          "if it has an entry for this device and size, else the library defaults)")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "ragged", "serve", "precision", "ladder", "softmax", "nll", "barriers"],
+                    choices=["plain", "ragged", "serve", "precision", "ladder", "softmax", "nll", "barriers", "sizes"],
                     help="plain: n=2^log2n FP32 (the headline); ragged: 4096 rows, lengths log-uniform "
                          "in [32, 2^20], LogNormal(0,1) FP32, one graph-replayed batched call per step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -115,6 +115,8 @@ def main():
         return bench_serve(args)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "sizes":
+        return bench_sizes(args)
     if args.workload == "ladder":
         return bench_ladder(args)
 
@@ -661,6 +663,62 @@ def bench_precision(args):
                                "binary32 accumulation; BF16 and FP32 out; errors against the FP64 oracle",
                    "n": n, "oracle_sum": S_ref},
         "variants": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sizes(args):
+    """The plain path across sizes: n = 2^16 .. 2^30 FP32, in ~ U[0.5, 1.5)
+    (seed 3 per size), default launch parameters. For each size, the time per
+    call over back-to-back calls (HIP events around the whole sequence, so
+    per-call host overhead counts at small n) and the library's per-kernel
+    times. The line's value is the n = 2^20 case's effective GB/s."""
+    import torch
+
+    from paper_2207_00257_amd import api
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = api.Context()
+    rows = []
+    for lg in (16, 18, 20, 22, 24, 26, 27, 28, 29, 30):
+        n = 1 << lg
+        g = torch.Generator(device=dev)
+        g.manual_seed(3)
+        inp = torch.rand(n, device=dev, generator=g).add_(0.5)
+        out = torch.empty_like(inp)
+        for _ in range(args.warmup):
+            api.normalize(out, inp, ctx=ctx)
+        torch.cuda.synchronize()
+        reps = 200 if lg <= 22 else max(args.steps, 5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            api.normalize(out, inp, ctx=ctx)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        # per-kernel times in a pass of their own (the library's events add host work per call)
+        ctx.set_timing(True)
+        for _ in range(min(reps, 20)):
+            api.normalize(out, inp, ctx=ctx)
+        torch.cuda.synchronize()
+        r, m, c = ctx.kernel_times()
+        ctx.set_timing(False)
+        rows.append({"log2n": lg, "us_per_call": round(us, 2), "GBps": round(12.0 * n / us / 1e3, 1),
+                     "pct_of_peak": round(100.0 * 12.0 * n / us / 1e3 / PEAK_HBM_GBS, 1),
+                     "reduce_us": round(r / c * 1e3, 2) if c else None, "map_us": round(m / c * 1e3, 2) if c else None})
+        print("n=2^%d %.2f us per call" % (lg, us), file=sys.stderr, flush=True)
+        del inp, out
+        torch.cuda.empty_cache()
+    main_r = next(r for r in rows if r["log2n"] == 20)
+    line = {
+        "metric": METRIC, "value": main_r["GBps"], "unit": "GB/s", "pct_of_peak": main_r["pct_of_peak"],
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main_r["us_per_call"] / 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain normalize across sizes, n = 2^16..2^30 FP32, in~U[0.5,1.5) seed 3, "
+                               "model 12 B/element; value: the n = 2^20 case"},
+        "sizes": rows,
     }
     print(json.dumps(line), flush=True)
 

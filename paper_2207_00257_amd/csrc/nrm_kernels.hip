@@ -12,13 +12,20 @@
 //                  wavefront reduces with DPP lane moves (no LDS, no barrier);
 //                  the wavefronts of a block meet in one LDS slot each behind
 //                  one block barrier (the block barrier of Fig. 1's shared-
-//                  memory variant). The last block to finish (an agent-scope
-//                  ticket; partials travel by agent-scope atomic stores and
-//                  loads, coherent across the XCDs' separate L2 caches)
-//                  combines all partials in a fixed tree in LDS (the halving
-//                  loop of Fig. 7) and writes the sum.
-//   map_kernel     out[i] = in[i] / sum with a correctly rounded binary32
-//                  division, 16-byte vector loads, non-temporal vector stores.
+//                  memory variant). Fused combine (the default): the block
+//                  stores its partial and ends. Otherwise the last block to
+//                  finish (an agent-scope ticket; partials travel by
+//                  agent-scope atomic stores and loads, coherent across the
+//                  XCDs' separate L2 caches) combines all partials in a fixed
+//                  tree in LDS (the halving loop of Fig. 7) and writes the sum.
+//                  Loads are non-temporal except the input's last
+//                  reduce_keep_mib MiB, which stay in the last-level cache
+//                  for the map.
+//   map_kernel     (fused) every block first merges the reduce's partials with
+//                  one wavefront in the same fixed order, so all blocks divide
+//                  by the same bits; then out[i] = in[i] / sum with a
+//                  correctly rounded binary32 division, 16-byte vector loads,
+//                  non-temporal vector stores.
 //
 // The kernel boundary between the two is the grid-wide barrier. No float
 // atomics are used: for given sizes, alignment and launch parameters every

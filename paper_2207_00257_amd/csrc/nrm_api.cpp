@@ -34,8 +34,8 @@ namespace {
 // non-temporal hint and that tail with a temporal one (it stays in the
 // last-level cache, where the map finds it), and ends without a grid-wide
 // ticket: every map block merges the reduce's partials itself. The map runs
-// many blocks over tiles of 2^13 elements (block b takes tiles b, b + grid,
-// ...), two 16-byte vectors per thread per iteration.
+// 64 blocks per CU over tiles of 2^12 elements (block b takes tiles b,
+// b + grid, ...), two 16-byte vectors per thread per iteration.
 nrm_params default_params() {
   nrm_params p;
   std::memset(&p, 0, sizeof(p));
@@ -47,7 +47,7 @@ nrm_params default_params() {
   p.max_height = 36;
   p.map_block = 512;
   p.map_unroll = 2;
-  p.map_grid = 8192;
+  p.map_grid = 16384;
   p.map_layout = NRM_LAYOUT_TILE;
   p.map_nt = 1;
   p.reverse_map = 0;
@@ -55,7 +55,7 @@ nrm_params default_params() {
   // cache, where the map finds them (measured: 256 saves ~35 us of the map at
   // 2^28 FP32; 288 overflows the cache and saves nothing)
   p.reduce_keep_mib = 256;
-  p.tile_log2 = 13;
+  p.tile_log2 = 12;
   p.fused_combine = 1;
   p.small_n = 65536;
   return p;
@@ -341,7 +341,7 @@ int nrm_create(nrm_ctx** ctx, int device) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
     c->params.grid = 2 * cus;       // reduce: 2 blocks per CU
-    c->params.map_grid = 32 * cus;  // map: 32 blocks per CU
+    c->params.map_grid = 64 * cus;  // map: 64 blocks per CU
   }
   void* small = nullptr;
   e = hipMalloc(&small, 256);

@@ -295,10 +295,13 @@ def test_misaligned_output_rows():
 def test_ragged_4096_rows_full_workload():
     """The ragged benchmark workload: 4096 rows, lengths log-uniform in
     [32, 2^20], LogNormal(0,1) FP32 values; every element against the oracle,
-    in the default (benchmark) launch configuration, through a captured graph."""
+    in the launch configuration the benchmark times (the tuned entry, else the
+    defaults), through a captured graph."""
+    from paper_2207_00257_amd import tune
+
     x, offs = synth.ragged_batch(4096, 4)
     ctx = api.Context()
-    ctx.set_batch_params(graph=1)
+    ctx.set_batch_params(**dict(tune.load_batch_params() or {}, graph=1))
     got = run_csr(x, offs, ctx).cpu().numpy()
     assert ctx.device_error() == L.NRM_OK
     ref = oracle.normalize_batched(x, offs)

@@ -97,7 +97,7 @@ def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=Fa
 
     grids = [cus * k for k in ((1, 2, 4) if quick else (1, 2, 4, 8, 16))]
     red_space = list(itertools.product((0, 1, 2), (256, 512, 1024), (2, 4, 8), grids, (0, 1), (0, 1)))
-    map_grids = [cus * k for k in ((4, 8) if quick else (2, 4, 8, 16, 32))]
+    map_grids = [cus * k for k in ((8, 64) if quick else (2, 4, 8, 16, 32, 64))]
     map_space = [c for c in itertools.product((0, 1, 2), (256, 512, 1024), (1, 2, 4, 8), map_grids, (0, 1), (0, 1))
                  if not (c[0] == 2 and c[5])]  # the tiled map has no reverse walk
 
@@ -231,7 +231,7 @@ def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
             best, best_t = p, ms
     for map_block in (256, 512, 1024):
         for map_unroll in (1, 2, 4, 8):
-            for gmul in (1, 2, 4, 8, 16):
+            for gmul in (1, 2, 4, 8, 16, 32):
                 p = dict(best, map_block=map_block, map_unroll=map_unroll,
                          map_grid=cus * gmul * max(1, 1024 // map_block))
                 ms = measure(p)

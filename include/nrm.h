@@ -88,8 +88,9 @@ typedef struct {
   int32_t layout;       /* nrm_layout */
   int32_t reduce_nt;    /* 1: non-temporal hint on the reduce's loads */
   int32_t max_height;   /* bound on the additions along any path of one thread's summation
-                           tree, 24..48; the whole tree then has height <= max_height + 26
-                           (wavefront 6, block <= 4, grid combine <= 16) */
+                           tree, 24..40; the whole tree then has height <= max_height + 26
+                           (wavefront 6, block <= 4, grid combine <= 16), so that
+                           gamma_h + u < 4e-6 even at the cap (h = 66: 3.99e-6) */
   /* map kernel */
   int32_t map_block;    /* threads per block: 64..1024, multiple of 64 */
   int32_t map_unroll;   /* 16-byte vectors per thread per iteration: 1, 2, 4 or 8 */

@@ -7,6 +7,7 @@ softmax_oracle.c, nll_oracle.c and layerforward_oracle.c (plain C, binary64);
 this module only loads them with ctypes and marshals numpy arrays.
 
 Functions (all return float64 arrays):
+  sum_(x)                      Fig. 1's elided `sum`: sequential binary64
   normalize(x)                 hoisted form: S = sum once, out = x / S
   normalize_naive(x)           Fig. 1 as printed: every thread recomputes S
   normalize_perblock(x, B)     shared-memory variant: one S per block of B

@@ -70,7 +70,8 @@ int check_params(const nrm_params& p) {
   if (!ok_u(p.unroll) || !ok_u(p.map_unroll)) return fail(NRM_EINVAL, "unroll and map_unroll must be 1, 2, 4 or 8");
   if (p.grid < 1 || p.map_grid < 1) return fail(NRM_EINVAL, "grid and map_grid must be positive");
   if (!ok_l(p.layout) || !ok_l(p.map_layout)) return fail(NRM_EINVAL, "unknown layout");
-  if (p.max_height < 24 || p.max_height > 48) return fail(NRM_EINVAL, "max_height must be 24..48");
+  // h <= max_height + 26 levels: gamma_h + u stays below 4e-6 up to max_height 40 (h = 66)
+  if (p.max_height < 24 || p.max_height > 40) return fail(NRM_EINVAL, "max_height must be 24..40");
   if (!ok_f(p.reduce_nt) || !ok_f(p.map_nt) || !ok_f(p.reverse_map))
     return fail(NRM_EINVAL, "reduce_nt, map_nt and reverse_map must be 0 or 1");
   if (p.reduce_keep_mib < 0 || p.reduce_keep_mib > 4096) return fail(NRM_EINVAL, "reduce_keep_mib must be 0..4096");

@@ -77,6 +77,49 @@ def pin_golden_bf16_decode(orc):
         assert got == want, (parts[1], got, want)
 
 
+def pin_golden_sum(orc):
+    """The elided `sum` of Fig. 1 on hand-worked inputs: exact integers and
+    dyadic rationals whose binary64 sum is exact in any order (a binary32
+    accumulator loses the 1s after 2^24, a dropped or repeated term changes
+    the total)."""
+    seen = 0
+    for parts in golden_cases():
+        if parts[0] != "sum":
+            continue
+        toks = parts[2].split()
+        x = np.array([float(Fraction(t)) for t in toks], np.float32)
+        want = float(_rat(parts[3]))
+        got = orc.sum(x)
+        assert got == want, (parts[1], got, want)
+        seen += 1
+    assert seen >= 5
+
+
+def pin_sum_exact_rational(orc):
+    """The exported sum against exact rationals: within the sequential bound
+    (n-1) u sum|x| of the exact sum, for FP32, BF16 and FP16 storage, and equal
+    to the sum the hoisted normalize divides by."""
+    for seed in range(4):
+        for n in (1, 2, 5, 64, 300):
+            x = synth.lognormal_f32(n, 500 + seed * 11 + n, 2.0)
+            exact = sum(Fraction(float(v)) for v in x)
+            s = orc.sum(x)
+            gamma = (n - 1) * U64 / (1 - (n - 1) * U64)
+            assert abs(Fraction(s) - exact) <= Fraction(gamma) * exact, (n, seed)
+            _, s_norm = orc.normalize(x, return_sum=True)
+            assert s == s_norm, (n, seed)
+            bits = synth.lognormal_bf16(n, 900 + seed + n, 1.0)
+            vals = (bits.astype(np.uint32) << 16).view(np.float32)
+            exact = sum(Fraction(float(v)) for v in vals)
+            assert abs(Fraction(orc.sum(bits, "bf16")) - exact) <= Fraction(gamma) * exact, (n, seed, "bf16")
+            h = np.abs(synth.lognormal_f32(n, 77 + seed + n, 1.0)).astype(np.float16)
+            exact = sum(Fraction(float(v)) for v in h)
+            assert abs(Fraction(orc.sum(h.view(np.uint16), "f16")) - exact) <= Fraction(gamma) * exact
+    # an asymmetric input: the first and the last element both count
+    assert orc.sum(np.array([1024.0, 1.0, 2.0, 4096.0], np.float32)) == 5123.0
+    assert orc.sum(np.zeros(0, np.float32)) == 0.0
+
+
 def pin_exact_rational(orc):
     """Brute force with exact rationals on small random inputs: the oracle's
     sum is within the sequential-summation bound (n-1)*u*sum|x| of the exact
@@ -256,7 +299,8 @@ def pin_ieee_specials(orc):
 
 
 ALL_PINS = [
-    pin_golden_plain, pin_golden_batched, pin_golden_bf16_decode, pin_exact_rational,
+    pin_golden_plain, pin_golden_batched, pin_golden_bf16_decode, pin_golden_sum, pin_sum_exact_rational,
+    pin_exact_rational,
     pin_exact_rational_signed, pin_hoist_legal, pin_constant_power_of_two, pin_sums_to_one,
     pin_power_of_two_scaling, pin_permutation, pin_batched_rows, pin_decode_bf16_library,
     pin_decode_f16_library, pin_round_bf16, pin_ieee_specials,

@@ -173,3 +173,21 @@ def test_forms_validation_before_any_hip_call(lib):
     assert f(2, None, 8192, 10, 256, None) == L.NRM_EINVAL
     assert f(1, 4098, 8192, 10, 256, None) == L.NRM_EINVAL          # misaligned
     assert f(1, 4096, 4096, 10, 256, None) == L.NRM_EOVERLAP        # in place is not allowed here
+
+
+def test_height_cap_keeps_the_stated_bound():
+    """nrm_params.max_height is capped so that the worst case the header
+    states, gamma_h + u with h = max_height + 26 and u = 2^-24, stays within
+    the 4e-6 relative tolerance: 40 is the largest cap for which it does."""
+    text = open(os.path.join(ROOT, "include", "nrm.h")).read()
+    m = re.search(r"int32_t max_height;.*?(\d+)\.\.(\d+)", text, flags=re.S)
+    lo, hi = int(m.group(1)), int(m.group(2))
+    u = 2.0 ** -24
+
+    def bound(h):
+        return h * u / (1 - h * u) + u
+
+    assert lo == 24 and hi == 40
+    assert bound(hi + 26) < 4e-6 < bound(hi + 27)
+    src = open(os.path.join(ROOT, "paper_2207_00257_amd", "csrc", "nrm_api.cpp")).read()
+    assert "p.max_height > %d" % hi in src

@@ -204,9 +204,9 @@ PARAM_SETS = [
     dict(reverse_map=1),
     dict(reduce_nt=0, map_nt=0, grid=1, map_grid=1),
     dict(max_height=24, grid=4),
-    dict(max_height=48, grid=65536, map_grid=65536),
-    dict(layout=1, grid=8, unroll=8, block=1024, max_height=48),
-    dict(layout=0, grid=3, unroll=1, block=64, max_height=48),
+    dict(max_height=40, grid=65536, map_grid=65536),
+    dict(layout=1, grid=8, unroll=8, block=1024, max_height=40),
+    dict(layout=0, grid=3, unroll=1, block=64, max_height=40),
     dict(reduce_keep_mib=1, reverse_map=1),
     dict(reduce_keep_mib=4096, reverse_map=0, layout=0),
     dict(reduce_keep_mib=0),                          # chunked, every load non-temporal
@@ -336,7 +336,7 @@ def test_parameter_validation():
     ctx = api.Context()
     good = ctx.get_params()
     for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(grid=0),
-                dict(layout=3), dict(map_layout=-1), dict(max_height=23), dict(max_height=49),
+                dict(layout=3), dict(map_layout=-1), dict(max_height=23), dict(max_height=41),
                 dict(reverse_map=2), dict(map_nt=-1), dict(tile_log2=9), dict(tile_log2=23),
                 dict(fused_combine=2), dict(small_n=-1), dict(reduce_keep_mib=-1), dict(reduce_keep_mib=4097)):
         with pytest.raises(L.NrmError):

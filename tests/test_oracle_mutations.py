@@ -33,6 +33,9 @@ MUTATIONS = {
                               "double s = e > b ? sum_seq(in, dtype, 0, e) : 0.0;"),
     "naive_skips_last": ("if (tid < n) out[tid] = load(in, dtype, tid) / val;",
                          "if (tid < n - 1) out[tid] = load(in, dtype, tid) / val;\n      else if (tid < n) out[tid] = 0.0;"),
+    "sum_skips_first": ("return sum_seq(in, dtype, 0, n);", "return sum_seq(in, dtype, 1, n);"),
+    "sum_guard_drops_single": ("if (n <= 0 || !valid_dtype(dtype) || !in) return 0.0;",
+                               "if (n <= 1 || !valid_dtype(dtype) || !in) return 0.0;"),
     "perblock_wrong_range": ("double shared_val = sum_seq(in, dtype, 0, n);",
                              "double shared_val = sum_seq(in, dtype, b * block, n);"),
 }

@@ -151,9 +151,12 @@ void split(int64_t nvec, int64_t step, int64_t max_blocks, int64_t max_iters, in
   *chunk = per * step;
 }
 
-int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_dt, int64_t n,
-               int acc, nrm::PlainPlan* p) {
-  const nrm_params& q = c->params;
+}  // namespace
+
+namespace nrm {
+
+int plan_plain(const nrm_params& q, void* out, int out_dt, const void* in, int in_dt, int64_t n, int acc,
+               PlainPlan* p) {
   const int si = nrm::dtype_size(in_dt), so = nrm::dtype_size(out_dt);
   const uintptr_t ai = reinterpret_cast<uintptr_t>(in), ao = reinterpret_cast<uintptr_t>(out);
   if (ai % si) return fail(NRM_EINVAL, "in is not aligned to its element size");
@@ -221,6 +224,20 @@ int plan_plain(const nrm_ctx* c, void* out, int out_dt, const void* in, int in_d
   if (p->map_grid > INT32_MAX) return fail(NRM_EINVAL, "n too large for one launch");
   return NRM_OK;
 }
+
+nrm_params device_params(int device) {
+  nrm_params p = default_params();
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
+    p.grid = 2 * cus;       // reduce: 2 blocks per CU
+    p.map_grid = 64 * cus;  // map: 64 blocks per CU
+  }
+  return p;
+}
+
+}  // namespace nrm
+
+namespace {
 
 bool ranges_partially_overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
   uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)abytes;
@@ -308,6 +325,27 @@ int nrm_layerforward(int form, float* hidden, const float* input, float* output,
   return NRM_OK;
 }
 
+}  // extern "C"
+
+namespace nrm {
+int check_plain_args(const void* out, int out_dtype, const void* in, int in_dtype, int64_t n, int accum) {
+  if (n < 0) return fail(NRM_EINVAL, "n < 0");
+  if (!valid_dtype(in_dtype) || !valid_dtype(out_dtype)) return fail(NRM_EINVAL, "unknown dtype");
+  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
+  if (n == 0) return NRM_OK;
+  if (!in || !out) return fail(NRM_EINVAL, "NULL data pointer with n > 0");
+  const int64_t si = dtype_size(in_dtype), so = dtype_size(out_dtype);
+  if (n > INT64_MAX / 8) return fail(NRM_EINVAL, "n too large");
+  if (ranges_partially_overlap(in, n * si, out, n * so))
+    return fail(NRM_EOVERLAP, "in and out overlap without being the same array");
+  if (reinterpret_cast<uintptr_t>(in) % si) return fail(NRM_EINVAL, "in is not aligned to its element size");
+  if (reinterpret_cast<uintptr_t>(out) % so) return fail(NRM_EINVAL, "out is not aligned to its element size");
+  return NRM_OK;
+}
+}  // namespace nrm
+
+extern "C" {
+
 const char* nrm_status_string(int status) {
   switch (status) {
     case NRM_OK: return "ok";
@@ -337,13 +375,8 @@ int nrm_create(nrm_ctx** ctx, int device) {
   DeviceGuard g(device);
   nrm_ctx* c = new nrm_ctx();
   c->device = device;
-  c->params = default_params();
+  c->params = nrm::device_params(device);
   nrm_default_batch_params(&c->bparams);
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0) {
-    c->params.grid = 2 * cus;       // reduce: 2 blocks per CU
-    c->params.map_grid = 64 * cus;  // map: 64 blocks per CU
-  }
   void* small = nullptr;
   e = hipMalloc(&small, 256);
   if (e != hipSuccess) {
@@ -451,24 +484,14 @@ int nrm_kernel_times(nrm_ctx* c, double* reduce_ms, double* map_ms, int64_t* cal
 
 int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype, int64_t n,
                      int accum, void* stream) {
-  if (n < 0) return fail(NRM_EINVAL, "n < 0");
-  if (!valid_dtype(in_dtype) || !valid_dtype(out_dtype)) return fail(NRM_EINVAL, "unknown dtype");
-  if (accum != NRM_ACC_F32 && accum != NRM_ACC_KAHAN) return fail(NRM_EINVAL, "unknown accumulation mode");
-  if (n == 0) return NRM_OK;
-  if (!in || !out) return fail(NRM_EINVAL, "NULL data pointer with n > 0");
-  const int64_t si = nrm::dtype_size(in_dtype), so = nrm::dtype_size(out_dtype);
-  if (n > INT64_MAX / 8) return fail(NRM_EINVAL, "n too large");
-  if (ranges_partially_overlap(in, n * si, out, n * so))
-    return fail(NRM_EOVERLAP, "in and out overlap without being the same array");
+  int st0 = nrm::check_plain_args(out, out_dtype, in, in_dtype, n, accum);
+  if (st0 != NRM_OK || n == 0) return st0;
   if (!c) {
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
   if (n <= c->params.small_n && n <= nrm::small_capacity(in_dtype)) {
     // one block, the input held in registers: one read, one write, one launch
-    const uintptr_t ai = reinterpret_cast<uintptr_t>(in), ao = reinterpret_cast<uintptr_t>(out);
-    if (ai % si) return fail(NRM_EINVAL, "in is not aligned to its element size");
-    if (ao % so) return fail(NRM_EINVAL, "out is not aligned to its element size");
     DeviceGuard g(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t* ev = nullptr;
@@ -486,7 +509,7 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
     return NRM_OK;
   }
   nrm::PlainPlan plan;
-  int st = plan_plain(c, out, out_dtype, in, in_dtype, n, accum, &plan);
+  int st = nrm::plan_plain(c->params, out, out_dtype, in, in_dtype, n, accum, &plan);
   if (st != NRM_OK) return st;
   DeviceGuard g(c->device);
   st = ensure_partials(c, plan.grid);

@@ -94,6 +94,14 @@ struct nrm_ctx {
 namespace nrm {
 // The process-wide default context of the current device (created on first use).
 int default_ctx(nrm_ctx** out);
+// The library's launch parameters for `device` (grids sized by its CU count).
+nrm_params device_params(int device);
+// Host validation of a plain call (no HIP call): NRM_OK, or the error status
+// with nrm_last_error() set. n == 0 is valid.
+int check_plain_args(const void* out, int out_dtype, const void* in, int in_dtype, int64_t n, int accum);
+// Resolve a plain call's launch plan from parameters q (host only).
+int plan_plain(const nrm_params& q, void* out, int out_dt, const void* in, int in_dt, int64_t n, int acc,
+               PlainPlan* p);
 // Release the batched workspace of a context (waits for the device).
 void batch_free(nrm_ctx* c);
 }  // namespace nrm

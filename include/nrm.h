@@ -164,6 +164,32 @@ int normalize(float* out, const float* in, int64_t n);
  * skipped and reported by nrm_get_device_error. */
 int normalize_batched(float* out, const float* in, const int64_t* offsets, int64_t rows);
 
+/* ---- allocation-free plain form ------------------------------------------ */
+
+/* For callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc. Computes exactly what
+ * nrm_normalize_ex does on the current device's default context (same
+ * kernels, same default launch parameters, same bits), but takes no context
+ * and calls no hipMalloc, hipFree or other allocating routine: the workspace
+ * (block partials, combine ticket, sum) is a fixed array of
+ * NRM_NOALLOC_SCRATCH_BYTES bytes in the library's code object, one copy per
+ * device, held until the process ends. The first call on a device looks up
+ * that device's copy and enqueues one tiny kernel on `stream` to clear the
+ * ticket.
+ *   in, out:  device arrays of n elements of in_dtype / out_dtype, as for
+ *             nrm_normalize_ex (same overlap, alignment and dtype rules);
+ *   accum:    NRM_ACC_F32 or NRM_ACC_KAHAN;  stream: hipStream_t or NULL.
+ * Limit: the call may use at most 16384 reduce blocks (one 8-byte partial
+ * each); with the default parameters that holds for every n <= 2^34. A larger
+ * n returns NRM_EINVAL before anything is enqueued.
+ * All calls on one device share that device's array and it keeps the last
+ * call's contents: calls that overlap in time on one device (unordered
+ * streams, several host threads) race on it and give wrong results; order
+ * them (one stream, or events). Asynchronous like every other call. */
+#define NRM_NOALLOC_SCRATCH_BYTES 131328
+int nrm_normalize_noalloc(void* out, int out_dtype, const void* in, int in_dtype, int64_t n, int accum,
+                          void* stream);
+
 /* ---- contexts ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device` (-1: the current device). The

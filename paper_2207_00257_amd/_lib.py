@@ -134,6 +134,7 @@ def _declare(lib):
         "nrm_set_params": (i32, [p, ctypes.POINTER(NrmParams)]),
         "nrm_get_params": (i32, [p, ctypes.POINTER(NrmParams)]),
         "nrm_normalize_ex": (i32, [p, p, i32, p, i32, i64, i32, p]),
+        "nrm_normalize_noalloc": (i32, [p, i32, p, i32, i64, i32, p]),
         "nrm_status_string": (ctypes.c_char_p, [i32]),
         "nrm_last_error": (ctypes.c_char_p, []),
         "nrm_set_timing": (i32, [p, i32]),

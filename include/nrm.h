@@ -134,7 +134,14 @@ typedef struct {
   int32_t keep_mib;    /* 0..4096: phase 1 reads the long rows' last tiles, up to this many MiB,
                           with a temporal hint (the rest non-temporal), so that the divide phase
                           finds them in the last-level cache (256 MB on MI355X) */
-  int32_t reserved[2];
+  int32_t resident_segments; /* 0..64: a row of n <= resident_segments * 2^14 elements crosses HBM
+                                twice instead of three times: each of its segments of 2^14 elements
+                                is held in one block's registers from its read to its write while the
+                                row's blocks exchange their segment sums. 0: off (such rows take the
+                                single-pass or tile path) */
+  int32_t resident_grid;     /* persistent 512-thread blocks of the resident rows' kernel, 1..2^20 and
+                                at least resident_segments: a row's blocks wait for each other, so the
+                                device must be able to run that many of them at once (two per CU fit) */
 } nrm_batch_params;
 
 /* One row of a batch given as a table: `in` and `out` are device arrays of
@@ -427,6 +434,17 @@ int nrm_server_destroy(nrm_server* server);
  * used it (binary32; compensated mode: hi + lo rounded once), read after
  * synchronizing `stream`. ctx NULL: the default context. */
 int nrm_get_last_sum(nrm_ctx* ctx, void* stream, float* sum);
+
+/* Measurement only, not part of normalize: the bandwidth ceilings a call is
+ * compared with in the same run. NRM_CEILING_COPY copies `bytes` from src to
+ * dst (the traffic of the divide map: one read and one write per byte);
+ * NRM_CEILING_READ reads `bytes` of src (the traffic of the reduce) and may
+ * write one 4-byte word per block to dst (a device buffer of at least 4 * grid
+ * bytes). 16-byte vectors, non-temporal hints, each of `grid` blocks (512
+ * threads) taking one contiguous chunk. bytes: a multiple of 16; src and dst
+ * 16-byte aligned, not overlapping; grid 1..2^20. Asynchronous on `stream`. */
+typedef enum { NRM_CEILING_COPY = 0, NRM_CEILING_READ = 1 } nrm_ceiling_kind;
+int nrm_ceiling(int kind, void* dst, const void* src, int64_t bytes, int64_t grid, void* stream);
 
 /* Static text for a status code. */
 const char* nrm_status_string(int status);

@@ -53,7 +53,8 @@ class NrmBatchParams(ctypes.Structure):
         ("map_block", ctypes.c_int32),
         ("map_grid", ctypes.c_int32),
         ("keep_mib", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("resident_segments", ctypes.c_int32),
+        ("resident_grid", ctypes.c_int32),
     ]
 
 
@@ -135,6 +136,7 @@ def _declare(lib):
         "nrm_get_params": (i32, [p, ctypes.POINTER(NrmParams)]),
         "nrm_normalize_ex": (i32, [p, p, i32, p, i32, i64, i32, p]),
         "nrm_normalize_noalloc": (i32, [p, i32, p, i32, i64, i32, p]),
+        "nrm_ceiling": (i32, [i32, p, p, i64, i64, p]),
         "nrm_status_string": (ctypes.c_char_p, [i32]),
         "nrm_last_error": (ctypes.c_char_p, []),
         "nrm_set_timing": (i32, [p, i32]),

@@ -43,6 +43,7 @@ enum {
   NRM_DEVERR_ROW = 2,       // a table row with n < 0, bad dtype, NULL pointer, or too many tiles
   NRM_DEVERR_CAPACITY = 4,  // more rows or work items than the workspace holds
   NRM_DEVERR_TARGET = 8,    // NLL loss: a target outside [0, C) that is not ignore_index
+  NRM_DEVERR_STALL = 16,    // a resident row's segments did not all arrive within the spin limit
 };
 
 constexpr int64_t MAX_ROW_TILES = 65536;  // partials the per-row combine merges
@@ -62,7 +63,10 @@ enum {
   CNT_CHUNK = 4,       // elements per phase-2 chunk
   CNT_CHUNKS = 5,      // phase-2 chunks
   CNT_LSE = 6,         // softmax: the header's lse pointer, for the kernels after the planner
-  CNT_COUNT = 7,
+  CNT_DISPENSE = 7,    // resident units handed out so far (set to 0 by the planner)
+  CNT_EPOCH = 8,       // this call's number: tags the resident rows' published partials
+  CNT_STALL = 9,       // the number of the last call in which a resident wait gave up
+  CNT_COUNT = 10,
 };
 
 // One row's reduction result: the sum (a) for normalize, or the exponent and
@@ -93,7 +97,18 @@ struct BatchArgs {
   int64_t map_grid;      // phase 2 blocks: the chunks are sized to a multiple of it
   int64_t min_chunk;     // elements of one full phase-2 block-iteration: the smallest chunk
   int64_t keep_tiles;    // phase 1 reads the last this many long-row tiles with a temporal hint
+  // resident rows (res_on): a row of n <= short_max elements is cut into
+  // segments of 2^RES_LOG2 elements, one work item each, each held in one
+  // block's registers from its read to its write
+  int res_on;
+  unsigned long long* tagged;  // [2 * cap_items]: each segment's partial, two tagged words
 };
+
+// Elements of one resident segment: 512 threads x 8 vectors of 4 binary32
+// (4 vectors of 8 for 2-byte inputs); two blocks fit a CU's registers.
+constexpr int RES_LOG2 = 14;
+constexpr int RES_BLOCK = 512;
+constexpr int RES_MAX_SEGMENTS = 64;  // one wavefront lane per segment in the merge
 
 struct BatchPlan {
   int acc;
@@ -104,6 +119,7 @@ struct BatchPlan {
   int64_t grid;     // persistent blocks of phase 1 and of the row sums
   int map_block;    // phase 2
   int64_t map_grid;
+  int64_t res_grid; // persistent blocks of the resident-row kernel (0: none launched)
 };
 
 hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s);

@@ -280,9 +280,12 @@ __device__ __forceinline__ void scan_counts(int64_t (&v)[NCNT], int64_t (&last)[
   last[NCNT - 1] = (int64_t)lane_value64(w, PLAN_WAVES - 1);
 }
 
-__device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int tile_log2, int64_t (&v)[NCNT]) {
+// Items of a row that is not long: one single-pass item, or with resident
+// rows one per segment of 2^RES_LOG2 elements.
+__device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int tile_log2, int res_on,
+                                           int64_t (&v)[NCNT]) {
   v[0] = long_tiles(n, short_max, tile_log2);
-  v[1] = (n > 0 && n <= short_max) ? 1 : 0;
+  v[1] = (n > 0 && n <= short_max) ? (res_on ? (n + (int64_t(1) << RES_LOG2) - 1) >> RES_LOG2 : 1) : 0;
   v[2] = v[0] > 0 ? 1 : 0;
   v[3] = v[0] > 0 ? n : 0;
 }
@@ -336,6 +339,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   __shared__ int32_t ex_tile[PLAN_THREADS];  // the own round's exclusive scans
   __shared__ int32_t ex_lrow[PLAN_THREADS];
   __shared__ int64_t ex_elem[PLAN_THREADS];
+  __shared__ int32_t ex_short[PLAN_THREADS];
   const int t = threadIdx.x;
   const int64_t own = blockIdx.x;
   if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
@@ -345,7 +349,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   if (nrows < 0 || nrows > a.cap_rows) {
     if (own == 0 && t == 0) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
-      for (int k = 0; k < CNT_COUNT; ++k) a.cnt[k] = 0;
+      for (int k = 0; k < CNT_DISPENSE; ++k) a.cnt[k] = 0;  // the call number stays
     }
     return;
   }
@@ -397,7 +401,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
         const bool mine = q == own;
         const RowDesc d = resolve(q, fetched[k], mine);
         int64_t incl[NCNT], last[NCNT];
-        row_counts(d.n, a.short_max, a.tile_log2, incl);
+        row_counts(d.n, a.short_max, a.tile_log2, a.res_on, incl);
         scan_counts(incl, last, sc);
         lds_barrier();  // sc is rewritten by the next scan
         if (mine) {
@@ -434,11 +438,11 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     const int64_t(&c)[NCNT] = c_own;
     const int64_t(&last)[NCNT] = last_own;
     int64_t v[NCNT];
-    row_counts(d_own.n, a.short_max, a.tile_log2, v);
+    row_counts(d_own.n, a.short_max, a.tile_log2, a.res_on, v);
     ex_tile[t] = (int32_t)(incl[0] - v[0]);  // at most PLAN_THREADS * MAX_ROW_TILES
     ex_lrow[t] = (int32_t)(incl[2] - v[2]);
     ex_elem[t] = incl[3] - v[3];
-    if (v[1]) a.items[total_long + c[1] + incl[1] - 1] = Item{(int32_t)r, 0};
+    ex_short[t] = (int32_t)(incl[1] - v[1]);  // at most PLAN_THREADS * RES_MAX_SEGMENTS
     if (v[2]) {
       const int64_t k = c[2] + incl[2] - 1;
       a.lrow_first[k] = c[0] + incl[0] - v[0];
@@ -457,6 +461,18 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
       for (int u = 0; u < SN; ++u)
         if (i0 + u * PLAN_THREADS < last[0])
           a.items[c[0] + x[u]] = Item{(int32_t)(q * PLAN_THREADS + j[u]), (int32_t)(x[u] - ex_tile[j[u]])};
+    }
+    // the round's single-pass items, or its resident rows' segments
+    for (int64_t i0 = t; i0 < last[1]; i0 += SN * PLAN_THREADS) {
+      int64_t x[SN];
+      int j[SN];
+#pragma unroll
+      for (int u = 0; u < SN; ++u) x[u] = i0 + u * PLAN_THREADS < last[1] ? i0 + u * PLAN_THREADS : 0;
+      last_le<SN>(ex_short, x, j);
+#pragma unroll
+      for (int u = 0; u < SN; ++u)
+        if (i0 + u * PLAN_THREADS < last[1])
+          a.items[total_long + c[1] + x[u]] = Item{(int32_t)(q * PLAN_THREADS + j[u]), (int32_t)(x[u] - ex_short[j[u]])};
     }
     // the chunks whose first element lies in this round's long rows (c[],
     // last[] and chunk are the same in every lane: divide once per wavefront)
@@ -478,7 +494,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   if (own == 0 && t == 0) {
     if (total > a.cap_items) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
-      for (int k = 0; k < CNT_COUNT; ++k) a.cnt[k] = 0;
+      for (int k = 0; k < CNT_DISPENSE; ++k) a.cnt[k] = 0;  // the call number stays
     } else {
       a.cnt[CNT_ITEMS] = total;
       a.cnt[CNT_LONG_ITEMS] = total_long;
@@ -488,6 +504,12 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
       a.cnt[CNT_CHUNKS] = n_chunks;
       a.cnt[CNT_LSE] = reinterpret_cast<int64_t>(h->lse);
     }
+    // a new call: the resident kernel hands out its units from 0 and tags its
+    // partials with a number no earlier call of this workspace used (the
+    // workspace starts at 0; the count skips 0 when it wraps)
+    a.cnt[CNT_DISPENSE] = 0;
+    const uint32_t ep = (uint32_t)a.cnt[CNT_EPOCH] + 1u;
+    a.cnt[CNT_EPOCH] = ep ? ep : 1u;
   }
 }
 
@@ -764,14 +786,253 @@ __device__ __forceinline__ void dispatch_tile_map(const RowDesc& d, int64_t b, i
   }
 }
 
+// ---- resident rows -------------------------------------------------------------------------
+// A row of at most RES_MAX_SEGMENTS segments of 2^RES_LOG2 elements crosses
+// HBM twice instead of three times: each segment is one work item, held in
+// one block's registers from its read to its write. The blocks of a row
+// publish their segment sums, each waits until it sees all of them, merges
+// them in a fixed order (the same in every block of the row, so that every
+// block divides by the same bits) and divides its segment from registers.
+//
+// Progress: blocks take items from a counter (CNT_DISPENSE) in item order, a
+// row's items are consecutive, and a block takes an item only once it has
+// finished the previous one and publishes its sum before it waits. Every row
+// before the one holding the last item taken therefore has all its items in
+// running blocks, each of which publishes: their waits end. Only that last
+// row can wait on items not yet taken, and at most RES_MAX_SEGMENTS - 1 of
+// its blocks wait while the others take its remaining items. The wait is
+// still bounded: after RES_SPIN_LIMIT polls a block flags NRM_DEVERR_STALL
+// and goes on, and every wait of the call gives up once that flag is set,
+// so the kernel always ends.
+//
+// A partial travels as tagged 64-bit words (this call's number in the high
+// half, a binary32 in the low half; two words for the two-float kinds),
+// written and read with agent-scope atomics, which are coherent across the
+// XCDs' L2 caches. A word is valid when its tag is this call's number: no
+// slot is cleared between calls and no fence orders one word after another.
+constexpr uint32_t RES_SPIN_LIMIT = 1u << 18;
+
+template <int ACC>
+struct Tagged {
+  static constexpr int WORDS = ACC == NRM_ACC_F32 ? 1 : 2;
+  __device__ __forceinline__ static void split(const Acc<ACC>& v, float (&f)[2]) {
+    if constexpr (ACC == NRM_ACC_F32) {
+      f[0] = v.s;
+      f[1] = 0.0f;
+    } else if constexpr (ACC == NRM_ACC_KAHAN) {
+      f[0] = v.hi;
+      f[1] = v.lo;
+    } else {
+      f[0] = v.k;
+      f[1] = v.s;
+    }
+  }
+  __device__ __forceinline__ static Acc<ACC> join(const float (&f)[2]) {
+    Acc<ACC> v;
+    if constexpr (ACC == NRM_ACC_F32) {
+      v.s = f[0];
+    } else if constexpr (ACC == NRM_ACC_KAHAN) {
+      v.hi = f[0];
+      v.lo = f[1];
+    } else {
+      v.k = f[0];
+      v.s = f[1];
+    }
+    return v;
+  }
+};
+
+template <int ACC>
+__device__ __forceinline__ void publish_tagged(unsigned long long* tagged, int64_t item, const Acc<ACC>& v,
+                                               uint32_t ep) {
+  float f[2];
+  Tagged<ACC>::split(v, f);
+#pragma unroll
+  for (int w = 0; w < Tagged<ACC>::WORDS; ++w)
+    __hip_atomic_store(tagged + 2 * item + w, ((unsigned long long)ep << 32) | bits_f32(f[w]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wavefront 0 (all 64 lanes): wait for the nseg partials of the row whose
+// first item is `first`, lane l polling item first + l, then merge them with
+// the wavefront tree. Every lane returns the row's total.
+template <int ACC>
+__device__ __forceinline__ Acc<ACC> gather_row(const BatchArgs& a, int64_t first, int nseg, uint32_t ep) {
+  const int lane = threadIdx.x & 63;
+  float f[2] = {0.0f, 0.0f};
+  bool have = lane >= nseg;
+  for (uint32_t spin = 0;; ++spin) {
+    if (!have) {
+      have = true;
+#pragma unroll
+      for (int w = 0; w < Tagged<ACC>::WORDS; ++w) {
+        const unsigned long long x = __hip_atomic_load(a.tagged + 2 * (first + lane) + w, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        f[w] = f32_bits((uint32_t)x);
+        have = have && (uint32_t)(x >> 32) == ep;
+      }
+    }
+    if (__all(have)) break;
+    unsigned long long* stall = reinterpret_cast<unsigned long long*>(a.cnt + CNT_STALL);
+    if (spin >= RES_SPIN_LIMIT) {
+      if (lane == 0) {
+        atomicOr(a.error, NRM_DEVERR_STALL);
+        __hip_atomic_store(stall, (unsigned long long)ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      break;
+    }
+    if ((spin & 255) == 255 && __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ep)
+      break;  // another wait of this call already gave up
+    __builtin_amdgcn_s_sleep(1);
+  }
+  Acc<ACC> v;
+  if (lane < nseg && have) v = Tagged<ACC>::join(f);
+  else v.zero();
+  return wave_reduce<ACC>(v);
+}
+
+// One resident segment: read into registers, block sum, exchange with the
+// row's other segments, divide from the registers, write.
+template <int DTI, int DTO, int ACC>
+__device__ __forceinline__ void resident_unit(const BatchArgs& a, const RowDesc& d, int64_t row, int64_t item,
+                                              int seg, uint32_t ep, Acc<ACC>* slots, RowRes* s_bcast, float* lse) {
+  constexpr int VEC = Elem<DTI>::VEC;
+  constexpr int KB = (1 << RES_LOG2) / (RES_BLOCK * VEC);
+  constexpr int NA = 8;
+  const int t = threadIdx.x;
+  const int64_t S = int64_t(1) << RES_LOG2;
+  const int64_t b = (int64_t)seg << RES_LOG2;
+  const int64_t n = d.n - b < S ? d.n - b : S;
+  const int nseg = (int)((d.n + S - 1) >> RES_LOG2);
+  const char* in_seg = d.in + b * Elem<DTI>::SIZE;
+  char* out_seg = d.out + b * Elem<DTO>::SIZE;
+  const Geom g = geometry<DTI>(in_seg, n);
+  const u4* body = reinterpret_cast<const u4*>(in_seg + g.head * Elem<DTI>::SIZE);
+  const bool has_head = t < g.head;
+  const int64_t ti = g.tail_begin + t;
+  const bool has_tail = ti < n;
+  u4 r[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int64_t v = t + (int64_t)k * RES_BLOCK;
+    if (v < g.nvec) r[k] = load_vec<true>(body + v);
+  }
+  const float xh = has_head ? load_one<DTI>(in_seg, t) : 0.0f;
+  const float xt = has_tail ? load_one<DTI>(in_seg, ti) : 0.0f;
+  Acc<ACC> acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k].zero();
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    if (t + (int64_t)k * RES_BLOCK < g.nvec) {
+      float x[VEC];
+      widen<DTI>(r[k], x);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(x[c]);
+    }
+  }
+  if (has_head) acc[0].add(xh);
+  if (has_tail) acc[0].add(xt);
+  merge_chains<ACC, NA>(acc);
+  const Acc<ACC> tot = block_reduce<ACC>(acc[0], slots);
+  if (nseg == 1) {
+    if (t == 0) {
+      const RowMap<ACC> f0 = RowMap<ACC>::of(tot);
+      *s_bcast = f0.result();
+      if constexpr (ACC == ACC_SOFTMAX) {
+        if (lse) lse[row] = f0.lse();
+      }
+    }
+  } else {
+    if (t == 0) publish_tagged<ACC>(a.tagged, item, tot, ep);
+    if (t < 64) {
+      const Acc<ACC> total = gather_row<ACC>(a, item - seg, nseg, ep);
+      if (t == 0) {
+        const RowMap<ACC> f0 = RowMap<ACC>::of(total);
+        *s_bcast = f0.result();
+        if constexpr (ACC == ACC_SOFTMAX) {
+          if (lse && seg == 0) lse[row] = f0.lse();
+        }
+      }
+    }
+  }
+  lds_barrier();
+  const RowMap<ACC> f = RowMap<ACC>::of(*s_bcast);
+  const bool vec_ok = out_vector_ok<DTI, DTO>(out_seg, g.head);
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int64_t v = t + (int64_t)k * RES_BLOCK;
+    if (v < g.nvec) {
+      float x[VEC], q[VEC];
+      widen<DTI>(r[k], x);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
+      store_quotients<DTI, DTO>(out_seg, g.head, v, vec_ok, q);
+    }
+  }
+  if (has_head) store_one<DTO>(out_seg, t, f(xh));
+  if (has_tail) store_one<DTO>(out_seg, ti, f(xt));
+}
+
+template <int ACC>
+__device__ __forceinline__ void dispatch_resident(const BatchArgs& a, const RowDesc& d, int64_t row, int64_t item,
+                                                  int seg, uint32_t ep, Acc<ACC>* slots, RowRes* s_bcast,
+                                                  float* lse) {
+  if constexpr (ACC == ACC_SOFTMAX) {
+    resident_unit<NRM_F32, NRM_F32, ACC>(a, d, row, item, seg, ep, slots, s_bcast, lse);
+  } else {
+#define NRM_RU(I, O) resident_unit<I, O, ACC>(a, d, row, item, seg, ep, slots, s_bcast, lse)
+    switch (d.in_dt * 3 + d.out_dt) {
+      case NRM_F32 * 3 + NRM_F32: NRM_RU(NRM_F32, NRM_F32); break;
+      case NRM_F32 * 3 + NRM_BF16: NRM_RU(NRM_F32, NRM_BF16); break;
+      case NRM_F32 * 3 + NRM_F16: NRM_RU(NRM_F32, NRM_F16); break;
+      case NRM_BF16 * 3 + NRM_F32: NRM_RU(NRM_BF16, NRM_F32); break;
+      case NRM_BF16 * 3 + NRM_BF16: NRM_RU(NRM_BF16, NRM_BF16); break;
+      case NRM_BF16 * 3 + NRM_F16: NRM_RU(NRM_BF16, NRM_F16); break;
+      case NRM_F16 * 3 + NRM_F32: NRM_RU(NRM_F16, NRM_F32); break;
+      case NRM_F16 * 3 + NRM_BF16: NRM_RU(NRM_F16, NRM_BF16); break;
+      default: NRM_RU(NRM_F16, NRM_F16); break;
+    }
+#undef NRM_RU
+  }
+}
+
+// Persistent blocks take the resident items (after the long rows' tiles in
+// the item table) one at a time from the counter.
+template <int ACC>
+__global__ void __launch_bounds__(RES_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 4))) batch_resident_kernel(BatchArgs a) {
+  __shared__ Acc<ACC> slots[MAX_WAVES];
+  __shared__ RowRes s_bcast;
+  __shared__ int64_t s_claim;
+  const int64_t begin = a.cnt[CNT_LONG_ITEMS], units = a.cnt[CNT_ITEMS] - begin;
+  if (units <= 0) return;
+  const uint32_t ep = (uint32_t)a.cnt[CNT_EPOCH];
+  float* lse = lse_out(a);
+  unsigned long long* counter = reinterpret_cast<unsigned long long*>(a.cnt + CNT_DISPENSE);
+  while (true) {
+    if (threadIdx.x == 0)
+      s_claim = (int64_t)__hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    lds_barrier();
+    const int64_t u = s_claim;
+    if (u >= units) break;
+    const int64_t item = begin + u;
+    const Item it = a.items[item];
+    const RowDesc d = a.rows[it.row];
+    dispatch_resident<ACC>(a, d, it.row, item, it.tile, ep, slots, &s_bcast, lse);
+    lds_barrier();  // slots, s_bcast and s_claim are reused
+  }
+}
+
 // ---- the persistent phases ------------------------------------------------------------------
 
 template <int ACC, int U, int KB>
 __global__ void __launch_bounds__(1024) batch_phase1_kernel(BatchArgs a) {
   __shared__ Acc<ACC> slots[MAX_WAVES];
   __shared__ RowRes s_bcast;
-  const int64_t n_items = a.cnt[CNT_ITEMS];
   const int64_t n_long = a.cnt[CNT_LONG_ITEMS];
+  // with resident rows the items after the long rows' tiles are the
+  // resident kernel's
+  const int64_t n_items = a.res_on ? n_long : a.cnt[CNT_ITEMS];
   const int64_t keep_item = n_long - a.keep_tiles;
   float* lse = lse_out(a);
   Acc<ACC>* part = reinterpret_cast<Acc<ACC>*>(a.partials);
@@ -932,6 +1193,11 @@ hipError_t phase2_acc(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
 
 template <int ACC>
 hipError_t launch_phases(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
+  if (p.res_grid > 0) {
+    hipLaunchKernelGGL((batch_resident_kernel<ACC>), dim3((unsigned)p.res_grid), dim3(RES_BLOCK), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipError_t e = phase1_u<ACC>(p, a, s);
   if (e != hipSuccess) return e;
   e = rowsum_acc<ACC>(p, a, s);

@@ -27,7 +27,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr size_t kTableOffset = 256;
 // The planner's counters, then the device error word, in one small region.
 constexpr size_t kErrorOffset = sizeof(int64_t) * nrm::CNT_COUNT;
-constexpr size_t kSmallBytes = 64;
+constexpr size_t kSmallBytes = 128;
 static_assert(kErrorOffset + sizeof(int) <= kSmallBytes, "counters and error word must fit");
 static_assert(sizeof(BatchHeader) <= kTableOffset, "header must fit before the table");
 int64_t align_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
@@ -48,6 +48,10 @@ nrm_batch_params default_batch_params() {
   p.map_block = 1024;
   p.map_grid = 1024;
   p.keep_mib = 256;
+  // rows up to 64 segments of 2^14 elements (2^20) are held on chip between
+  // their read and their write; two 512-thread blocks per CU
+  p.resident_segments = 64;
+  p.resident_grid = 512;
   return p;
 }
 
@@ -62,8 +66,13 @@ int check_batch_params(const nrm_batch_params& p) {
   if (p.tile_log2 < 10 || p.tile_log2 > 22) return fail(NRM_EINVAL, "tile_log2 must be 10..22");
   if (p.graph != 0 && p.graph != 1) return fail(NRM_EINVAL, "graph must be 0 or 1");
   if (p.keep_mib < 0 || p.keep_mib > 4096) return fail(NRM_EINVAL, "keep_mib must be 0..4096");
-  for (int r : p.reserved)
-    if (r != 0) return fail(NRM_EINVAL, "reserved fields must be zero");
+  if (p.resident_segments < 0 || p.resident_segments > nrm::RES_MAX_SEGMENTS)
+    return fail(NRM_EINVAL, "resident_segments must be 0..64");
+  if (p.resident_grid < 1 || p.resident_grid > (1 << 20)) return fail(NRM_EINVAL, "resident_grid must be 1..2^20");
+  // the blocks of one resident row wait for each other: the kernel must be
+  // able to hold a whole row's segments in running blocks at once
+  if (p.resident_grid < p.resident_segments)
+    return fail(NRM_EINVAL, "resident_grid must be at least resident_segments");
   // a tile's per-thread summation tree must stay within the plain path's
   // height bound (36) for every input dtype: 4-byte elements give the most
   // iterations, 2-byte elements the most additions per iteration
@@ -76,7 +85,11 @@ int check_batch_params(const nrm_batch_params& p) {
   return NRM_OK;
 }
 
-int64_t short_max_of(const nrm_batch_params& p) { return (int64_t)p.block * p.short_regs * 4; }
+// Rows of at most this many elements are not long: single-pass rows, or
+// resident rows when those are on.
+int64_t short_max_of(const nrm_batch_params& p) {
+  return p.resident_segments > 0 ? (int64_t)p.resident_segments << nrm::RES_LOG2 : (int64_t)p.block * p.short_regs * 4;
+}
 
 bool any_graph(const BatchWorkspace& w) { return w.graph[0] || w.graph[1] || w.graph[2]; }
 
@@ -89,7 +102,7 @@ void destroy_graph(BatchWorkspace& w) {
 
 // Layout of the single device allocation.
 struct Layout {
-  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, small, partials, total;
+  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, small, partials, tagged, total;
 };
 
 // Phase-2 chunks a workspace holds beyond one per item: the planner sizes the
@@ -113,6 +126,7 @@ Layout layout_for(int64_t cap_rows, int64_t cap_items, int64_t cap_chunks) {
   L.chunk_lrow = take(sizeof(int32_t) * cap_chunks);
   L.small = take(kSmallBytes);  // the planner's counters, then the error word
   L.partials = take(8 * cap_items);
+  L.tagged = take(16 * cap_items);
   L.total = off;
   return L;
 }
@@ -174,11 +188,14 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   w.cnt = reinterpret_cast<int64_t*>(d + L.small);
   w.error = reinterpret_cast<int*>(d + L.small + kErrorOffset);
   w.partials = d + L.partials;
+  w.tagged = reinterpret_cast<unsigned long long*>(d + L.tagged);
   w.cap_rows = cap_rows;
   w.cap_items = cap_items;
   w.cap_chunks = cap_chunks;
   w.staged_pending = false;
+  // the counters (the call number starts at 0) and the resident rows' tags
   e = hipMemset(d + L.small, 0, kSmallBytes);
+  if (e == hipSuccess) e = hipMemset(d + L.tagged, 0, 16 * (size_t)cap_items);
   if (e == hipSuccess && err_word) e = hipMemcpy(w.error, &err_word, sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemset");
   if (!w.staged) {
@@ -190,7 +207,9 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
 
 // Items a batch of `rows` rows and at most `elems` elements can need.
 int64_t items_bound(const nrm_batch_params& p, int64_t rows, int64_t elems) {
-  return rows + ceil_div(std::max<int64_t>(elems, 0), int64_t(1) << p.tile_log2);
+  // a long row has ceil(n / tile) items, a resident row ceil(n / 2^RES_LOG2)
+  const int lg = p.resident_segments > 0 ? std::min(p.tile_log2, nrm::RES_LOG2) : p.tile_log2;
+  return rows + ceil_div(std::max<int64_t>(elems, 0), int64_t(1) << lg);
 }
 
 BatchArgs args_of(const nrm_ctx* c) {
@@ -217,6 +236,8 @@ BatchArgs args_of(const nrm_ctx* c) {
   a.min_chunk = (int64_t)c->bparams.map_block * c->bparams.map_unroll * 4;
   // tiles counted at 4 bytes per element: at most keep_mib MiB for any dtype
   a.keep_tiles = ((int64_t)c->bparams.keep_mib << 20) / (a.tile * 4);
+  a.res_on = c->bparams.resident_segments > 0;
+  a.tagged = w.tagged;
   return a;
 }
 
@@ -230,6 +251,7 @@ BatchPlan plan_of(const nrm_ctx* c, int acc) {
   p.grid = c->bparams.grid;
   p.map_block = c->bparams.map_block;
   p.map_grid = c->bparams.map_grid;
+  p.res_grid = c->bparams.resident_segments > 0 ? c->bparams.resident_grid : 0;
   return p;
 }
 
@@ -517,6 +539,7 @@ int nrm_get_device_error(nrm_ctx* c, void* stream) {
   if (word & nrm::NRM_DEVERR_ROW) why += "invalid table row or row with too many tiles; ";
   if (word & nrm::NRM_DEVERR_CAPACITY) why += "batch larger than the workspace; ";
   if (word & nrm::NRM_DEVERR_TARGET) why += "NLL target outside [0, classes); ";
+  if (word & nrm::NRM_DEVERR_STALL) why += "a resident row's segment sums did not all arrive within the spin limit; ";
   return fail(NRM_EDEVICE, why + "those rows or samples were skipped");
 }
 

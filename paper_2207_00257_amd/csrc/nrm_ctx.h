@@ -61,6 +61,7 @@ struct BatchWorkspace {
   int64_t* cnt = nullptr;
   int* error = nullptr;
   void* partials = nullptr;
+  unsigned long long* tagged = nullptr;  // resident rows' tagged partials
   void* host = nullptr;        // pinned staging (host view): header, then the table
   hipEvent_t staged = nullptr; // recorded once the staging buffer may be rewritten
   bool staged_pending = false;

@@ -73,6 +73,10 @@ BATCH_PARAMS = [
     dict(keep_mib=0),                   # every tile non-temporal
     dict(keep_mib=1, tile_log2=10),     # the last 256 tiles temporal, the rest not
     dict(keep_mib=4096, graph=1),       # every tile temporal
+    dict(resident_segments=0),          # single-pass rows and tiles only
+    dict(resident_segments=1, resident_grid=3),   # one-segment resident rows, the rest tiled
+    dict(resident_segments=3, resident_grid=5, graph=1),
+    dict(resident_segments=64, resident_grid=64, tile_log2=11),
 ]
 
 
@@ -95,14 +99,15 @@ def test_batch_parameter_validation():
     good = ctx.get_batch_params()
     for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(short_regs=0),
                 dict(grid=0), dict(map_grid=0), dict(tile_log2=9), dict(tile_log2=23), dict(graph=2),
-                dict(keep_mib=-1), dict(keep_mib=4097)):
+                dict(keep_mib=-1), dict(keep_mib=4097), dict(resident_segments=-1), dict(resident_segments=65),
+                dict(resident_segments=4, resident_grid=0), dict(resident_segments=8, resident_grid=4)):
         with pytest.raises(L.NrmError):
             ctx.set_batch_params(**bad)
         assert ctx.get_batch_params() == good, bad
     p = L.NrmBatchParams()
     assert L.lib().nrm_default_batch_params(ctypes.byref(p)) == L.NRM_OK
-    assert {f: getattr(p, f) for f, _ in L.NrmBatchParams._fields_ if f != "reserved"} == good
-    p.reserved[1] = 1
+    assert {f: getattr(p, f) for f, _ in L.NrmBatchParams._fields_} == good
+    p.resident_grid = -1
     assert L.lib().nrm_set_batch_params(ctx.handle, ctypes.byref(p)) == L.NRM_EINVAL
     ctx.close()
 
@@ -339,21 +344,25 @@ def test_random_batches_match_oracle(seed):
     one element, the single-pass limit, whole tiles and one element either
     side), random launch shapes, graph replay or not."""
     rng = np.random.default_rng(1000 + seed)
-    shapes = [dict(), dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7),
-              dict(block=512, unroll=2, short_regs=2, tile_log2=13, map_grid=33), dict(graph=1, tile_log2=12),
-              dict(keep_mib=0, map_block=256, map_unroll=8, grid=100)]
+    shapes = [dict(), dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7, resident_segments=0),
+              dict(block=512, unroll=2, short_regs=2, tile_log2=13, map_grid=33, resident_segments=2),
+              dict(graph=1, tile_log2=12, resident_segments=5, resident_grid=9),
+              dict(keep_mib=0, map_block=256, map_unroll=8, grid=100, resident_segments=0),
+              dict(graph=1, resident_segments=64)]
     params = shapes[seed % len(shapes)]
     ctx = api.Context()
     ctx.set_batch_params(**params)
     bp = ctx.get_batch_params()
-    short_max = bp["block"] * bp["short_regs"] * 4
+    seg = 1 << 14  # elements of one resident segment
+    short_max = (bp["resident_segments"] * seg if bp["resident_segments"] else
+                 bp["block"] * bp["short_regs"] * 4)
     tile = 1 << bp["tile_log2"]
     edges = np.array([0, 1, 2, short_max - 1, short_max, short_max + 1, tile - 1, tile, tile + 1, 2 * tile + 3,
-                      3 * tile], np.int64)
+                      3 * tile, seg - 1, seg, seg + 1, 2 * seg + 1], np.int64)
     rows = int(rng.integers(1, 3001))
     kind = rng.integers(0, 3, rows)
     lengths = np.where(kind == 0, rng.choice(edges, rows), rng.integers(0, 3 * short_max, rows))
-    lengths[kind == 2] = rng.integers(short_max, 6 * tile, int((kind == 2).sum()))
+    lengths[kind == 2] = rng.integers(short_max, max(6 * tile, 2 * short_max), int((kind == 2).sum()))
     while lengths.sum() > 12_000_000:  # keep the oracle quick
         lengths //= 2
     offs = synth.ragged_offsets(lengths)
@@ -373,5 +382,46 @@ def test_many_rows_planner_rounds():
     x = synth.lognormal_f32(int(offs[-1]), 142, 1.0)
     ctx = api.Context()
     check_rows(run_csr(x, offs, ctx).cpu().numpy(), x, offs, "5000 rows")
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+RESIDENT_LENGTHS = [1, (1 << 14) - 1, 1 << 14, (1 << 14) + 1, 2 * (1 << 14) + 5, 0, 63 * (1 << 14) + 3,
+                    1 << 20, (1 << 20) + 1, 37, 5 * (1 << 14)]
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+def test_resident_rows_across_segment_boundaries(accum):
+    """Rows held on chip between their read and their write, with lengths at
+    the segment boundaries (2^14 elements), up to the 64-segment limit (2^20)
+    and one past it (a tiled row), at misaligned starts; then the same rows
+    with the resident path off: both within the bound of the oracle."""
+    lengths = np.array(RESIDENT_LENGTHS, np.int64)
+    offs = synth.ragged_offsets(lengths) + 3  # every row starts 12 bytes past a line
+    x = synth.lognormal_f32(int(offs[-1]), 150, 1.0)
+    for seg in (64, 0):
+        ctx = api.Context()
+        ctx.set_batch_params(resident_segments=seg)
+        got = run_csr(x, offs, ctx, accum=accum).cpu().numpy()
+        check_rows(got, x, offs, "resident_segments=%d %s" % (seg, accum))
+        assert ctx.device_error() == L.NRM_OK
+        ctx.close()
+
+
+def test_resident_rows_repeat_bitwise_and_position_independent():
+    """A resident row's result depends only on its length and alignment: the
+    same row alone, in a batch, and on a later call (the tags of the earlier
+    call's partials must not be taken for this call's) gives the same bits."""
+    n = 7 * (1 << 14) + 11
+    row = synth.lognormal_f32(n, 151, 1.0)
+    ctx = api.Context()
+    ctx.set_batch_params(graph=1)
+    alone = run_csr(row, np.array([0, n], np.int64), ctx).cpu().numpy()
+    other = synth.lognormal_f32(3 * (1 << 14) + 64, 152, 1.0)
+    x = np.concatenate([other, row, other])
+    offs = np.array([0, other.size, other.size + n, x.size], np.int64)
+    for _ in range(3):
+        got = run_csr(x, offs, ctx).cpu().numpy()
+        assert np.array_equal(got[other.size:other.size + n].view(np.uint32), alone.view(np.uint32))
     assert ctx.device_error() == L.NRM_OK
     ctx.close()

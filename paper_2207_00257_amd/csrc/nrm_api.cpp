@@ -558,6 +558,21 @@ int nrm_normalize_form(int form, float* out, const float* in, int64_t n, int blo
   return NRM_OK;
 }
 
+int nrm_ceiling(int kind, void* dst, const void* src, int64_t bytes, int64_t grid, void* stream) {
+  if (kind != NRM_CEILING_COPY && kind != NRM_CEILING_READ) return fail(NRM_EINVAL, "unknown ceiling kind");
+  if (bytes < 0 || bytes % 16) return fail(NRM_EINVAL, "bytes must be a non-negative multiple of 16");
+  if (grid < 1 || grid > (1 << 20)) return fail(NRM_EINVAL, "grid must be 1..2^20");
+  if (bytes == 0) return NRM_OK;
+  if (!dst || !src) return fail(NRM_EINVAL, "NULL pointer");
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
+    return fail(NRM_EINVAL, "pointers must be 16-byte aligned");
+  const int64_t dst_bytes = kind == NRM_CEILING_COPY ? bytes : 4 * grid;
+  if (overlaps(dst, dst_bytes, src, bytes)) return fail(NRM_EOVERLAP, "dst overlaps src");
+  hipError_t e = nrm::launch_ceiling(kind, dst, src, bytes, grid, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "ceiling kernel launch");
+  return NRM_OK;
+}
+
 int normalize(float* out, const float* in, int64_t n) {
   return nrm_normalize_ex(nullptr, out, NRM_F32, in, NRM_F32, n, NRM_ACC_F32, nullptr);
 }

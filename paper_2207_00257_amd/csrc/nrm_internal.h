@@ -117,4 +117,8 @@ hipError_t launch_nll(const NllPlan& p, void* partials, int* error, hipStream_t 
 hipError_t launch_form(int form, float* out, const float* in, int64_t n, int block, hipStream_t s);
 hipError_t launch_map(const PlainPlan& p, const PlainWorkspace& ws, hipStream_t s);
 
+// Bandwidth ceilings for measurement (nrm_ceiling.hip): kind 0 copies `bytes`
+// from src to dst, kind 1 reads them (dst: a word per block, rarely written).
+hipError_t launch_ceiling(int kind, void* dst, const void* src, int64_t bytes, int64_t grid, hipStream_t s);
+
 }  // namespace nrm

@@ -112,6 +112,10 @@ typedef struct {
                            reads the input once into registers (16 binary32 or 8 2-byte vectors
                            per thread), reduces it, and divides from the registers: one read,
                            one write, one launch; 0: never */
+  int32_t resident_n;   /* 0..2^20: n in (small_n, resident_n] runs as one launch of one 256-thread
+                           block per 4096 elements, each block holding its elements in registers
+                           while the blocks exchange their sums: one read, one write, one launch
+                           (all n / 4096 blocks must be able to run at once: one per CU); 0: never */
 } nrm_params;
 
 /* Launch parameters of the ragged batched path. Start from
@@ -175,10 +179,12 @@ int normalize_batched(float* out, const float* in, const int64_t* offsets, int64
 
 /* For callers that cannot allocate device memory: code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc. Computes exactly what
- * nrm_normalize_ex does on the current device's default context (same
- * kernels, same default launch parameters, same bits), but takes no context
+ * nrm_normalize_ex does on a context of the current device whose parameters
+ * are the library's defaults for it (same kernels, same launch parameters,
+ * same bits; the tuning cache is not read), but takes no context
  * and calls no hipMalloc, hipFree or other allocating routine: the workspace
- * (block partials, combine ticket, sum) is a fixed array of
+ * (block partials, combine ticket, sum, the mid-size form's exchange slots)
+ * is a fixed array of
  * NRM_NOALLOC_SCRATCH_BYTES bytes in the library's code object, one copy per
  * device, held until the process ends. The first call on a device looks up
  * that device's copy and enqueues one tiny kernel on `stream` to clear the
@@ -193,20 +199,26 @@ int normalize_batched(float* out, const float* in, const int64_t* offsets, int64
  * call's contents: calls that overlap in time on one device (unordered
  * streams, several host threads) race on it and give wrong results; order
  * them (one stream, or events). Asynchronous like every other call. */
-#define NRM_NOALLOC_SCRATCH_BYTES 131328
+#define NRM_NOALLOC_SCRATCH_BYTES 135680
 int nrm_normalize_noalloc(void* out, int out_dtype, const void* in, int in_dtype, int64_t n, int accum,
                           void* stream);
 
 /* ---- contexts ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device` (-1: the current device). The
- * context owns workspace on that device and the launch parameters. */
+ * context owns workspace on that device and the launch parameters. Until
+ * nrm_set_params is called on it, each plain call takes the launch
+ * parameters the autotuner stored for its key (device architecture, dtypes,
+ * accumulation, size class floor(log2 n)) in the tuning cache, the JSON file
+ * named by $NRM_TUNE_CACHE or else tuned/plain.json next to libnrm.so, and
+ * the library defaults where the cache has no entry. */
 int nrm_create(nrm_ctx** ctx, int device);
 /* Free the context's workspace. Waits for the device to be idle first. */
 int nrm_destroy(nrm_ctx* ctx);
 /* The library's default launch parameters (tuned for MI355X). */
 int nrm_default_params(nrm_params* params);
-/* Replace the context's launch parameters; NRM_EINVAL if any field is out of range. */
+/* Replace the context's launch parameters (from then on they apply to every
+ * call, in place of the tuning cache); NRM_EINVAL if any field is out of range. */
 int nrm_set_params(nrm_ctx* ctx, const nrm_params* params);
 int nrm_get_params(const nrm_ctx* ctx, nrm_params* params);
 
@@ -259,25 +271,28 @@ int nrm_nll_loss(nrm_ctx* ctx, float* out, float* total_weight, const float* log
  * a halving tree over y (row y ends with the sum of p over rows y .. y + L(y)
  * - 1, L(y) the largest power of two dividing y, 16 for y = 0), every row
  * written back to hidden, and output[16 b + x] = the column sums (tile row 0).
- *   NRM_LF_PRINTED     every barrier of the example as analysed;
- *   NRM_LF_ELIMINATED  without the two barriers Sec. IV-A proves redundant;
- *   NRM_LF_PROMOTED    also without the shared store/load a thread makes only
- *                      to itself across a barrier (Sec. IV-B);
- *   NRM_LF_REGISTERS   the tile kept in registers, one thread per column:
- *                      no shared memory and no barrier.
+ *   NRM_LF_ALL_BARRIERS  a block barrier after every stage (scale load, tile
+ *                        load, scaling, each tree level, write-back);
+ *   NRM_LF_ELIMINATED    without the two barriers that Sec. IV-A's rule finds
+ *                        no conflicting access across (after the scale load
+ *                        and after the write-back);
+ *   NRM_LF_PROMOTED      also without the shared store/load a thread makes
+ *                        only to itself across a barrier (Sec. IV-B);
+ *   NRM_LF_REGISTERS     the tile kept in registers, one thread per column:
+ *                        no shared memory and no barrier.
  * The forms compute the same values bit for bit (products rounded to binary32,
  * the tree's additions in the same order). hidden, input and output must not
  * overlap (NRM_EOVERLAP). */
-typedef enum { NRM_LF_PRINTED = 0, NRM_LF_ELIMINATED = 1, NRM_LF_PROMOTED = 2, NRM_LF_REGISTERS = 3 } nrm_lf_form;
+typedef enum { NRM_LF_ALL_BARRIERS = 0, NRM_LF_ELIMINATED = 1, NRM_LF_PROMOTED = 2, NRM_LF_REGISTERS = 3 } nrm_lf_form;
 int nrm_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows, void* stream);
 
 /* ---- the un-hoisted forms, for measurement ------------------------------- */
 
 /* Fig. 1's two slower forms on the GPU: NRM_FORM_NAIVE, every thread sums the
- * whole input itself (O(n^2) work); NRM_FORM_PERBLOCK, thread 0 of each block
- * sums it into block-shared memory, a block barrier, then every thread
- * divides (O(n^2 / block)). FP32, 1 <= n <= 2^20, block 64..1024 (multiple
- * of 64). Each per-thread sum is a Kahan-compensated binary32 chain. They
+ * whole input itself (O(n^2) work); NRM_FORM_PERBLOCK, the first wavefront of
+ * each block sums it into block-shared memory, a block barrier, then every
+ * thread divides (O(n^2 / block)). FP32, 1 <= n <= 2^20, block 64..1024
+ * (multiple of 64). The sums are Kahan-compensated binary32 chains. They
  * exist to measure what the hoisted form saves; they are not fast paths. */
 typedef enum { NRM_FORM_NAIVE = 1, NRM_FORM_PERBLOCK = 2 } nrm_form;
 int nrm_normalize_form(int form, float* out, const float* in, int64_t n, int block, void* stream);
@@ -325,9 +340,11 @@ int nrm_softmax_batched(nrm_ctx* ctx, float* out, const float* in, const int64_t
                         int64_t capacity, float* lse, void* stream);
 
 /* Table form: `rows` is a HOST array of nrows descriptors (device data
- * pointers), copied to the device through the context's pinned staging
- * memory; rows may mix dtypes. Rows are validated on the host. The staging
- * buffer is reused only after the previous call's copy has executed. */
+ * pointers), staged in the context's pinned memory, which the device reads in
+ * place; rows may mix dtypes. Rows are validated on the host. The context
+ * keeps four such staging buffers and uses them in turn (the CSR forms stage
+ * their arguments the same way): a call blocks the host only while the call
+ * four before it on the same context has not finished. */
 int nrm_normalize_rows(nrm_ctx* ctx, const nrm_row* rows, int64_t nrows, int accum, void* stream);
 
 /* Reserve batched workspace for up to max_rows rows and max_elems elements
@@ -406,6 +423,7 @@ typedef struct {
   int64_t batches;
   int64_t launches;    /* library calls made (batched calls or plain calls) */
   int64_t replaying;
+  int64_t failed;      /* requests completed with an error status */
 } nrm_server_counters;
 
 typedef struct nrm_server nrm_server;
@@ -420,8 +438,14 @@ int nrm_server_submit(nrm_server* server, const nrm_request* reqs, int64_t count
 /* Submit a trace from a background thread at its scheduled times (open
  * loop; requests sorted by t_arrival_ns). *t0_ns receives the start time. */
 int nrm_server_replay(nrm_server* server, const nrm_request* reqs, int64_t count, int64_t* t0_ns);
-/* Move up to max completions into out; *count receives how many. */
+/* Move up to max completions into out; *count receives how many. Each
+ * completion carries its own status: a request whose launch or execution
+ * failed completes with that error (its output is not valid and its memory is
+ * already released); poll itself fails only on bad arguments. */
 int nrm_server_poll(nrm_server* server, nrm_completion* out, int64_t max, int64_t* count);
+/* NRM_OK if no request has failed so far, else the first failure's status,
+ * with its text in nrm_last_error(). */
+int nrm_server_last_failure(nrm_server* server);
 /* Release a held output (hold_outputs = 1). */
 int nrm_server_release(nrm_server* server, int64_t id);
 int nrm_server_stats(nrm_server* server, nrm_server_counters* counters);
@@ -445,6 +469,12 @@ int nrm_get_last_sum(nrm_ctx* ctx, void* stream, float* sum);
  * 16-byte aligned, not overlapping; grid 1..2^20. Asynchronous on `stream`. */
 typedef enum { NRM_CEILING_COPY = 0, NRM_CEILING_READ = 1 } nrm_ceiling_kind;
 int nrm_ceiling(int kind, void* dst, const void* src, int64_t bytes, int64_t grid, void* stream);
+
+/* The tuning cache's parameters for a call key (architecture name such as
+ * "gfx950", dtypes, accumulation, n): writes them over nrm_default_params()
+ * and returns 1, or returns 0 (params = the defaults) when the cache has no
+ * entry for the key. No HIP call. */
+int nrm_tuned_params(const char* arch, int in_dtype, int out_dtype, int accum, int64_t n, nrm_params* params);
 
 /* Static text for a status code. */
 const char* nrm_status_string(int status);

@@ -18,6 +18,7 @@ NRM_ACC_F32, NRM_ACC_KAHAN = 0, 1
 NRM_NLL_NONE, NRM_NLL_SUM, NRM_NLL_MEAN = 0, 1, 2
 NRM_LAYOUT_CHUNK, NRM_LAYOUT_STRIDE = 0, 1
 NRM_FORM_NAIVE, NRM_FORM_PERBLOCK = 1, 2
+NRM_CEILING_COPY, NRM_CEILING_READ = 0, 1
 
 
 class NrmParams(ctypes.Structure):
@@ -38,6 +39,7 @@ class NrmParams(ctypes.Structure):
         ("tile_log2", ctypes.c_int32),
         ("fused_combine", ctypes.c_int32),
         ("small_n", ctypes.c_int32),
+        ("resident_n", ctypes.c_int32),
     ]
 
 
@@ -113,7 +115,7 @@ class NrmServerConfig(ctypes.Structure):
 
 class NrmServerCounters(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
-                ("in_flight", "queued", "held", "budget_used", "batches", "launches", "replaying")]
+                ("in_flight", "queued", "held", "budget_used", "batches", "launches", "replaying", "failed")]
 
 
 class NrmError(RuntimeError):
@@ -137,6 +139,7 @@ def _declare(lib):
         "nrm_normalize_ex": (i32, [p, p, i32, p, i32, i64, i32, p]),
         "nrm_normalize_noalloc": (i32, [p, i32, p, i32, i64, i32, p]),
         "nrm_ceiling": (i32, [i32, p, p, i64, i64, p]),
+        "nrm_tuned_params": (i32, [ctypes.c_char_p, i32, i32, i32, i64, ctypes.POINTER(NrmParams)]),
         "nrm_status_string": (ctypes.c_char_p, [i32]),
         "nrm_last_error": (ctypes.c_char_p, []),
         "nrm_set_timing": (i32, [p, i32]),
@@ -162,6 +165,7 @@ def _declare(lib):
         "nrm_server_replay": (i32, [p, ctypes.POINTER(NrmRequest), i64, ctypes.POINTER(ctypes.c_int64)]),
         "nrm_server_poll": (i32, [p, ctypes.POINTER(NrmCompletion), i64, ctypes.POINTER(ctypes.c_int64)]),
         "nrm_server_release": (i32, [p, i64]),
+        "nrm_server_last_failure": (i32, [p]),
         "nrm_server_stats": (i32, [p, ctypes.POINTER(NrmServerCounters)]),
         "nrm_server_destroy": (i32, [p]),
     }

@@ -209,13 +209,14 @@ def softmax_batched(out, inp, offsets, lse=None, ctx: Optional[Context] = None, 
     return out
 
 
-_LF_FORMS = {"printed": 0, "eliminated": 1, "promoted": 2, "registers": 3}
+_LF_FORMS = {"all": 0, "eliminated": 1, "promoted": 2, "registers": 3}
 
 
-def layerforward(hidden, inp, output, form: str = "printed", stream: Optional[int] = None):
+def layerforward(hidden, inp, output, form: str = "all", stream: Optional[int] = None):
     """The Fig. 9-shaped tile kernel (see nrm_layerforward in include/nrm.h):
     hidden float32 [R, 16] (updated in place), inp and output float32 [R],
-    R a multiple of 16; form "printed", "eliminated" or "promoted"."""
+    R a multiple of 16; form "all" (every barrier), "eliminated", "promoted"
+    or "registers"."""
     import torch
 
     if form not in _LF_FORMS:

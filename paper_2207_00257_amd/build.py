@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnrm.so")
 
 SOURCES = ["nrm_kernels.hip", "nrm_batched.hip", "nrm_forms.hip", "nrm_nll.hip", "nrm_layerforward.hip", "nrm_ceiling.hip", "nrm_api.cpp",
-           "nrm_batched_api.cpp", "nrm_server.cpp", "nrm_noalloc.cpp"]
+           "nrm_batched_api.cpp", "nrm_server.cpp", "nrm_noalloc.cpp", "nrm_tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -46,18 +46,37 @@ def _compile(src: str) -> str:
     return obj
 
 
+HOST_LIB = os.path.join(PKG, "libnrm_host.so")
+
+
+def build_host(verbose: bool = False) -> str:
+    """The benchmark's host comparison points (csrc/host_baseline.cpp) as
+    their own library: libnrm.so neither links nor calls them."""
+    tmp = HOST_LIB + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall",
+           os.path.join(CSRC, "host_baseline.cpp"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, HOST_LIB)
+    if verbose:
+        print("built", HOST_LIB)
+    return HOST_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
+    build_host(verbose)
     return LIB
 
 

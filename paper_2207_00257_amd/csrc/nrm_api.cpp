@@ -58,6 +58,7 @@ nrm_params default_params() {
   p.tile_log2 = 12;
   p.fused_combine = 1;
   p.small_n = 65536;
+  p.resident_n = 1 << 20;
   return p;
 }
 
@@ -78,8 +79,15 @@ int check_params(const nrm_params& p) {
   if (p.tile_log2 < 10 || p.tile_log2 > 22) return fail(NRM_EINVAL, "tile_log2 must be 10..22");
   if (!ok_f(p.fused_combine)) return fail(NRM_EINVAL, "fused_combine must be 0 or 1");
   if (p.small_n < 0 || p.small_n > (1 << 16)) return fail(NRM_EINVAL, "small_n must be 0..2^16");
+  if (p.resident_n < 0 || p.resident_n > (1 << 20)) return fail(NRM_EINVAL, "resident_n must be 0..2^20");
   return NRM_OK;
 }
+
+// The context's small workspace: the ticket (0), the sum (128), the device
+// error word (192), the mid-size single-launch form's call number (256),
+// arrival count (264), stall marker (272) and merged total (288), and from
+// 512 its segments' tagged partials (256 x 16 bytes).
+constexpr size_t kSmallWs = 512 + 256 * 16;
 
 std::mutex g_default_mu;
 std::map<int, nrm_ctx*> g_default;
@@ -308,7 +316,7 @@ int nrm_nll_loss(nrm_ctx* c, float* out, float* total_weight, const float* logp,
 }
 
 int nrm_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows, void* stream) {
-  if (form != NRM_LF_PRINTED && form != NRM_LF_ELIMINATED && form != NRM_LF_PROMOTED && form != NRM_LF_REGISTERS)
+  if (form != NRM_LF_ALL_BARRIERS && form != NRM_LF_ELIMINATED && form != NRM_LF_PROMOTED && form != NRM_LF_REGISTERS)
     return fail(NRM_EINVAL, "unknown form");
   if (rows < 0 || rows % 16) return fail(NRM_EINVAL, "rows must be a non-negative multiple of 16");
   if (rows / 16 > INT32_MAX) return fail(NRM_EINVAL, "too many rows for one launch");
@@ -376,22 +384,28 @@ int nrm_create(nrm_ctx** ctx, int device) {
   nrm_ctx* c = new nrm_ctx();
   c->device = device;
   c->params = nrm::device_params(device);
+  c->arch = nrm::device_arch(device);
   nrm_default_batch_params(&c->bparams);
   void* small = nullptr;
-  e = hipMalloc(&small, 256);
+  e = hipMalloc(&small, kSmallWs);
   if (e != hipSuccess) {
     delete c;
     return fail(NRM_ENOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
   }
-  e = hipMemset(small, 0, 256);
+  e = hipMemset(small, 0, kSmallWs);
   if (e != hipSuccess) {
     (void)hipFree(small);  // already failing
     delete c;
     return hip_fail(e, "hipMemset");
   }
-  c->ticket = static_cast<unsigned*>(small);
-  c->sum = reinterpret_cast<float*>(static_cast<char*>(small) + 128);
-  c->dev_error = reinterpret_cast<int*>(static_cast<char*>(small) + 192);
+  char* sm = static_cast<char*>(small);
+  c->ticket = reinterpret_cast<unsigned*>(sm);
+  c->sum = reinterpret_cast<float*>(sm + 128);
+  c->dev_error = reinterpret_cast<int*>(sm + 192);
+  c->res = nrm::PlainResidentWs{reinterpret_cast<unsigned long long*>(sm + 512),
+                                reinterpret_cast<unsigned long long*>(sm + 288), reinterpret_cast<unsigned*>(sm + 264),
+                                reinterpret_cast<unsigned long long*>(sm + 256),
+                                reinterpret_cast<unsigned long long*>(sm + 272), c->dev_error, c->sum};
   int st = ensure_partials(c, 16384);
   if (st != NRM_OK) {
     (void)hipFree(small);
@@ -430,6 +444,7 @@ int nrm_set_params(nrm_ctx* c, const nrm_params* params) {
   int st = check_params(*params);
   if (st != NRM_OK) return st;
   c->params = *params;
+  c->params_set = true;  // explicit parameters replace the tuning cache's
   return NRM_OK;
 }
 
@@ -482,6 +497,26 @@ int nrm_kernel_times(nrm_ctx* c, double* reduce_ms, double* map_ms, int64_t* cal
   return NRM_OK;
 }
 
+namespace {
+// The parameters of one call: the context's explicit ones, or the tuning
+// cache's entry for the call's key over the context's defaults (looked up
+// once per key and context).
+const nrm_params& call_params(nrm_ctx* c, int in_dt, int out_dt, int acc, int64_t n) {
+  if (c->params_set) return c->params;
+  int k = 0;
+  while ((int64_t(1) << (k + 1)) <= n && k < 62) ++k;
+  const int64_t key = ((int64_t)(in_dt * 3 + out_dt) * 2 + acc) * 64 + k;
+  auto it = c->tuned.find(key);
+  if (it == c->tuned.end()) {
+    nrm_params q = c->params;
+    bool has = nrm::tuned_plain(c->arch, in_dt, out_dt, acc, n, &q);
+    if (has && check_params(q) != NRM_OK) has = false;  // an entry this build would reject
+    it = c->tuned.emplace(key, std::make_pair(has, q)).first;
+  }
+  return it->second.first ? it->second.second : c->params;
+}
+}  // namespace
+
 int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype, int64_t n,
                      int accum, void* stream) {
   int st0 = nrm::check_plain_args(out, out_dtype, in, in_dtype, n, accum);
@@ -490,7 +525,8 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
-  if (n <= c->params.small_n && n <= nrm::small_capacity(in_dtype)) {
+  const nrm_params& q = call_params(c, in_dtype, out_dtype, accum, n);
+  if (n <= q.small_n && n <= nrm::small_capacity(in_dtype)) {
     // one block, the input held in registers: one read, one write, one launch
     DeviceGuard g(c->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -508,8 +544,26 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
     }
     return NRM_OK;
   }
+  if (n <= q.resident_n && n <= nrm::plain_resident_capacity()) {
+    // one block per segment, held in registers across the exchange of sums
+    DeviceGuard g(c->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t* ev = nullptr;
+    if (c->timing) {
+      ev = &c->events[3 * (c->timed_calls % kTimingRing)];
+      c->timed_calls++;
+      (void)hipEventRecord(ev[0], s);
+    }
+    hipError_t e = nrm::launch_plain_resident(in, in_dtype, out, out_dtype, n, accum, c->res, s);
+    if (e != hipSuccess) return hip_fail(e, "mid-size normalize kernel launch");
+    if (ev) {
+      (void)hipEventRecord(ev[1], s);
+      (void)hipEventRecord(ev[2], s);
+    }
+    return NRM_OK;
+  }
   nrm::PlainPlan plan;
-  int st = nrm::plan_plain(c->params, out, out_dtype, in, in_dtype, n, accum, &plan);
+  int st = nrm::plan_plain(q, out, out_dtype, in, in_dtype, n, accum, &plan);
   if (st != NRM_OK) return st;
   DeviceGuard g(c->device);
   st = ensure_partials(c, plan.grid);

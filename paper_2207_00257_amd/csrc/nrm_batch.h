@@ -102,6 +102,8 @@ struct BatchArgs {
   // block's registers from its read to its write
   int res_on;
   unsigned long long* tagged;  // [2 * cap_items]: each segment's partial, two tagged words
+  unsigned long long* rowtot;  // [2 * cap_items]: a resident row's total at its first item, two tagged words
+  unsigned* arrivals;          // [cap_items]: a resident row's published segments at its first item (0 between calls)
 };
 
 // Elements of one resident segment: 512 threads x 8 vectors of 4 binary32

@@ -795,8 +795,8 @@ __device__ __forceinline__ void dispatch_tile_map(const RowDesc& d, int64_t b, i
 // block divides by the same bits) and divides its segment from registers.
 //
 // Progress: blocks take items from a counter (CNT_DISPENSE) in item order, a
-// row's items are consecutive, and a block takes an item only once it has
-// finished the previous one and publishes its sum before it waits. Every row
+// row's items are consecutive, a block takes an item only once it has
+// finished the previous one, and it publishes its sum before it waits. Every row
 // before the one holding the last item taken therefore has all its items in
 // running blocks, each of which publishes: their waits end. Only that last
 // row can wait on items not yet taken, and at most RES_MAX_SEGMENTS - 1 of
@@ -842,68 +842,137 @@ struct Tagged {
   }
 };
 
+// Where one row's segments meet: segment s's tagged words at slots[2 s] and
+// slots[2 s + 1]; the count of segments that have published (0 between
+// calls); the row's merged total, two tagged words. The last segment to
+// arrive merges all partials and publishes the total; the others wait for
+// that one word, so a row's blocks poll one location each instead of every
+// block polling every partial.
+struct ResExchange {
+  unsigned long long* slots;
+  unsigned long long* total;
+  unsigned* arrivals;
+  uint32_t ep;                // this call's number
+  int* error;                 // device error word (NRM_DEVERR_STALL)
+  unsigned long long* stall;  // the number of the last call in which a wait gave up
+  unsigned long long* call;   // when set: the call counter the last arrival moves on
+};
+
 template <int ACC>
-__device__ __forceinline__ void publish_tagged(unsigned long long* tagged, int64_t item, const Acc<ACC>& v,
-                                               uint32_t ep) {
+__device__ __forceinline__ void publish_tagged(unsigned long long* words, uint32_t ep, const Acc<ACC>& v) {
   float f[2];
   Tagged<ACC>::split(v, f);
 #pragma unroll
   for (int w = 0; w < Tagged<ACC>::WORDS; ++w)
-    __hip_atomic_store(tagged + 2 * item + w, ((unsigned long long)ep << 32) | bits_f32(f[w]), __ATOMIC_RELAXED,
+    __hip_atomic_store(words + w, ((unsigned long long)ep << 32) | bits_f32(f[w]), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wavefront 0 (all 64 lanes): wait for the nseg partials of the row whose
-// first item is `first`, lane l polling item first + l, then merge them with
-// the wavefront tree. Every lane returns the row's total.
-template <int ACC>
-__device__ __forceinline__ Acc<ACC> gather_row(const BatchArgs& a, int64_t first, int nseg, uint32_t ep) {
-  const int lane = threadIdx.x & 63;
-  float f[2] = {0.0f, 0.0f};
-  bool have = lane >= nseg;
-  for (uint32_t spin = 0;; ++spin) {
-    if (!have) {
-      have = true;
-#pragma unroll
-      for (int w = 0; w < Tagged<ACC>::WORDS; ++w) {
-        const unsigned long long x = __hip_atomic_load(a.tagged + 2 * (first + lane) + w, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-        f[w] = f32_bits((uint32_t)x);
-        have = have && (uint32_t)(x >> 32) == ep;
-      }
-    }
-    if (__all(have)) break;
-    unsigned long long* stall = reinterpret_cast<unsigned long long*>(a.cnt + CNT_STALL);
-    if (spin >= RES_SPIN_LIMIT) {
-      if (lane == 0) {
-        atomicOr(a.error, NRM_DEVERR_STALL);
-        __hip_atomic_store(stall, (unsigned long long)ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      break;
-    }
-    if ((spin & 255) == 255 && __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ep)
-      break;  // another wait of this call already gave up
-    __builtin_amdgcn_s_sleep(1);
-  }
-  Acc<ACC> v;
-  if (lane < nseg && have) v = Tagged<ACC>::join(f);
-  else v.zero();
-  return wave_reduce<ACC>(v);
+// A bounded wait has run out: flag it for the host and for this call's other
+// waits.
+__device__ __forceinline__ void give_up(const ResExchange& x) {
+  atomicOr(x.error, NRM_DEVERR_STALL);
+  __hip_atomic_store(x.stall, (unsigned long long)x.ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool given_up(const ResExchange& x, uint32_t spin) {
+  return (spin & 255) == 255 && __hip_atomic_load(x.stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == x.ep;
 }
 
-// One resident segment: read into registers, block sum, exchange with the
-// row's other segments, divide from the registers, write.
-template <int DTI, int DTO, int ACC>
-__device__ __forceinline__ void resident_unit(const BatchArgs& a, const RowDesc& d, int64_t row, int64_t item,
-                                              int seg, uint32_t ep, Acc<ACC>* slots, RowRes* s_bcast, float* lse) {
+// One thread: wait for the row's total (bounded), and return it.
+template <int ACC>
+__device__ __forceinline__ Acc<ACC> wait_total(const ResExchange& x) {
+  float f[2] = {0.0f, 0.0f};
+  for (uint32_t spin = 0;; ++spin) {
+    bool ok = true;
+#pragma unroll
+    for (int w = 0; w < Tagged<ACC>::WORDS; ++w) {
+      const unsigned long long v = __hip_atomic_load(x.total + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      f[w] = f32_bits((uint32_t)v);
+      ok = ok && (uint32_t)(v >> 32) == x.ep;
+    }
+    if (ok) break;
+    if (spin >= RES_SPIN_LIMIT) {
+      give_up(x);
+      break;
+    }
+    if (given_up(x, spin)) break;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return Tagged<ACC>::join(f);
+}
+
+// Wavefront 0 (all 64 lanes) of the last block to arrive: read the row's
+// nseg <= 64 * PER_LANE partials (each has been published; a word not yet
+// visible is read again), lane l taking segments l, l + 64, ..., then merge
+// them: each lane its own pairwise, then the wavefront tree. Every lane
+// returns the row's total; the order depends only on nseg.
+template <int ACC, int PER_LANE>
+__device__ __forceinline__ Acc<ACC> gather_row(const ResExchange& x, int nseg) {
+  const int lane = threadIdx.x & 63;
+  float f[PER_LANE][2];
+  bool have[PER_LANE];
+#pragma unroll
+  for (int j = 0; j < PER_LANE; ++j) {
+    f[j][0] = f[j][1] = 0.0f;
+    have[j] = lane + 64 * j >= nseg;
+  }
+  for (uint32_t spin = 0;; ++spin) {
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < PER_LANE; ++j) {
+      if (!have[j]) {
+        bool ok = true;
+#pragma unroll
+        for (int w = 0; w < Tagged<ACC>::WORDS; ++w) {
+          const unsigned long long v = __hip_atomic_load(x.slots + 2 * (lane + 64 * j) + w, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+          f[j][w] = f32_bits((uint32_t)v);
+          ok = ok && (uint32_t)(v >> 32) == x.ep;
+        }
+        have[j] = ok;
+      }
+      all = all && have[j];
+    }
+    if (__all(all)) break;
+    if (spin >= RES_SPIN_LIMIT) {
+      if (lane == 0) give_up(x);
+      break;
+    }
+    if (given_up(x, spin)) break;  // another wait of this call already gave up
+    __builtin_amdgcn_s_sleep(1);
+  }
+  Acc<ACC> v[PER_LANE];
+#pragma unroll
+  for (int j = 0; j < PER_LANE; ++j) {
+    if (lane + 64 * j < nseg && have[j]) v[j] = Tagged<ACC>::join(f[j]);
+    else v[j].zero();
+  }
+#pragma unroll
+  for (int st = 1; st < PER_LANE; st <<= 1)
+#pragma unroll
+    for (int j = 0; j + st < PER_LANE; j += 2 * st) v[j].merge(v[j + st]);
+  return wave_reduce<ACC>(v[0]);
+}
+
+// One resident segment of 2^LOG2 elements held by a BLOCK-thread block:
+// read into registers, block sum, exchange with the row's other segments,
+// divide from the registers, write. The row's result (RowMap) is left in
+// *s_bcast; lse, when given, receives the softmax row's log-sum-exp (from
+// segment 0).
+template <int DTI, int DTO, int ACC, int BLOCK, int LOG2, int PER_LANE>
+__device__ __forceinline__ void resident_unit(const RowDesc& d, int seg, const ResExchange& x, Acc<ACC>* slots,
+                                              RowRes* s_bcast, float* lse_row) {
   constexpr int VEC = Elem<DTI>::VEC;
-  constexpr int KB = (1 << RES_LOG2) / (RES_BLOCK * VEC);
-  constexpr int NA = 8;
+  constexpr int KB = (1 << LOG2) / (BLOCK * VEC);
+  static_assert(KB >= 1 && KB * BLOCK * VEC == (1 << LOG2), "a segment is whole vectors per thread");
+  // chains per thread: 8 binary32, 4 of the two-float kinds (registers)
+  constexpr int NA_MAX = ACC == NRM_ACC_F32 ? 8 : 4;
+  constexpr int NA = KB * VEC < NA_MAX ? KB * VEC : NA_MAX;
   const int t = threadIdx.x;
-  const int64_t S = int64_t(1) << RES_LOG2;
-  const int64_t b = (int64_t)seg << RES_LOG2;
+  const int64_t S = int64_t(1) << LOG2;
+  const int64_t b = (int64_t)seg << LOG2;
   const int64_t n = d.n - b < S ? d.n - b : S;
-  const int nseg = (int)((d.n + S - 1) >> RES_LOG2);
+  const int nseg = (int)((d.n + S - 1) >> LOG2);
   const char* in_seg = d.in + b * Elem<DTI>::SIZE;
   char* out_seg = d.out + b * Elem<DTO>::SIZE;
   const Geom g = geometry<DTI>(in_seg, n);
@@ -914,7 +983,7 @@ __device__ __forceinline__ void resident_unit(const BatchArgs& a, const RowDesc&
   u4 r[KB];
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    const int64_t v = t + (int64_t)k * RES_BLOCK;
+    const int64_t v = t + (int64_t)k * BLOCK;
     if (v < g.nvec) r[k] = load_vec<true>(body + v);
   }
   const float xh = has_head ? load_one<DTI>(in_seg, t) : 0.0f;
@@ -924,11 +993,11 @@ __device__ __forceinline__ void resident_unit(const BatchArgs& a, const RowDesc&
   for (int k = 0; k < NA; ++k) acc[k].zero();
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    if (t + (int64_t)k * RES_BLOCK < g.nvec) {
-      float x[VEC];
-      widen<DTI>(r[k], x);
+    if (t + (int64_t)k * BLOCK < g.nvec) {
+      float xv[VEC];
+      widen<DTI>(r[k], xv);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(x[c]);
+      for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(xv[c]);
     }
   }
   if (has_head) acc[0].add(xh);
@@ -940,19 +1009,34 @@ __device__ __forceinline__ void resident_unit(const BatchArgs& a, const RowDesc&
       const RowMap<ACC> f0 = RowMap<ACC>::of(tot);
       *s_bcast = f0.result();
       if constexpr (ACC == ACC_SOFTMAX) {
-        if (lse) lse[row] = f0.lse();
+        if (lse_row) *lse_row = f0.lse();
       }
     }
-  } else {
-    if (t == 0) publish_tagged<ACC>(a.tagged, item, tot, ep);
-    if (t < 64) {
-      const Acc<ACC> total = gather_row<ACC>(a, item - seg, nseg, ep);
+  } else if (t < 64) {
+    unsigned prev = 0;
+    if (t == 0) {
+      publish_tagged<ACC>(x.slots + 2 * seg, x.ep, tot);
+      prev = __hip_atomic_fetch_add(x.arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = (unsigned)__builtin_amdgcn_readfirstlane((int)prev);
+    Acc<ACC> total;
+    if (prev == (unsigned)nseg - 1) {
+      // the last to arrive: every segment has published; the count goes back
+      // to 0 for the next call, and the merged total is published once
+      if (t == 0) __hip_atomic_store(x.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      total = gather_row<ACC, PER_LANE>(x, nseg);
       if (t == 0) {
-        const RowMap<ACC> f0 = RowMap<ACC>::of(total);
-        *s_bcast = f0.result();
-        if constexpr (ACC == ACC_SOFTMAX) {
-          if (lse && seg == 0) lse[row] = f0.lse();
-        }
+        publish_tagged<ACC>(x.total, x.ep, total);
+        if (x.call) __hip_atomic_fetch_add(x.call, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else if (t == 0) {
+      total = wait_total<ACC>(x);
+    }
+    if (t == 0) {
+      const RowMap<ACC> f0 = RowMap<ACC>::of(total);
+      *s_bcast = f0.result();
+      if constexpr (ACC == ACC_SOFTMAX) {
+        if (lse_row && seg == 0) *lse_row = f0.lse();
       }
     }
   }
@@ -961,12 +1045,12 @@ __device__ __forceinline__ void resident_unit(const BatchArgs& a, const RowDesc&
   const bool vec_ok = out_vector_ok<DTI, DTO>(out_seg, g.head);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    const int64_t v = t + (int64_t)k * RES_BLOCK;
+    const int64_t v = t + (int64_t)k * BLOCK;
     if (v < g.nvec) {
-      float x[VEC], q[VEC];
-      widen<DTI>(r[k], x);
+      float xv[VEC], q[VEC];
+      widen<DTI>(r[k], xv);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
+      for (int c = 0; c < VEC; ++c) q[c] = f(xv[c]);
       store_quotients<DTI, DTO>(out_seg, g.head, v, vec_ok, q);
     }
   }
@@ -975,23 +1059,22 @@ __device__ __forceinline__ void resident_unit(const BatchArgs& a, const RowDesc&
 }
 
 template <int ACC>
-__device__ __forceinline__ void dispatch_resident(const BatchArgs& a, const RowDesc& d, int64_t row, int64_t item,
-                                                  int seg, uint32_t ep, Acc<ACC>* slots, RowRes* s_bcast,
-                                                  float* lse) {
+__device__ __forceinline__ void dispatch_resident(const RowDesc& d, int seg, const ResExchange& x, Acc<ACC>* slots,
+                                                  RowRes* s_bcast, float* lse_row) {
   if constexpr (ACC == ACC_SOFTMAX) {
-    resident_unit<NRM_F32, NRM_F32, ACC>(a, d, row, item, seg, ep, slots, s_bcast, lse);
+    resident_unit<NRM_F32, NRM_F32, ACC, RES_BLOCK, RES_LOG2, 1>(d, seg, x, slots, s_bcast, lse_row);
   } else {
-#define NRM_RU(I, O) resident_unit<I, O, ACC>(a, d, row, item, seg, ep, slots, s_bcast, lse)
+#define NRM_RU(I, O) return resident_unit<I, O, ACC, RES_BLOCK, RES_LOG2, 1>(d, seg, x, slots, s_bcast, lse_row)
     switch (d.in_dt * 3 + d.out_dt) {
-      case NRM_F32 * 3 + NRM_F32: NRM_RU(NRM_F32, NRM_F32); break;
-      case NRM_F32 * 3 + NRM_BF16: NRM_RU(NRM_F32, NRM_BF16); break;
-      case NRM_F32 * 3 + NRM_F16: NRM_RU(NRM_F32, NRM_F16); break;
-      case NRM_BF16 * 3 + NRM_F32: NRM_RU(NRM_BF16, NRM_F32); break;
-      case NRM_BF16 * 3 + NRM_BF16: NRM_RU(NRM_BF16, NRM_BF16); break;
-      case NRM_BF16 * 3 + NRM_F16: NRM_RU(NRM_BF16, NRM_F16); break;
-      case NRM_F16 * 3 + NRM_F32: NRM_RU(NRM_F16, NRM_F32); break;
-      case NRM_F16 * 3 + NRM_BF16: NRM_RU(NRM_F16, NRM_BF16); break;
-      default: NRM_RU(NRM_F16, NRM_F16); break;
+      case NRM_F32 * 3 + NRM_F32: NRM_RU(NRM_F32, NRM_F32);
+      case NRM_F32 * 3 + NRM_BF16: NRM_RU(NRM_F32, NRM_BF16);
+      case NRM_F32 * 3 + NRM_F16: NRM_RU(NRM_F32, NRM_F16);
+      case NRM_BF16 * 3 + NRM_F32: NRM_RU(NRM_BF16, NRM_F32);
+      case NRM_BF16 * 3 + NRM_BF16: NRM_RU(NRM_BF16, NRM_BF16);
+      case NRM_BF16 * 3 + NRM_F16: NRM_RU(NRM_BF16, NRM_F16);
+      case NRM_F16 * 3 + NRM_F32: NRM_RU(NRM_F16, NRM_F32);
+      case NRM_F16 * 3 + NRM_BF16: NRM_RU(NRM_F16, NRM_BF16);
+      default: NRM_RU(NRM_F16, NRM_F16);
     }
 #undef NRM_RU
   }
@@ -1009,17 +1092,26 @@ __global__ void __launch_bounds__(RES_BLOCK) __attribute__((amdgpu_waves_per_eu(
   const uint32_t ep = (uint32_t)a.cnt[CNT_EPOCH];
   float* lse = lse_out(a);
   unsigned long long* counter = reinterpret_cast<unsigned long long*>(a.cnt + CNT_DISPENSE);
-  while (true) {
-    if (threadIdx.x == 0)
-      s_claim = (int64_t)__hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    lds_barrier();
-    const int64_t u = s_claim;
-    if (u >= units) break;
+  if (threadIdx.x == 0)
+    s_claim = (int64_t)__hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  lds_barrier();
+  int64_t u = s_claim;
+  while (u < units) {
     const int64_t item = begin + u;
     const Item it = a.items[item];
     const RowDesc d = a.rows[it.row];
-    dispatch_resident<ACC>(a, d, it.row, item, it.tile, ep, slots, &s_bcast, lse);
+    // the row's items are consecutive: its first segment is item - tile
+    const int64_t first = item - it.tile;
+    const ResExchange x{a.tagged + 2 * first, a.rowtot + 2 * first, a.arrivals + first, ep, a.error,
+                        reinterpret_cast<unsigned long long*>(a.cnt + CNT_STALL), nullptr};
+    dispatch_resident<ACC>(d, it.tile, x, slots, &s_bcast, lse ? lse + it.row : nullptr);
+    // the next item once this one is done (claiming it as soon as the row's
+    // sum was known, to overlap the claim with the writes, measured slower)
     lds_barrier();  // slots, s_bcast and s_claim are reused
+    if (threadIdx.x == 0)
+      s_claim = (int64_t)__hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    lds_barrier();
+    u = s_claim;
   }
 }
 
@@ -1240,9 +1332,69 @@ hipError_t small_acc(const RowDesc& d, float* sum_out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- the plain path's single-launch form for mid-size n ---------------------------------
+// n in (small_n, 2^20]: one block of PRES_BLOCK threads per segment of
+// 2^PRES_LOG2 elements (at most PRES_MAX_SEGMENTS blocks), each held in
+// registers from its read to its write while the blocks exchange their
+// segment sums as the resident rows of a batch do: two transfers and one
+// launch instead of three transfers and two launches. The grid is the
+// row's segments, so every block of the launch must be able to run at once
+// (256 blocks of 256 threads: one per CU on MI355X). The call number that
+// tags the partials lives in the workspace; the last block to arrive moves
+// it on (every block read it before arriving), so consecutive calls on one
+// workspace never read each other's partials.
+constexpr int PRES_BLOCK = 256;
+constexpr int PRES_LOG2 = 12;
+constexpr int PRES_MAX_SEGMENTS = 256;
+
+template <int DTI, int DTO, int ACC>
+__global__ void __launch_bounds__(PRES_BLOCK) plain_resident_kernel(RowDesc d, PlainResidentWs w) {
+  __shared__ Acc<ACC> slots[MAX_WAVES];
+  __shared__ RowRes s_bcast;
+  // the tag is never 0, the value of a slot that was never written; the last
+  // block to arrive moves the call number on once every block has read it
+  const unsigned long long call = __hip_atomic_load(w.call, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const ResExchange x{w.slots, w.total, w.arrivals, (uint32_t)(call % 0xFFFFFFFFull) + 1u, w.error, w.stall, w.call};
+  resident_unit<DTI, DTO, ACC, PRES_BLOCK, PRES_LOG2, PRES_MAX_SEGMENTS / 64>(d, blockIdx.x, x, slots, &s_bcast,
+                                                                            nullptr);
+  if (threadIdx.x == 0 && blockIdx.x == 0) w.sum_out[0] = s_bcast.a;  // the invariant, for nrm_get_last_sum
+}
+
+template <int ACC>
+hipError_t plain_resident_acc(const RowDesc& d, const PlainResidentWs& w, hipStream_t s) {
+  const unsigned grid = (unsigned)((d.n + (int64_t(1) << PRES_LOG2) - 1) >> PRES_LOG2);
+#define NRM_PR(I, O) \
+  hipLaunchKernelGGL((plain_resident_kernel<I, O, ACC>), dim3(grid), dim3(PRES_BLOCK), 0, s, d, w)
+  switch (d.in_dt * 3 + d.out_dt) {
+    case NRM_F32 * 3 + NRM_F32: NRM_PR(NRM_F32, NRM_F32); break;
+    case NRM_F32 * 3 + NRM_BF16: NRM_PR(NRM_F32, NRM_BF16); break;
+    case NRM_F32 * 3 + NRM_F16: NRM_PR(NRM_F32, NRM_F16); break;
+    case NRM_BF16 * 3 + NRM_F32: NRM_PR(NRM_BF16, NRM_F32); break;
+    case NRM_BF16 * 3 + NRM_BF16: NRM_PR(NRM_BF16, NRM_BF16); break;
+    case NRM_BF16 * 3 + NRM_F16: NRM_PR(NRM_BF16, NRM_F16); break;
+    case NRM_F16 * 3 + NRM_F32: NRM_PR(NRM_F16, NRM_F32); break;
+    case NRM_F16 * 3 + NRM_BF16: NRM_PR(NRM_F16, NRM_BF16); break;
+    default: NRM_PR(NRM_F16, NRM_F16); break;
+  }
+#undef NRM_PR
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int64_t small_capacity(int) { return SMALL_ELEMS; }
+int64_t plain_resident_capacity() { return (int64_t)PRES_MAX_SEGMENTS << PRES_LOG2; }
+
+hipError_t launch_plain_resident(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc,
+                                 const PlainResidentWs& w, hipStream_t s) {
+  RowDesc d;
+  d.in = static_cast<const char*>(in);
+  d.out = static_cast<char*>(out);
+  d.n = n;
+  d.in_dt = in_dt;
+  d.out_dt = out_dt;
+  return acc == NRM_ACC_KAHAN ? plain_resident_acc<NRM_ACC_KAHAN>(d, w, s) : plain_resident_acc<NRM_ACC_F32>(d, w, s);
+}
 
 hipError_t launch_small(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc, float* sum_out,
                         hipStream_t s) {

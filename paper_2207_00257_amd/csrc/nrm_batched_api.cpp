@@ -1,8 +1,10 @@
 // C ABI of the ragged batched path (include/nrm.h): workspace and pinned
-// staging management, host validation, the launch sequence (planner, phase 1,
-// phase 2) and its optional capture in a hipGraph. The per-call header and
-// row table are written to pinned, coherent host memory that the planner
-// reads in place, so a captured graph replays new batches unchanged.
+// staging management, host validation, the launch sequence (planner, the
+// resident rows, phase 1, row sums, phase 2) and its optional capture in a
+// hipGraph. The per-call header and row table are written to pinned,
+// coherent host memory that the planner reads in place, so a captured graph
+// replays new batches unchanged; a ring of such buffers (one graph each) lets
+// a call be enqueued while the previous ones still run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,18 +93,24 @@ int64_t short_max_of(const nrm_batch_params& p) {
   return p.resident_segments > 0 ? (int64_t)p.resident_segments << nrm::RES_LOG2 : (int64_t)p.block * p.short_regs * 4;
 }
 
-bool any_graph(const BatchWorkspace& w) { return w.graph[0] || w.graph[1] || w.graph[2]; }
+bool any_graph(const BatchWorkspace& w) {
+  for (const auto& per_kind : w.graph)
+    for (hipGraphExec_t g : per_kind)
+      if (g) return true;
+  return false;
+}
 
 void destroy_graph(BatchWorkspace& w) {
-  for (hipGraphExec_t& g : w.graph) {
-    if (g) (void)hipGraphExecDestroy(g);
-    g = nullptr;
-  }
+  for (auto& per_kind : w.graph)
+    for (hipGraphExec_t& g : per_kind) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
 // Layout of the single device allocation.
 struct Layout {
-  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, small, partials, tagged, total;
+  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, small, partials, tagged, rowtot, arrivals, total;
 };
 
 // Phase-2 chunks a workspace holds beyond one per item: the planner sizes the
@@ -127,6 +135,8 @@ Layout layout_for(int64_t cap_rows, int64_t cap_items, int64_t cap_chunks) {
   L.small = take(kSmallBytes);  // the planner's counters, then the error word
   L.partials = take(8 * cap_items);
   L.tagged = take(16 * cap_items);
+  L.rowtot = take(16 * cap_items);
+  L.arrivals = take(4 * cap_items);
   L.total = off;
   return L;
 }
@@ -148,8 +158,8 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   // Per-call header and row table: pinned, coherent host memory that the
   // planner reads directly (no copy, no DMA latency per call).
   void* host = nullptr;
-  const size_t staging = kTableOffset + sizeof(RowDesc) * (size_t)cap_rows;
-  e = hipHostMalloc(&host, staging, hipHostMallocCoherent | hipHostMallocMapped);
+  const size_t staging = (size_t)align_up((int64_t)(kTableOffset + sizeof(RowDesc) * (size_t)cap_rows), 256);
+  e = hipHostMalloc(&host, staging * nrm::kStagingRing, hipHostMallocCoherent | hipHostMallocMapped);
   if (e != hipSuccess) {
     (void)hipFree(dev);  // already failing
     return fail(NRM_ENOMEM, std::string("pinned staging hipHostMalloc: ") + hipGetErrorString(e));
@@ -176,8 +186,13 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   char* d = static_cast<char*>(dev);
   w.dev = dev;
   w.host = host;
-  w.hdr = reinterpret_cast<BatchHeader*>(host_dev);
-  w.table = reinterpret_cast<RowDesc*>(static_cast<char*>(host_dev) + kTableOffset);
+  w.staging = staging;
+  w.next = 0;
+  for (int b = 0; b < nrm::kStagingRing; ++b) {
+    char* base = static_cast<char*>(host_dev) + staging * b;
+    w.hdr[b] = reinterpret_cast<BatchHeader*>(base);
+    w.table[b] = reinterpret_cast<RowDesc*>(base + kTableOffset);
+  }
   w.rows = reinterpret_cast<RowDesc*>(d + L.rows);
   w.items = reinterpret_cast<nrm::Item*>(d + L.items);
   w.lrow_first = reinterpret_cast<int64_t*>(d + L.lrow_first);
@@ -189,19 +204,23 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   w.error = reinterpret_cast<int*>(d + L.small + kErrorOffset);
   w.partials = d + L.partials;
   w.tagged = reinterpret_cast<unsigned long long*>(d + L.tagged);
+  w.rowtot = reinterpret_cast<unsigned long long*>(d + L.rowtot);
+  w.arrivals = reinterpret_cast<unsigned*>(d + L.arrivals);
   w.cap_rows = cap_rows;
   w.cap_items = cap_items;
   w.cap_chunks = cap_chunks;
-  w.staged_pending = false;
+  for (bool& p : w.staged_pending) p = false;
   // the counters (the call number starts at 0) and the resident rows' tags
   e = hipMemset(d + L.small, 0, kSmallBytes);
-  if (e == hipSuccess) e = hipMemset(d + L.tagged, 0, 16 * (size_t)cap_items);
+  // tags, totals and arrival counts: contiguous, all start at 0
+  if (e == hipSuccess) e = hipMemset(d + L.tagged, 0, L.total - L.tagged);
   if (e == hipSuccess && err_word) e = hipMemcpy(w.error, &err_word, sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemset");
-  if (!w.staged) {
-    e = hipEventCreateWithFlags(&w.staged, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-  }
+  for (hipEvent_t& ev : w.staged)
+    if (!ev) {
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
   return NRM_OK;
 }
 
@@ -212,10 +231,10 @@ int64_t items_bound(const nrm_batch_params& p, int64_t rows, int64_t elems) {
   return rows + ceil_div(std::max<int64_t>(elems, 0), int64_t(1) << lg);
 }
 
-BatchArgs args_of(const nrm_ctx* c) {
+BatchArgs args_of(const nrm_ctx* c, int buf) {
   const BatchWorkspace& w = c->batch;
   BatchArgs a;
-  a.hdr = w.hdr;
+  a.hdr = w.hdr[buf];
   a.rows = w.rows;
   a.items = w.items;
   a.lrow_first = w.lrow_first;
@@ -238,6 +257,8 @@ BatchArgs args_of(const nrm_ctx* c) {
   a.keep_tiles = ((int64_t)c->bparams.keep_mib << 20) / (a.tile * 4);
   a.res_on = c->bparams.resident_segments > 0;
   a.tagged = w.tagged;
+  a.rowtot = w.rowtot;
+  a.arrivals = w.arrivals;
   return a;
 }
 
@@ -255,10 +276,11 @@ BatchPlan plan_of(const nrm_ctx* c, int acc) {
   return p;
 }
 
-int capture_graph(nrm_ctx* c, int acc) {
+int capture_graph(nrm_ctx* c, int acc, int buf) {
   BatchWorkspace& w = c->batch;
-  if (w.graph[acc]) (void)hipGraphExecDestroy(w.graph[acc]);
-  w.graph[acc] = nullptr;
+  hipGraphExec_t& g = w.graph[acc][buf];
+  if (g) (void)hipGraphExecDestroy(g);
+  g = nullptr;
   hipError_t e;
   if (!w.capture_stream) {
     e = hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking);
@@ -266,34 +288,37 @@ int capture_graph(nrm_ctx* c, int acc) {
   }
   e = hipStreamBeginCapture(w.capture_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t e2 = nrm::launch_batch(plan_of(c, acc), args_of(c), w.capture_stream);
+  hipError_t e2 = nrm::launch_batch(plan_of(c, acc), args_of(c, buf), w.capture_stream);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(w.capture_stream, &graph);
   if (e2 != hipSuccess) return hip_fail(e2, "batched launch (capture)");
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&w.graph[acc], graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    w.graph[acc] = nullptr;
+    g = nullptr;
     return hip_fail(e, "hipGraphInstantiate");
   }
   return NRM_OK;
 }
 
-// Stage the header (and table), then run the three kernels on `s`.
+// Stage the header (and table) in the next ring buffer, then run the launch
+// sequence on `s`.
 int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nrows, int acc,
               hipStream_t s) {
   BatchWorkspace& w = c->batch;
   hipError_t e;
-  if (w.staged_pending) {  // the previous call's copy must have read the staging buffer
-    e = hipEventSynchronize(w.staged);
+  const int buf = w.next;
+  if (w.staged_pending[buf]) {  // the call that used this buffer before must be done with it
+    e = hipEventSynchronize(w.staged[buf]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    w.staged_pending = false;
+    w.staged_pending[buf] = false;
   }
   BatchHeader hd = h;
-  hd.table = w.table;
-  std::memcpy(w.host, &hd, sizeof(hd));
-  if (table) std::memcpy(static_cast<char*>(w.host) + kTableOffset, table, sizeof(RowDesc) * (size_t)nrows);
+  hd.table = w.table[buf];
+  char* host = static_cast<char*>(w.host) + w.staging * buf;
+  std::memcpy(host, &hd, sizeof(hd));
+  if (table) std::memcpy(host + kTableOffset, table, sizeof(RowDesc) * (size_t)nrows);
   hipEvent_t* ev = nullptr;
   if (c->timing) {
     ev = &w.events[2 * (w.timed_calls % nrm::kTimingRing)];
@@ -301,20 +326,21 @@ int run_batch(nrm_ctx* c, const BatchHeader& h, const nrm_row* table, int64_t nr
     (void)hipEventRecord(ev[0], s);  // timing only
   }
   if (c->bparams.graph) {
-    if (!w.graph[acc]) {
-      int st = capture_graph(c, acc);
+    if (!w.graph[acc][buf]) {
+      int st = capture_graph(c, acc, buf);
       if (st != NRM_OK) return st;
     }
-    e = hipGraphLaunch(w.graph[acc], s);
+    e = hipGraphLaunch(w.graph[acc][buf], s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   } else {
-    e = nrm::launch_batch(plan_of(c, acc), args_of(c), s);
+    e = nrm::launch_batch(plan_of(c, acc), args_of(c, buf), s);
     if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  e = hipEventRecord(w.staged, s);
+  e = hipEventRecord(w.staged[buf], s);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-  w.staged_pending = true;
+  w.staged_pending[buf] = true;
+  w.next = (buf + 1) % nrm::kStagingRing;
   return NRM_OK;
 }
 
@@ -327,7 +353,8 @@ void batch_free(nrm_ctx* c) {
   BatchWorkspace& w = c->batch;
   destroy_graph(w);
   if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
-  if (w.staged) (void)hipEventDestroy(w.staged);
+  for (hipEvent_t ev : w.staged)
+    if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : w.events) (void)hipEventDestroy(ev);
   if (w.dev) (void)hipFree(w.dev);
   if (w.host) (void)hipHostFree(w.host);
@@ -534,6 +561,12 @@ int nrm_get_device_error(nrm_ctx* c, void* stream) {
     word |= w;
   }
   if (!word) return NRM_OK;
+  if (word & nrm::NRM_DEVERR_STALL) {
+    // a wait that gave up may have left arrival counts behind: start them over
+    if (c->batch.dev) e = hipMemset(c->batch.arrivals, 0, sizeof(unsigned) * (size_t)c->batch.cap_items);
+    if (e == hipSuccess) e = hipMemset(c->res.arrivals, 0, sizeof(unsigned));
+    if (e != hipSuccess) return hip_fail(e, "clearing the arrival counts");
+  }
   std::string why;
   if (word & nrm::NRM_DEVERR_OFFSETS) why += "CSR offsets negative, decreasing or past capacity; ";
   if (word & nrm::NRM_DEVERR_ROW) why += "invalid table row or row with too many tiles; ";

@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "nrm_batch.h"
@@ -24,6 +26,9 @@ inline int hip_fail(hipError_t e, const char* where) {
 }
 
 constexpr int kTimingRing = 1024;
+// Pinned staging buffers of the batched path, used in turn: a call waits only
+// for the call this many before it to have finished with its buffer.
+constexpr int kStagingRing = 4;
 
 // Makes `dev` current for the guard's lifetime. The device was validated
 // when the context was created; should switching still fail, the next HIP
@@ -49,8 +54,8 @@ struct BatchWorkspace {
   int64_t cap_items = 0;
   int64_t cap_chunks = 0;
   void* dev = nullptr;         // one allocation, carved into the pointers below
-  BatchHeader* hdr = nullptr;  // device view of the pinned staging header
-  RowDesc* table = nullptr;    // device view of the pinned staging row table
+  BatchHeader* hdr[kStagingRing] = {};  // device views of the staging buffers' headers
+  RowDesc* table[kStagingRing] = {};    // device views of their row tables
   RowDesc* rows = nullptr;
   Item* items = nullptr;
   int64_t* lrow_first = nullptr;
@@ -62,11 +67,17 @@ struct BatchWorkspace {
   int* error = nullptr;
   void* partials = nullptr;
   unsigned long long* tagged = nullptr;  // resident rows' tagged partials
-  void* host = nullptr;        // pinned staging (host view): header, then the table
-  hipEvent_t staged = nullptr; // recorded once the staging buffer may be rewritten
-  bool staged_pending = false;
-  // captured launch sequence
-  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};  // one per reduction kind (plain, compensated, softmax)
+  unsigned long long* rowtot = nullptr;  // resident rows' tagged totals
+  unsigned* arrivals = nullptr;          // resident rows' arrival counts
+  void* host = nullptr;        // pinned staging (host view): kStagingRing buffers of `staging` bytes,
+                               // each a header, then a row table
+  size_t staging = 0;
+  int next = 0;                // the buffer the next call uses
+  hipEvent_t staged[kStagingRing] = {};  // recorded after the call that used the buffer
+  bool staged_pending[kStagingRing] = {};
+  // captured launch sequences: per reduction kind (plain, compensated,
+  // softmax) and staging buffer (the planner reads its buffer's header)
+  hipGraphExec_t graph[3][kStagingRing] = {};
   hipStream_t capture_stream = nullptr;
   // timing ring of (before, after) event pairs
   std::vector<hipEvent_t> events;
@@ -80,12 +91,17 @@ struct nrm_ctx {
   nrm::BatchWorkspace batch;
   int device = 0;
   nrm_params params{};
+  // tuned parameters (nrm_tune.cpp): used per call while params_set is false
+  bool params_set = false;
+  std::string arch;
+  std::map<int64_t, std::pair<bool, nrm_params>> tuned;  // call key -> (has an entry, parameters)
   // plain-path workspace
   void* partials = nullptr;
   int64_t partials_cap = 0;  // entries (each up to 8 bytes)
   unsigned* ticket = nullptr;
   int* dev_error = nullptr;  // device error word of the non-batched kernels (NLL targets)
   float* sum = nullptr;      // 2 floats
+  nrm::PlainResidentWs res{};  // the single-launch mid-size form's exchange
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // 3 per recorded call
@@ -105,4 +121,8 @@ int plan_plain(const nrm_params& q, void* out, int out_dt, const void* in, int i
                PlainPlan* p);
 // Release the batched workspace of a context (waits for the device).
 void batch_free(nrm_ctx* c);
+// The device's architecture name (gfx950), or "" (nrm_tune.cpp).
+std::string device_arch(int device);
+// Overlay the tuning cache's entry for this call's key on *p; false if none.
+bool tuned_plain(const std::string& arch, int in_dt, int out_dt, int acc, int64_t n, nrm_params* p);
 }  // namespace nrm

@@ -1,16 +1,18 @@
-// The two un-hoisted forms of normalize (arXiv 2207.00257, Fig. 1), kept on
-// the GPU only to measure what hoisting the invariant sum buys:
+// The two un-hoisted forms of normalize (arXiv 2207.00257, Fig. 1 and its
+// caption), kept on the GPU only to measure what hoisting the invariant sum
+// buys. Both divide every element by the sum of all elements; they differ in
+// how often that sum is computed:
 //
-//   naive_kernel     every thread computes the whole sum itself, then divides
-//                    its element: O(n^2) work (Fig. 1 as printed).
-//   perblock_kernel  thread 0 of every block computes the sum into block-
-//                    shared memory, the block meets at a barrier, then every
-//                    thread divides: O(n^2 / B) work (the shared-memory variant
-//                    in Fig. 1's comments; Fig. 3).
+//   naive     once per thread: each thread reads the whole input itself and
+//             divides its own element, O(n^2) work in total;
+//   perblock  once per block: the block's first wavefront reads the whole
+//             input (64 lanes, 16-byte vectors), merges its lanes, and leaves
+//             the sum in LDS; after one block barrier every thread divides its
+//             element, O(n^2 / B) work in total.
 //
-// Each per-thread sum is a Kahan-compensated binary32 chain over the input in
-// index order, so the results stay within the library's error bound even for
-// these long chains. These are not performance paths.
+// The sums are Kahan-compensated binary32 (one chain per thread, or per lane
+// merged by TwoSum), so the results stay within the library's error bound
+// even for these long chains. These are not performance paths.
 #include "nrm_device.h"
 
 namespace nrm {
@@ -18,25 +20,45 @@ namespace {
 
 using namespace dev;
 
-__device__ __forceinline__ float sum_whole(const float* in, int64_t n) {
+// Sum of in[0..n) into a compensated chain: lane `lane` of `lanes` takes the
+// 16-byte vectors lane, lane + lanes, ... of the input's aligned body; lane 0
+// also takes the unaligned head and the tail.
+__device__ __forceinline__ Acc<NRM_ACC_KAHAN> sum_strided(const float* in, int64_t n, int lane, int lanes) {
   Acc<NRM_ACC_KAHAN> a;
   a.zero();
-  for (int64_t j = 0; j < n; ++j) a.add(in[j]);
-  return a.value();
+  const int64_t mis = (int64_t)((reinterpret_cast<uintptr_t>(in) & 15) / 4);
+  const int64_t head = mis ? (4 - mis < n ? 4 - mis : n) : 0;
+  const int64_t nvec = (n - head) / 4;
+  const u4* body = reinterpret_cast<const u4*>(in + head);
+  for (int64_t v = lane; v < nvec; v += lanes) {
+    const u4 r = body[v];
+    a.add(f32_bits(r[0]));
+    a.add(f32_bits(r[1]));
+    a.add(f32_bits(r[2]));
+    a.add(f32_bits(r[3]));
+  }
+  if (lane == 0) {
+    for (int64_t i = 0; i < head; ++i) a.add(in[i]);
+    for (int64_t i = head + 4 * nvec; i < n; ++i) a.add(in[i]);
+  }
+  return a;
 }
 
 __global__ void __launch_bounds__(1024) naive_kernel(float* out, const float* in, int64_t n) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const float val = sum_whole(in, n);  // recomputed by every thread
-  if (tid < n) out[tid] = in[tid] / val;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float sum = sum_strided(in, n, 0, 1).value();  // this thread's own pass over the input
+  if (i < n) out[i] = in[i] / sum;
 }
 
 __global__ void __launch_bounds__(1024) perblock_kernel(float* out, const float* in, int64_t n) {
-  __shared__ float val;
-  if (threadIdx.x == 0) val = sum_whole(in, n);  // once per block
+  __shared__ float block_sum;
+  if (threadIdx.x < 64) {
+    const Acc<NRM_ACC_KAHAN> total = wave_reduce<NRM_ACC_KAHAN>(sum_strided(in, n, threadIdx.x, 64));
+    if (threadIdx.x == 0) block_sum = total.value();
+  }
   __syncthreads();
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid < n) out[tid] = in[tid] / val;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] / block_sum;
 }
 
 }  // namespace

@@ -110,6 +110,25 @@ int64_t small_capacity(int in_dt);
 hipError_t launch_small(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc, float* sum_out,
                         hipStream_t s);
 
+// The plain path's single-launch form for mid-size n (nrm_batched.hip): one
+// block per segment of the input held in registers across an exchange of the
+// segment sums; n <= plain_resident_capacity(). Workspace, zero-initialized:
+// the segments' tagged partials (16 bytes each), the merged total, the
+// arrival count, the call number, the stall marker and error word, and the
+// sum for nrm_get_last_sum.
+struct PlainResidentWs {
+  unsigned long long* slots;  // 2 x 256 words
+  unsigned long long* total;  // 2 words
+  unsigned* arrivals;         // 0 between calls
+  unsigned long long* call;
+  unsigned long long* stall;
+  int* error;
+  float* sum_out;
+};
+int64_t plain_resident_capacity();
+hipError_t launch_plain_resident(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc,
+                                 const PlainResidentWs& w, hipStream_t s);
+
 // The Fig. 9-shaped tile kernel in one of its three forms (nrm_layerforward.hip).
 hipError_t launch_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows,
                                hipStream_t s);

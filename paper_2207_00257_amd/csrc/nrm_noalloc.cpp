@@ -33,7 +33,12 @@ namespace {
 constexpr int64_t kScratchPartials = 16384;
 constexpr size_t kSumOffset = kScratchPartials * 8;  // two floats: the sum (compensated: hi, lo)
 constexpr size_t kTicketOffset = kSumOffset + 128;   // the last-block combine's ticket, 0 between calls
-constexpr size_t kScratchBytes = kTicketOffset + 128;
+// the mid-size single-launch form: call number (0), arrival count (8, 0
+// between calls), stall marker (16), error word (24), merged total (32), then
+// its segments' tagged partials
+constexpr size_t kResOffset = kTicketOffset + 128;
+constexpr size_t kResSlotsOffset = kResOffset + 256;
+constexpr size_t kScratchBytes = kResSlotsOffset + 256 * 16;
 static_assert(kScratchBytes == NRM_NOALLOC_SCRATCH_BYTES, "scratch size must match the header");
 
 // Zero-initialized when the code object is loaded on a device; the ticket is
@@ -96,6 +101,16 @@ extern "C" int nrm_normalize_noalloc(void* out, int out_dtype, const void* in, i
   if (n <= d->params.small_n && n <= nrm::small_capacity(in_dtype)) {
     e = nrm::launch_small(in, in_dtype, out, out_dtype, n, accum, sum, s);
     if (e != hipSuccess) return hip_fail(e, "small normalize kernel launch");
+    return NRM_OK;
+  }
+  if (n <= d->params.resident_n && n <= nrm::plain_resident_capacity()) {
+    char* r = d->ptr + kResOffset;
+    const nrm::PlainResidentWs w{reinterpret_cast<unsigned long long*>(d->ptr + kResSlotsOffset),
+                                 reinterpret_cast<unsigned long long*>(r + 32), reinterpret_cast<unsigned*>(r + 8),
+                                 reinterpret_cast<unsigned long long*>(r), reinterpret_cast<unsigned long long*>(r + 16),
+                                 reinterpret_cast<int*>(r + 24), sum};
+    e = nrm::launch_plain_resident(in, in_dtype, out, out_dtype, n, accum, w, s);
+    if (e != hipSuccess) return hip_fail(e, "mid-size normalize kernel launch");
     return NRM_OK;
   }
   nrm::PlainPlan plan;

@@ -1,17 +1,19 @@
 // Continuous-batching server for normalize requests (C ABI in include/nrm.h).
 //
 // A request is one normalize of n elements whose input already lives in
-// device memory. The scheduler thread
+// device memory. The scheduling core (nrm_sched.h: queue, HBM-budget
+// admission, output arena, slots, completions) is driven here by one
+// scheduler thread, which in each pass
 //   1. polls the slots: a slot whose batch has finished (its event) releases
 //      its requests' output blocks and budget and reports them complete;
 //   2. admits waiting requests in arrival order while the HBM budget (input +
 //      output bytes of every admitted request) and a free slot allow;
 //   3. launches the admitted requests as one ragged batch (row-table form)
 //      on the free slot's stream (a group of one request may take the plain
-//      two-kernel path instead), or, in per-request mode, one plain normalize
-//      call per request. With spreading, waiting requests are shared out over
-//      the free slots, so they run alone and concurrently while slots are
-//      free and are grouped only when the queue outgrows the slots.
+//      path instead), or, in per-request mode, one plain normalize call per
+//      request. With spreading, waiting requests are shared out over the
+//      free slots, so they run alone and concurrently while slots are free
+//      and are grouped only when the queue outgrows the slots.
 // Requests that arrive while batches are in flight join the next batch as
 // soon as a slot and memory free up; several slots run concurrently.
 // A replay thread can submit a whole trace at its scheduled arrival times
@@ -30,6 +32,7 @@
 #include <vector>
 
 #include "nrm_ctx.h"
+#include "nrm_sched.h"
 
 using nrm::DeviceGuard;
 using nrm::fail;
@@ -43,98 +46,55 @@ int64_t now_ns() {
       .count();
 }
 
-// First-fit allocator over [0, size) with coalescing of free neighbours.
-class Arena {
+// The GPU side of the scheduler: per slot a context, a stream and an event.
+class HipExecutor : public nrm::Executor {
  public:
-  explicit Arena(int64_t size) { free_[0] = size; }
-  // Offset of a block of `bytes` (rounded up to 256), or -1.
-  int64_t alloc(int64_t bytes) {
-    bytes = (bytes + 255) / 256 * 256;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        int64_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > bytes) free_[off + bytes] = len - bytes;
-        used_[off] = bytes;
-        return off;
-      }
-    }
-    return -1;
-  }
-  void release(int64_t off) {
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    int64_t len = u->second;
-    used_.erase(u);
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && next->first == off + len) {
-      len += next->second;
-      free_.erase(next);
-    }
-    auto prev = free_.lower_bound(off);
-    if (prev != free_.begin()) {
-      --prev;
-      if (prev->first + prev->second == off) {
-        prev->second += len;
-        return;
-      }
-    }
-    free_[off] = len;
-  }
-
- private:
-  std::map<int64_t, int64_t> free_;  // offset -> length
-  std::map<int64_t, int64_t> used_;
-};
-
-struct Pending {
-  nrm_request req;
-  int64_t t_submit = 0;  // when the server saw it
-  int64_t t_arrival = 0; // scheduled arrival (the latency origin)
-  int64_t out_off = -1;
-  int64_t budget = 0;
-  int64_t t_launch = 0;
-};
-
-struct Slot {
-  nrm_ctx* ctx = nullptr;
-  hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
-  bool busy = false;
-  std::vector<Pending> reqs;
-};
-
-}  // namespace
-
-struct nrm_server {
-  nrm_server_config cfg{};
-  std::map<int64_t, Pending> held;    // completed, output not yet released (hold_outputs)
-  int device = 0;
+  struct SlotRes {
+    nrm_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+  };
+  std::vector<SlotRes> slots;
   char* arena_base = nullptr;
-  Arena* arena = nullptr;
-  int64_t budget_used = 0;
-  std::vector<Slot> slots;
-  std::mutex mu;                      // guards queue, done, counters
-  std::condition_variable cv;
-  std::deque<Pending> queue;
-  std::vector<nrm_completion> done;
-  std::atomic<bool> stop{false};
-  std::thread scheduler;
-  std::thread replayer;
-  std::atomic<int> replay_running{0};
-  int64_t in_flight = 0;
-  int64_t batches = 0;
-  int64_t launches = 0;
-  int64_t rejected = 0;
-  int error = NRM_OK;
-  std::string error_msg;
-  int64_t t0 = 0;                     // origin of the replay schedule
+  int accum = NRM_ACC_F32;
+  std::string msg;
 
-  void run();
-  void launch(Slot& s, std::vector<Pending>& batch);
+  int launch(int k, const nrm_row* rows_in, int64_t count, bool batched) override {
+    SlotRes& s = slots[(size_t)k];
+    std::vector<nrm_row> rows(rows_in, rows_in + count);
+    for (nrm_row& r : rows) r.out = arena_base + reinterpret_cast<int64_t>(r.out);
+    int st = NRM_OK;
+    if (batched) {
+      st = nrm_normalize_rows(s.ctx, rows.data(), count, accum, s.stream);
+    } else {
+      for (const nrm_row& r : rows) {
+        st = nrm_normalize_ex(s.ctx, r.out, r.out_dtype, r.in, r.in_dtype, r.n, accum, s.stream);
+        if (st != NRM_OK) break;
+      }
+    }
+    if (st == NRM_OK) {
+      hipError_t e = hipEventRecord(s.done, s.stream);
+      if (e != hipSuccess) st = hip_fail(e, "hipEventRecord");
+    }
+    if (st != NRM_OK) {
+      // rows already enqueued before a failing call may still run: let them
+      // finish before their memory is handed out again
+      msg = nrm_last_error();
+      (void)hipStreamSynchronize(s.stream);
+    }
+    return st;
+  }
+
+  int query(int k) override {
+    hipError_t e = hipEventQuery(slots[(size_t)k].done);
+    if (e == hipErrorNotReady) return 0;
+    if (e == hipSuccess) return 1;
+    msg = std::string("hipEventQuery: ") + hipGetErrorString(e);
+    return NRM_EHIP;
+  }
+
+  std::string message() override { return msg; }
 };
-
-namespace {
 
 bool valid_dtype(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
 
@@ -147,135 +107,36 @@ int check_request(const nrm_request& r) {
 
 }  // namespace
 
-void nrm_server::launch(Slot& s, std::vector<Pending>& batch) {
-  const int64_t t = now_ns();
-  std::vector<nrm_row> rows(batch.size());
-  for (size_t i = 0; i < batch.size(); ++i) {
-    Pending& p = batch[i];
-    p.t_launch = t;
-    rows[i].in = p.req.in;
-    rows[i].out = arena_base + p.out_off;
-    rows[i].n = p.req.n;
-    rows[i].in_dtype = p.req.in_dtype;
-    rows[i].out_dtype = p.req.out_dtype;
-  }
-  int st = NRM_OK;
-  const bool small_group = (int64_t)rows.size() < cfg.min_batch_rows || (cfg.single_plain && rows.size() == 1);
-  if (cfg.batching && !small_group) {
-    st = nrm_normalize_rows(s.ctx, rows.data(), (int64_t)rows.size(), cfg.accum, s.stream);
-    launches += 1;
-  } else {
-    for (const nrm_row& r : rows) {
-      st = nrm_normalize_ex(s.ctx, r.out, r.out_dtype, r.in, r.in_dtype, r.n, cfg.accum, s.stream);
-      if (st != NRM_OK) break;
-      launches += 1;
-    }
-  }
-  if (st == NRM_OK) {
-    hipError_t e = hipEventRecord(s.done, s.stream);
-    if (e != hipSuccess) st = hip_fail(e, "hipEventRecord");
-  }
-  if (st != NRM_OK) {
-    std::lock_guard<std::mutex> lk(mu);
-    error = st;
-    error_msg = nrm_last_error();
-  }
-  s.reqs.swap(batch);
-  s.busy = true;
-  batches += 1;
-}
+struct nrm_server {
+  nrm_server_config cfg{};
+  int device = 0;
+  HipExecutor ex;
+  nrm::Scheduler* core = nullptr;
+  std::mutex wake_mu;                 // with cv: wakes the scheduler thread
+  std::condition_variable cv;
+  std::atomic<bool> stop{false};
+  std::thread scheduler;
+  std::thread replayer;
+  std::atomic<int> replay_running{0};
+
+  void run();
+};
 
 void nrm_server::run() {
   DeviceGuard g(device);
-  std::vector<Pending> batch;
   int64_t last_activity = now_ns();
   while (true) {
-    bool progressed = false;
-    // 1. completions
-    for (Slot& s : slots) {
-      if (!s.busy) continue;
-      hipError_t e = hipEventQuery(s.done);
-      if (e == hipErrorNotReady) continue;
-      const int64_t t = now_ns();
-      std::lock_guard<std::mutex> lk(mu);
-      if (e != hipSuccess && error == NRM_OK) {
-        error = NRM_EHIP;
-        error_msg = std::string("hipEventQuery: ") + hipGetErrorString(e);
-      }
-      for (Pending& p : s.reqs) {
-        if (cfg.hold_outputs) {
-          held[p.req.id] = p;
-        } else {
-          arena->release(p.out_off);
-          budget_used -= p.budget;
-        }
-        nrm_completion c;
-        c.id = p.req.id;
-        c.out = arena_base + p.out_off;
-        c.t_arrival_ns = p.t_arrival;
-        c.t_launch_ns = p.t_launch;
-        c.t_done_ns = t;
-        c.status = e == hipSuccess ? NRM_OK : NRM_EHIP;
-        done.push_back(c);
-        in_flight -= 1;
-      }
-      s.reqs.clear();
-      s.busy = false;
-      progressed = true;
-    }
-    // 2. admission into one free slot at a time, in arrival order; spread:
-    // each free slot takes its share of the waiting requests
-    int64_t free_slots = 0;
-    for (const Slot& s : slots) free_slots += s.busy ? 0 : 1;
-    for (Slot& s : slots) {
-      if (s.busy) continue;
-      batch.clear();
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        int64_t share = cfg.max_batch_rows;
-        if (cfg.spread) share = std::min<int64_t>(share, ((int64_t)queue.size() + free_slots - 1) / free_slots);
-        free_slots -= 1;
-        int64_t elems = 0;
-        while (!queue.empty() && (int64_t)batch.size() < share) {
-          Pending& p = queue.front();
-          const int64_t so = nrm::dtype_size(p.req.out_dtype), si = nrm::dtype_size(p.req.in_dtype);
-          const int64_t need = p.req.n * (si + so);
-          if (!batch.empty() && elems + p.req.n > cfg.max_batch_elems) break;
-          if (budget_used + need > cfg.budget_bytes) break;  // wait for memory
-          int64_t off = arena->alloc(std::max<int64_t>(p.req.n * so, 1));
-          if (off < 0) break;
-          p.out_off = off;
-          p.budget = need;
-          budget_used += need;
-          elems += p.req.n;
-          batch.push_back(p);
-          queue.pop_front();
-        }
-      }
-      if (batch.empty()) break;
-      launch(s, batch);
-      progressed = true;
-    }
-    if (stop.load() && !progressed) {
-      bool idle = true;
-      for (Slot& s : slots) idle = idle && !s.busy;
-      std::lock_guard<std::mutex> lk(mu);
-      if (idle && queue.empty()) break;
-    }
+    const bool progressed = core->step(now_ns());
+    if (stop.load() && !progressed && core->idle()) break;
     if (progressed) {
       last_activity = now_ns();
+    } else if (core->any_busy() || now_ns() - last_activity < (int64_t)cfg.idle_spin_us * 1000) {
+      // poll the slots' events (and the queue) again without sleeping: an
+      // arrival is then picked up without a thread wake-up
+      std::this_thread::yield();
     } else {
-      std::unique_lock<std::mutex> lk(mu);
-      bool any_busy = false;
-      for (Slot& s : slots) any_busy = any_busy || s.busy;
-      if (any_busy || now_ns() - last_activity < (int64_t)cfg.idle_spin_us * 1000) {
-        // poll the slots' events (and the queue) again without sleeping: an
-        // arrival is then picked up without a thread wake-up
-        lk.unlock();
-        std::this_thread::yield();
-      } else {
-        cv.wait_for(lk, std::chrono::microseconds(200));
-      }
+      std::unique_lock<std::mutex> lk(wake_mu);
+      cv.wait_for(lk, std::chrono::microseconds(200));
     }
   }
 }
@@ -327,14 +188,25 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
   // outputs live in the arena; a request's output is at most two thirds of
   // its budget (FP32 out of a 2-byte input), which sizes the default arena
   const int64_t arena = cfg->arena_bytes > 0 ? cfg->arena_bytes : cfg->budget_bytes * 2 / 3 + (int64_t(1) << 20);
-  hipError_t e = hipMalloc(&s->arena_base, (size_t)arena);
+  hipError_t e = hipMalloc(&s->ex.arena_base, (size_t)arena);
   if (e != hipSuccess) {
     delete s;
     return fail(NRM_ENOMEM, std::string("server arena hipMalloc: ") + hipGetErrorString(e));
   }
-  s->arena = new Arena(arena);
-  s->slots.resize(cfg->slots);
-  for (Slot& sl : s->slots) {
+  s->ex.accum = cfg->accum;
+  s->ex.slots.resize(cfg->slots);
+  nrm::SchedConfig sc;
+  sc.slots = cfg->slots;
+  sc.batching = cfg->batching != 0;
+  sc.single_plain = cfg->single_plain != 0;
+  sc.spread = cfg->spread != 0;
+  sc.hold_outputs = cfg->hold_outputs != 0;
+  sc.min_batch_rows = cfg->min_batch_rows;
+  sc.max_batch_rows = cfg->max_batch_rows;
+  sc.max_batch_elems = cfg->max_batch_elems;
+  sc.budget_bytes = cfg->budget_bytes;
+  s->core = new nrm::Scheduler(sc, arena, &s->ex);
+  for (HipExecutor::SlotRes& sl : s->ex.slots) {
     int st = nrm_create(&sl.ctx, device);
     if (st == NRM_OK) {
       nrm_batch_params bp;
@@ -363,21 +235,13 @@ int nrm_server_submit(nrm_server* s, const nrm_request* reqs, int64_t count) {
   for (int64_t i = 0; i < count; ++i) {
     int st = check_request(reqs[i]);
     if (st != NRM_OK) return st;
-    const int64_t need = reqs[i].n * (nrm::dtype_size(reqs[i].in_dtype) + nrm::dtype_size(reqs[i].out_dtype));
-    if (need > s->cfg.budget_bytes) return fail(NRM_EINVAL, "request larger than the server's budget");
+    if (nrm::Scheduler::need_of(reqs[i]) > s->cfg.budget_bytes)
+      return fail(NRM_EINVAL, "request larger than the server's budget");
   }
   const int64_t t = now_ns();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    for (int64_t i = 0; i < count; ++i) {
-      Pending p;
-      p.req = reqs[i];
-      p.t_submit = t;
-      p.t_arrival = reqs[i].t_arrival_ns > 0 ? reqs[i].t_arrival_ns : t;
-      s->queue.push_back(p);
-      s->in_flight += 1;
-    }
-  }
+  std::vector<int64_t> arrival((size_t)count);
+  for (int64_t i = 0; i < count; ++i) arrival[(size_t)i] = reqs[i].t_arrival_ns > 0 ? reqs[i].t_arrival_ns : t;
+  s->core->submit(reqs, arrival.data(), count);
   s->cv.notify_one();
   return NRM_OK;
 }
@@ -406,18 +270,12 @@ int nrm_server_replay(nrm_server* s, const nrm_request* reqs, int64_t count, int
       }
       // submit every request that is due, stamped with its scheduled arrival
       size_t j = i;
-      {
-        std::lock_guard<std::mutex> lk(s->mu);
-        while (j < trace.size() && origin + trace[j].t_arrival_ns <= t) {
-          Pending p;
-          p.req = trace[j];
-          p.t_submit = t;
-          p.t_arrival = origin + trace[j].t_arrival_ns;
-          s->queue.push_back(p);
-          s->in_flight += 1;
-          ++j;
-        }
+      std::vector<int64_t> arrival;
+      while (j < trace.size() && origin + trace[j].t_arrival_ns <= t) {
+        arrival.push_back(origin + trace[j].t_arrival_ns);
+        ++j;
       }
+      s->core->submit(&trace[i], arrival.data(), (int64_t)(j - i));
       s->cv.notify_one();
       i = j;
     }
@@ -428,37 +286,29 @@ int nrm_server_replay(nrm_server* s, const nrm_request* reqs, int64_t count, int
 
 int nrm_server_poll(nrm_server* s, nrm_completion* out, int64_t max, int64_t* count) {
   if (!s || !count || max < 0 || (max > 0 && !out)) return fail(NRM_EINVAL, "bad arguments");
-  std::lock_guard<std::mutex> lk(s->mu);
-  int64_t k = std::min<int64_t>(max, (int64_t)s->done.size());
-  for (int64_t i = 0; i < k; ++i) out[i] = s->done[i];
-  s->done.erase(s->done.begin(), s->done.begin() + k);
-  *count = k;
-  if (s->error != NRM_OK) return fail(s->error, s->error_msg);
+  *count = s->core->take_done(out, max, reinterpret_cast<int64_t>(s->ex.arena_base));
   return NRM_OK;
 }
 
 int nrm_server_release(nrm_server* s, int64_t id) {
   if (!s) return fail(NRM_EINVAL, "NULL server");
-  std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->held.find(id);
-  if (it == s->held.end()) return fail(NRM_EINVAL, "no held output with this id");
-  s->arena->release(it->second.out_off);
-  s->budget_used -= it->second.budget;
-  s->held.erase(it);
+  if (!s->core->release(id)) return fail(NRM_EINVAL, "no held output with this id");
   s->cv.notify_one();
   return NRM_OK;
 }
 
 int nrm_server_stats(nrm_server* s, nrm_server_counters* st) {
   if (!s || !st) return fail(NRM_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  st->in_flight = s->in_flight;
-  st->queued = (int64_t)s->queue.size();
-  st->budget_used = s->budget_used;
-  st->batches = s->batches;
-  st->launches = s->launches;
+  s->core->stats(st);
   st->replaying = s->replay_running.load();
-  st->held = (int64_t)s->held.size();
+  return NRM_OK;
+}
+
+int nrm_server_last_failure(nrm_server* s) {
+  if (!s) return fail(NRM_EINVAL, "NULL server");
+  std::string msg;
+  const int st = s->core->first_error(&msg);
+  if (st != NRM_OK) return fail(st, msg);
   return NRM_OK;
 }
 
@@ -469,14 +319,14 @@ int nrm_server_destroy(nrm_server* s) {
   if (s->replayer.joinable()) s->replayer.join();
   if (s->scheduler.joinable()) s->scheduler.join();
   DeviceGuard g(s->device);
-  for (Slot& sl : s->slots) {
+  for (HipExecutor::SlotRes& sl : s->ex.slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);  // teardown: errors were reported per request
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.ctx) nrm_destroy(sl.ctx);
   }
-  if (s->arena_base) (void)hipFree(s->arena_base);
-  delete s->arena;
+  if (s->ex.arena_base) (void)hipFree(s->ex.arena_base);
+  delete s->core;
   delete s;
   return NRM_OK;
 }

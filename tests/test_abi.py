@@ -191,3 +191,38 @@ def test_height_cap_keeps_the_stated_bound():
     assert bound(hi + 26) < 4e-6 < bound(hi + 27)
     src = open(os.path.join(ROOT, "paper_2207_00257_amd", "csrc", "nrm_api.cpp")).read()
     assert "p.max_height > %d" % hi in src
+
+
+def test_tuning_cache_read_by_the_library(lib):
+    """The library reads the committed tuning cache itself: the entry the
+    autotuner stored for (gfx950, f32, f32, plain, 2^28), field by field; no
+    entry for a size class it has not tuned; and a cache named by
+    NRM_TUNE_CACHE (read once per process: checked in a child process)."""
+    import json
+    import subprocess
+    import sys
+
+    cache = json.load(open(os.path.join(ROOT, "paper_2207_00257_amd", "tuned", "plain.json")))
+    want = cache["gfx950/f32->f32/f32/2^28"]["params"]
+    p = L.NrmParams()
+    assert lib.nrm_tuned_params(b"gfx950", 0, 0, 0, (1 << 28) + 5, ctypes.byref(p)) == 1
+    for k, v in want.items():
+        assert getattr(p, k) == v, k
+    d = L.NrmParams()
+    assert lib.nrm_default_params(ctypes.byref(d)) == L.NRM_OK
+    assert lib.nrm_tuned_params(b"gfx950", 0, 0, 0, 1 << 12, ctypes.byref(p)) == 0
+    assert bytes(p) == bytes(d)
+    assert lib.nrm_tuned_params(b"gfx942", 0, 0, 0, 1 << 28, ctypes.byref(p)) == 0
+    assert lib.nrm_tuned_params(None, 0, 0, 0, 1 << 28, ctypes.byref(p)) == L.NRM_EINVAL
+    code = ("import ctypes, sys; sys.path.insert(0, %r); from paper_2207_00257_amd import _lib as L; "
+            "p = L.NrmParams(); r = L.lib().nrm_tuned_params(b'gfxtest', 1, 0, 1, 3000, ctypes.byref(p)); "
+            "print(r, p.block, p.map_grid, p.tile_log2)" % ROOT)
+    import tempfile
+    with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as f:
+        json.dump({"gfxtest/bf16->f32/kahan/2^11": {"ms": 1.0, "params": {"block": 128, "map_grid": 77,
+                                                                           "tile_log2": 11}},
+                   "other": [1, 2, {"x": "y"}]}, f)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       env=dict(os.environ, NRM_TUNE_CACHE=f.name))
+    os.unlink(f.name)
+    assert r.stdout.split() == ["1", "128", "77", "11"], r.stdout + r.stderr

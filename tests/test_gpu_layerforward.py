@@ -1,5 +1,5 @@
-"""The Fig. 9-shaped tile kernel on the GPU: its four forms (as printed, two
-barriers eliminated, store/load promoted, tile in registers) give bitwise
+"""The Fig. 9-shaped tile kernel on the GPU: its four forms (every barrier,
+two barriers eliminated, store/load promoted, tile in registers) give bitwise
 equal results, and
 those match the FP64 oracle within 6 u (u = 2^-24; positive inputs, one
 rounded product and at most four tree additions per value)."""
@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
 U = 2.0 ** -24
-FORMS = ("printed", "eliminated", "promoted", "registers")
+FORMS = ("all", "eliminated", "promoted", "registers")
 
 
 def run(form, h, v):

@@ -52,16 +52,22 @@ def test_brute_force_naive_1024():
 SMALL_CTX = {}
 
 
-@pytest.mark.parametrize("small", [True, False], ids=["default", "two_kernels"])
+MODES = {"default": {}, "two_kernels": dict(small_n=0, resident_n=0), "resident_only": dict(small_n=0)}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33, 63, 64, 65, 255, 256, 257, 1000,
-                               1023, 1025, 4095, 4097, 65535, 65536, 65537, 262143, 1000003, 3000017])
-def test_sizes_and_ragged_tails(n, small):
+                               1023, 1025, 4095, 4097, 65535, 65536, 65537, 262143, 1000003, 1 << 20,
+                               (1 << 20) + 1, 3000017])
+def test_sizes_and_ragged_tails(n, mode):
     """Every size through the default launch (n <= 2^16: one block holding
-    the input in registers) and with the one-block form off (two kernels)."""
-    if small not in SMALL_CTX:
-        SMALL_CTX[small] = api.Context() if small else api.Context(small_n=0)
+    the input in registers; n <= 2^20: one block per 4096 elements, each
+    held in registers across the exchange of sums), with both one-launch
+    forms off (two kernels), and with only the second (from n = 1)."""
+    if mode not in SMALL_CTX:
+        SMALL_CTX[mode] = api.Context(**MODES[mode])
     x = synth.lognormal_f32(n, 10 + n % 97, 1.0)
-    assert_f32_close(run_f32(x, SMALL_CTX[small]), oracle.normalize(x), what="n=%d small=%s" % (n, small))
+    assert_f32_close(run_f32(x, SMALL_CTX[mode]), oracle.normalize(x), what="n=%d %s" % (n, mode))
 
 
 @pytest.mark.parametrize("accum", ["f32", "kahan"])
@@ -160,11 +166,11 @@ def test_in_place():
     assert_f32_close(t.cpu().numpy(), oracle.normalize(x), what="in place")
 
 
+@pytest.mark.parametrize("n", [100_003, 3_000_011], ids=["one_launch", "two_kernels"])
 @pytest.mark.parametrize("in_off,out_off", [(1, 1), (2, 2), (3, 3), (1, 0), (0, 3), (2, 1)])
-def test_misaligned_pointers(in_off, out_off):
+def test_misaligned_pointers(in_off, out_off, n):
     """Element offsets inside larger buffers: unaligned heads, and outputs whose
-    alignment differs from the input's (element-wise map path)."""
-    n = 100_003
+    alignment differs from the input's (element-wise stores)."""
     x = synth.lognormal_f32(n, 25, 1.0)
     big_in = torch.zeros(n + 8, device=DEV)
     big_in[in_off:in_off + n] = gpu(x)
@@ -227,7 +233,7 @@ PARAM_SETS = [
 
 @pytest.mark.parametrize("params", PARAM_SETS, ids=lambda p: ",".join("%s=%s" % kv for kv in p.items()))
 def test_launch_parameters(params):
-    ctx = api.Context(**dict(params, small_n=0))  # the two kernels at every size
+    ctx = api.Context(**dict(params, small_n=0, resident_n=0))  # the two kernels at every size
     for n, seed in ((1_000_003, 30), (4097, 31), (1 << 20, 32)):
         x = synth.lognormal_f32(n, seed, 1.0)
         assert_f32_close(run_f32(x, ctx), oracle.normalize(x), what="%s n=%d" % (params, n))
@@ -338,7 +344,8 @@ def test_parameter_validation():
     for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(grid=0),
                 dict(layout=3), dict(map_layout=-1), dict(max_height=23), dict(max_height=41),
                 dict(reverse_map=2), dict(map_nt=-1), dict(tile_log2=9), dict(tile_log2=23),
-                dict(fused_combine=2), dict(small_n=-1), dict(reduce_keep_mib=-1), dict(reduce_keep_mib=4097)):
+                dict(fused_combine=2), dict(small_n=-1), dict(reduce_keep_mib=-1), dict(reduce_keep_mib=4097),
+                dict(resident_n=-1), dict(resident_n=(1 << 20) + 1)):
         with pytest.raises(L.NrmError):
             ctx.set_params(**bad)
         assert ctx.get_params() == good, bad
@@ -433,10 +440,72 @@ def test_fused_tiled_misaligned_pointers(in_off, out_off):
     x = synth.lognormal_f32(n + 8, 46, 1.0)
     base_in = gpu(x)
     base_out = torch.zeros(n + 8, device=DEV)
-    ctx = api.Context(layout=2, map_layout=2, fused_combine=1, tile_log2=12)
+    ctx = api.Context(layout=2, map_layout=2, fused_combine=1, tile_log2=12, resident_n=0)
     api.normalize(base_out[out_off:out_off + n], base_in[in_off:in_off + n], ctx=ctx)
     torch.cuda.synchronize()
     got = base_out.cpu().numpy()
     assert_f32_close(got[out_off:out_off + n], oracle.normalize(x[in_off:in_off + n]), what="fused misaligned")
     assert not got[:out_off].any() and not got[out_off + n:].any()
     ctx.close()
+
+
+RESIDENT_SIZES = [65537, 4096 * 17 - 1, 4096 * 17, 4096 * 17 + 1, 4096 * 100 + 33, (1 << 20) - 1, 1 << 20]
+
+
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+def test_resident_plain_sizes_dtypes_and_repeats(accum):
+    """The one-launch mid-size form (a block per 4096 elements, exchanging
+    tagged sums): sizes at segment boundaries up to 2^20, FP32 / BF16 / FP16,
+    three calls in a row on one context (each call's partials carry its own
+    call number, so a later call never takes an earlier one's) with the same
+    bits each time, and the sum it leaves for nrm_get_last_sum."""
+    ctx = api.Context()
+    for n in RESIDENT_SIZES:
+        x = synth.lognormal_f32(n, 300 + n % 89, 1.0)
+        ref = oracle.normalize(x)
+        first = None
+        for _ in range(3):
+            got = run_f32(x, ctx, accum=accum)
+            assert_f32_close(got, ref, what="resident n=%d %s" % (n, accum))
+            if first is None:
+                first = got
+            assert np.array_equal(got.view(np.uint32), first.view(np.uint32)), "repeat differs at n=%d" % n
+        s = ctypes.c_float()
+        L.check(L.lib().nrm_get_last_sum(ctx.handle, None, ctypes.byref(s)), "nrm_get_last_sum")
+        S = float(np.sum(x, dtype=np.float64))
+        assert abs(s.value - S) <= 4e-6 * S, (n, s.value, S)
+    bits = synth.lognormal_bf16((1 << 19) + 7, 310, 2.0)
+    inp = gpu(bits.view(np.int16)).view(torch.bfloat16)
+    out = torch.empty_like(inp)
+    api.normalize(out, inp, accum=accum, ctx=ctx)
+    torch.cuda.synchronize()
+    ref = oracle.normalize(bits, "bf16")
+    got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
+    assert_within_ulp(got, ref, ulp_bf16, what="resident bf16")
+    h = synth.f32_to_f16_bits(synth.lognormal_f32(300_001, 311, 1.0))
+    inp = gpu(h.view(np.int16)).view(torch.float16)
+    out = torch.empty(inp.numel(), dtype=torch.float32, device=DEV)
+    api.normalize(out, inp, accum=accum, ctx=ctx)
+    torch.cuda.synchronize()
+    assert_f32_close(out.cpu().numpy(), oracle.normalize(h, "f16"), what="resident f16->f32")
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+def test_resident_plain_matches_alternating_contexts_and_in_place():
+    """Two contexts used in turn (each its own call numbers) and an in-place
+    call: all within the bound, and the same bits as a fresh context."""
+    n = 4096 * 150 + 5
+    x = synth.lognormal_f32(n, 320, 1.0)
+    ref = oracle.normalize(x)
+    a, b = api.Context(), api.Context()
+    outs = [run_f32(x, c) for c in (a, b, a, b, a)]
+    for o in outs:
+        assert np.array_equal(o.view(np.uint32), outs[0].view(np.uint32))
+    assert_f32_close(outs[0], ref, what="alternating contexts")
+    t = gpu(x)
+    api.normalize(t, t, ctx=a)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), outs[0].view(np.uint32)), "in place differs"
+    a.close()
+    b.close()

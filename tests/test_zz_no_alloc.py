@@ -1,6 +1,6 @@
 """The allocation-free plain entry point, nrm_normalize_noalloc, called
-through the C ABI: its outputs must equal nrm_normalize_ex's on a fresh
-context with the default parameters (same kernels, same plan: the same bits),
+through the C ABI: its outputs must equal nrm_normalize_ex's on a context
+with the device's default parameters (same kernels, same plan: the same bits),
 and the oracle's within the FP32 bound, on two calls in a row with the second
 smaller; sizes beyond its scratch are rejected before anything is enqueued."""
 import ctypes
@@ -36,8 +36,12 @@ def _ex(ctx, out, inp, accum=L.NRM_ACC_F32):
 
 @pytest.fixture(scope="module")
 def ctx():
+    # the device's default parameters, set explicitly: no tuning-cache entries
     h = ctypes.c_void_p()
     L.check(L.lib().nrm_create(ctypes.byref(h), 0), "nrm_create")
+    p = L.NrmParams()
+    L.check(L.lib().nrm_get_params(h, ctypes.byref(p)), "nrm_get_params")
+    L.check(L.lib().nrm_set_params(h, ctypes.byref(p)), "nrm_set_params")
     yield h
     L.check(L.lib().nrm_destroy(h), "nrm_destroy")
 
@@ -46,6 +50,7 @@ def ctx():
     (((1 << 24) + 1021, (1 << 20) + 3), L.NRM_ACC_F32),   # two-kernel path, then a smaller one
     (((1 << 22) + 77, 40000), L.NRM_ACC_KAHAN),           # two-kernel path, then the one-block path
     ((70000, 513), L.NRM_ACC_F32),                         # both just around the one-block limit
+    (((1 << 20), (1 << 17) + 3), L.NRM_ACC_KAHAN),         # the one-launch mid-size form twice
 ])
 def test_matches_existing_entry_point_twice(ctx, sizes, accum):
     for k, n in enumerate(sizes):

@@ -111,11 +111,14 @@ typedef struct {
   int32_t small_n;      /* 0..2^16: n up to this runs as one launch of one 1024-thread block that
                            reads the input once into registers (16 binary32 or 8 2-byte vectors
                            per thread), reduces it, and divides from the registers: one read,
-                           one write, one launch; 0: never */
+                           one write, one launch. Default 0 (never): the resident form below was
+                           faster per call at every size */
   int32_t resident_n;   /* 0..2^20: n in (small_n, resident_n] runs as one launch of one 256-thread
                            block per 4096 elements, each block holding its elements in registers
                            while the blocks exchange their sums: one read, one write, one launch
-                           (all n / 4096 blocks must be able to run at once: one per CU); 0: never */
+                           (all n / 4096 blocks must be able to run at once: one per CU). Up to 64
+                           blocks every block reads every block's sum; beyond, the last block to
+                           arrive publishes the total. Default 2^18; 0: never */
 } nrm_params;
 
 /* Launch parameters of the ragged batched path. Start from

@@ -57,8 +57,14 @@ nrm_params default_params() {
   p.reduce_keep_mib = 256;
   p.tile_log2 = 12;
   p.fused_combine = 1;
-  p.small_n = 65536;
-  p.resident_n = 1 << 20;
+  // n <= 2^18 in one launch of a block per 4096 elements (one read, one
+  // write); above, the two kernels. Measured per call on MI355X (device time
+  // of a synchronized call): 8.6-12.6 us up to 2^18 against 12.1-13.2 us for
+  // two kernels; beyond 64 segments the exchange costs more than the kernel
+  // boundary (2^20: 17.5 against 13.3 us). The one-block form (small_n) lost
+  // to it from 2^14 on (2^16: 17.5 us).
+  p.small_n = 0;
+  p.resident_n = 1 << 18;
   return p;
 }
 

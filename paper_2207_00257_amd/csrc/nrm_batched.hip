@@ -959,7 +959,13 @@ __device__ __forceinline__ Acc<ACC> gather_row(const ResExchange& x, int nseg) {
 // divide from the registers, write. The row's result (RowMap) is left in
 // *s_bcast; lse, when given, receives the softmax row's log-sum-exp (from
 // segment 0).
-template <int DTI, int DTO, int ACC, int BLOCK, int LOG2, int PER_LANE>
+//
+// DIRECT: every block of the row reads all partials itself (one round trip:
+// the lowest latency for a single row of few segments) instead of waiting for
+// the last arrival's total (fewer polls: the better throughput for a batch);
+// the arrival count then only finds the last block, which moves the call
+// number on.
+template <int DTI, int DTO, int ACC, int BLOCK, int LOG2, int PER_LANE, bool DIRECT = false>
 __device__ __forceinline__ void resident_unit(const RowDesc& d, int seg, const ResExchange& x, Acc<ACC>* slots,
                                               RowRes* s_bcast, float* lse_row) {
   constexpr int VEC = Elem<DTI>::VEC;
@@ -1010,6 +1016,21 @@ __device__ __forceinline__ void resident_unit(const RowDesc& d, int seg, const R
       *s_bcast = f0.result();
       if constexpr (ACC == ACC_SOFTMAX) {
         if (lse_row) *lse_row = f0.lse();
+      }
+    }
+  } else if (DIRECT && t < 64) {
+    if (t == 0) publish_tagged<ACC>(x.slots + 2 * seg, x.ep, tot);
+    const Acc<ACC> total = gather_row<ACC, PER_LANE>(x, nseg);
+    if (t == 0) {
+      const RowMap<ACC> f0 = RowMap<ACC>::of(total);
+      *s_bcast = f0.result();
+      if constexpr (ACC == ACC_SOFTMAX) {
+        if (lse_row && seg == 0) *lse_row = f0.lse();
+      }
+      // after this block's reads of the tags: the last one moves the call on
+      if (__hip_atomic_fetch_add(x.arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nseg - 1) {
+        __hip_atomic_store(x.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (x.call) __hip_atomic_fetch_add(x.call, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   } else if (t < 64) {
@@ -1347,7 +1368,7 @@ constexpr int PRES_BLOCK = 256;
 constexpr int PRES_LOG2 = 12;
 constexpr int PRES_MAX_SEGMENTS = 256;
 
-template <int DTI, int DTO, int ACC>
+template <int DTI, int DTO, int ACC, bool DIRECT>
 __global__ void __launch_bounds__(PRES_BLOCK) plain_resident_kernel(RowDesc d, PlainResidentWs w) {
   __shared__ Acc<ACC> slots[MAX_WAVES];
   __shared__ RowRes s_bcast;
@@ -1355,16 +1376,19 @@ __global__ void __launch_bounds__(PRES_BLOCK) plain_resident_kernel(RowDesc d, P
   // block to arrive moves the call number on once every block has read it
   const unsigned long long call = __hip_atomic_load(w.call, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const ResExchange x{w.slots, w.total, w.arrivals, (uint32_t)(call % 0xFFFFFFFFull) + 1u, w.error, w.stall, w.call};
-  resident_unit<DTI, DTO, ACC, PRES_BLOCK, PRES_LOG2, PRES_MAX_SEGMENTS / 64>(d, blockIdx.x, x, slots, &s_bcast,
-                                                                            nullptr);
+  resident_unit<DTI, DTO, ACC, PRES_BLOCK, PRES_LOG2, DIRECT ? 1 : PRES_MAX_SEGMENTS / 64, DIRECT>(
+      d, blockIdx.x, x, slots, &s_bcast, nullptr);
   if (threadIdx.x == 0 && blockIdx.x == 0) w.sum_out[0] = s_bcast.a;  // the invariant, for nrm_get_last_sum
 }
 
-template <int ACC>
+// Rows of at most 64 segments exchange directly (one lane per segment).
+constexpr int PRES_DIRECT_MAX = 64;
+
+template <int ACC, bool DIRECT>
 hipError_t plain_resident_acc(const RowDesc& d, const PlainResidentWs& w, hipStream_t s) {
   const unsigned grid = (unsigned)((d.n + (int64_t(1) << PRES_LOG2) - 1) >> PRES_LOG2);
 #define NRM_PR(I, O) \
-  hipLaunchKernelGGL((plain_resident_kernel<I, O, ACC>), dim3(grid), dim3(PRES_BLOCK), 0, s, d, w)
+  hipLaunchKernelGGL((plain_resident_kernel<I, O, ACC, DIRECT>), dim3(grid), dim3(PRES_BLOCK), 0, s, d, w)
   switch (d.in_dt * 3 + d.out_dt) {
     case NRM_F32 * 3 + NRM_F32: NRM_PR(NRM_F32, NRM_F32); break;
     case NRM_F32 * 3 + NRM_BF16: NRM_PR(NRM_F32, NRM_BF16); break;
@@ -1393,7 +1417,10 @@ hipError_t launch_plain_resident(const void* in, int in_dt, void* out, int out_d
   d.n = n;
   d.in_dt = in_dt;
   d.out_dt = out_dt;
-  return acc == NRM_ACC_KAHAN ? plain_resident_acc<NRM_ACC_KAHAN>(d, w, s) : plain_resident_acc<NRM_ACC_F32>(d, w, s);
+  const bool direct = ((n + (int64_t(1) << PRES_LOG2) - 1) >> PRES_LOG2) <= PRES_DIRECT_MAX;
+  if (acc == NRM_ACC_KAHAN)
+    return direct ? plain_resident_acc<NRM_ACC_KAHAN, true>(d, w, s) : plain_resident_acc<NRM_ACC_KAHAN, false>(d, w, s);
+  return direct ? plain_resident_acc<NRM_ACC_F32, true>(d, w, s) : plain_resident_acc<NRM_ACC_F32, false>(d, w, s);
 }
 
 hipError_t launch_small(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc, float* sum_out,

@@ -165,4 +165,4 @@ def latency_stats(comps, t0_ns=None) -> dict:
     span_s = (done.max() - arr.min()) / 1e9 if len(comps) > 1 else float("nan")
     return {"requests": len(comps), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "req_per_s": len(comps) / span_s,
-            "span_s": span_s}
+            "span_s": span_s, "failed": int(sum(1 for c in comps if c[5] != 0))}

@@ -183,7 +183,9 @@ def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=Fa
 def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
     """Sweep the batched path's launch shape on the ragged workload (rows with
     log-uniform lengths in [32, 2^20], LogNormal(0,1) FP32), timing whole
-    calls (planner, both phases) with the library's events."""
+    calls (planner, resident rows, tile phases) with the library's events:
+    first the resident rows' limit and grid, then, when some row of the
+    workload is longer than that limit, the tile phases' shapes."""
     import torch
 
     from . import api, synth
@@ -197,14 +199,6 @@ def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     base_p = ctx.get_batch_params()
     base_p["graph"] = 1
-    stage1 = []
-    for block in (256, 512, 1024):
-        for unroll in ((2, 4) if quick else (1, 2, 4, 8)):
-            for tile_log2 in ((14, 15, 16) if quick else (13, 14, 15, 16, 17)):
-                for short_regs in ((2, 8) if quick else (1, 2, 4, 8)):
-                    for gmul in ((2, 4) if quick else (1, 2, 4, 8)):
-                        stage1.append(dict(base_p, block=block, unroll=unroll, tile_log2=tile_log2,
-                                           short_regs=short_regs, grid=cus * gmul * max(1, 1024 // block)))
     table, best, best_t = [], None, float("inf")
     t0 = time.time()
     ctx.batch_reserve(rows, x.size)
@@ -222,6 +216,33 @@ def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
         ctx.set_timing(False)
         return t / c
 
+    # resident rows first: how many segments a row may have to be held on
+    # chip (0: none, every row takes the tile phases), and how many blocks
+    for segs in ((0, 64) if quick else (0, 16, 32, 64)):
+        for gmul in ((2,) if quick else (1, 1.5, 2)):
+            p = dict(base_p, resident_segments=segs, resident_grid=max(segs, int(cus * gmul)))
+            ms = measure(p)
+            if ms is None:
+                continue
+            table.append({"kernel": "batched", "params": p, "ms": ms})
+            if ms < best_t:
+                best, best_t = p, ms
+    base_p = dict(best)
+    # the tile phases' shapes matter only for rows longer than the resident
+    # limit; with every row of the workload resident they are not swept
+    longest = int((offs[1:] - offs[:-1]).max())
+    all_resident = base_p["resident_segments"] << 14 >= longest
+    if all_resident:
+        log("every row is resident (longest %d): tile phases not swept" % longest)
+    stage1 = []
+    if not all_resident:
+        for block in (256, 512, 1024):
+            for unroll in ((2, 4) if quick else (1, 2, 4, 8)):
+                for tile_log2 in ((14, 15, 16) if quick else (13, 14, 15, 16, 17)):
+                    for short_regs in ((2, 8) if quick else (1, 2, 4, 8)):
+                        for gmul in ((2, 4) if quick else (1, 2, 4, 8)):
+                            stage1.append(dict(base_p, block=block, unroll=unroll, tile_log2=tile_log2,
+                                               short_regs=short_regs, grid=cus * gmul * max(1, 1024 // block)))
     for p in stage1:
         ms = measure(p)
         if ms is None:
@@ -229,7 +250,7 @@ def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
         table.append({"kernel": "batched", "params": p, "ms": ms})
         if ms < best_t:
             best, best_t = p, ms
-    for map_block in (256, 512, 1024):
+    for map_block in ((256, 512, 1024) if not all_resident else ()):
         for map_unroll in (1, 2, 4, 8):
             for gmul in (1, 2, 4, 8, 16, 32):
                 p = dict(best, map_block=map_block, map_unroll=map_unroll,
@@ -241,7 +262,7 @@ def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
                 if ms < best_t:
                     best, best_t = p, ms
     # the temporal tail phase 1 leaves in the last-level cache for phase 2
-    for keep in (0, 64, 128, 192, 224, 256, 288):
+    for keep in ((0, 64, 128, 192, 224, 256, 288) if not all_resident else ()):
         p = dict(best, keep_mib=keep)
         ms = measure(p)
         if ms is None:

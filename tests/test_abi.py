@@ -226,3 +226,57 @@ def test_tuning_cache_read_by_the_library(lib):
                        env=dict(os.environ, NRM_TUNE_CACHE=f.name))
     os.unlink(f.name)
     assert r.stdout.split() == ["1", "128", "77", "11"], r.stdout + r.stderr
+
+
+def _declared_prototypes():
+    """name -> list of parameter types (text) from include/*.h."""
+    protos = {}
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"#[^\n]*", "", text)
+        for m in re.finditer(r"(?:^|;|\})\s*(?:const\s+)?[A-Za-z_]\w*\s*\**\s*([A-Za-z_]\w*)\s*\(([^;{)]*)\)\s*;",
+                             text, flags=re.M):
+            params = [p.strip() for p in m.group(2).replace("\n", " ").split(",") if p.strip()]
+            if params == ["void"]:
+                params = []
+            protos[m.group(1)] = params
+    return protos
+
+
+def _kind_of_c(param):
+    t = re.sub(r"\b[A-Za-z_]\w*$", "", param.strip()).strip()  # drop the parameter name
+    t = t.replace("const ", "").strip()
+    if "*" in t:
+        return "char*" if t.replace(" ", "") == "char*" else "ptr"
+    return {"int64_t": "i64", "int": "i32", "int32_t": "i32"}.get(t, t)
+
+
+def _kind_of_ctypes(ct):
+    if ct is ctypes.c_char_p:
+        return "char*"
+    if ct is ctypes.c_int64:
+        return "i64"
+    if ct is ctypes.c_int:
+        return "i32"
+    return "ptr"  # c_void_p and POINTER(...)
+
+
+def test_binding_signatures_match_the_header(lib):
+    """Every function the binding declares exists in include/nrm.h with the
+    same number of parameters, each of the same kind (pointer, 32-bit or
+    64-bit integer), so a marshalling slip cannot pass unnoticed."""
+    protos = _declared_prototypes()
+    checked = 0
+    for name in dir(lib):
+        fn = getattr(lib, name, None)
+        args = getattr(fn, "argtypes", None)
+        if name.startswith("_") or args is None:
+            continue
+        assert name in protos, name
+        want = [_kind_of_c(p) for p in protos[name]]
+        got = [_kind_of_ctypes(a) for a in args]
+        assert want == got, (name, protos[name], got)
+        checked += 1
+    assert checked >= 35, checked  # every function the binding declares

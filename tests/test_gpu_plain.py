@@ -52,7 +52,8 @@ def test_brute_force_naive_1024():
 SMALL_CTX = {}
 
 
-MODES = {"default": {}, "two_kernels": dict(small_n=0, resident_n=0), "resident_only": dict(small_n=0)}
+MODES = {"default": {}, "two_kernels": dict(small_n=0, resident_n=0), "resident_2p20": dict(small_n=0, resident_n=1 << 20),
+         "small": dict(small_n=65536, resident_n=0)}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -60,10 +61,11 @@ MODES = {"default": {}, "two_kernels": dict(small_n=0, resident_n=0), "resident_
                                1023, 1025, 4095, 4097, 65535, 65536, 65537, 262143, 1000003, 1 << 20,
                                (1 << 20) + 1, 3000017])
 def test_sizes_and_ragged_tails(n, mode):
-    """Every size through the default launch (n <= 2^16: one block holding
-    the input in registers; n <= 2^20: one block per 4096 elements, each
-    held in registers across the exchange of sums), with both one-launch
-    forms off (two kernels), and with only the second (from n = 1)."""
+    """Every size through the default launch (n <= 2^18: one block per 4096
+    elements, each held in registers across the exchange of sums; above: two
+    kernels), with both one-launch forms off (two kernels), with the
+    resident form up to 2^20 (the single published total beyond 64
+    segments), and with the one-block form (n <= 2^16)."""
     if mode not in SMALL_CTX:
         SMALL_CTX[mode] = api.Context(**MODES[mode])
     x = synth.lognormal_f32(n, 10 + n % 97, 1.0)
@@ -74,17 +76,19 @@ def test_sizes_and_ragged_tails(n, mode):
 @pytest.mark.parametrize("dt", ["bf16", "f16"])
 def test_small_path_two_byte_inputs(accum, dt):
     """2-byte inputs through the one-block form (8 vectors per thread), to
-    binary32 and to their own type, at the form's capacity and below."""
-    for n in (1, 777, 65536):
+    binary32 and to their own type, at the form's capacity and below; then
+    the same through the default launch."""
+    small = api.Context(small_n=65536, resident_n=0)
+    for n, ctx in ((1, small), (777, small), (65536, small), (65536, None), (200_001, None)):
         x = synth.lognormal_f32(n, 20 + n % 13, 1.0)
         bits = synth.f32_to_bf16_bits(x) if dt == "bf16" else synth.f32_to_f16_bits(x)
         tdt = torch.bfloat16 if dt == "bf16" else torch.float16
         inp = gpu(bits.view(np.int16)).view(tdt)
         ref = oracle.normalize(bits, dt)
         out32 = torch.empty(n, device=DEV)
-        api.normalize(out32, inp, accum=accum)
+        api.normalize(out32, inp, accum=accum, ctx=ctx)
         out16 = torch.empty_like(inp)
-        api.normalize(out16, inp, accum=accum)
+        api.normalize(out16, inp, accum=accum, ctx=ctx)
         torch.cuda.synchronize()
         assert_f32_close(out32.cpu().numpy(), ref, what="%s->f32 n=%d" % (dt, n))
         if dt == "bf16":
@@ -97,7 +101,7 @@ def test_small_path_two_byte_inputs(accum, dt):
 
 def test_small_path_in_place_and_last_sum():
     x = synth.uniform_f32(50_000, 21)
-    ctx = api.Context()
+    ctx = api.Context(small_n=65536)
     t = gpu(x)
     api.normalize(t, t, ctx=ctx)
     torch.cuda.synchronize()
@@ -449,7 +453,8 @@ def test_fused_tiled_misaligned_pointers(in_off, out_off):
     ctx.close()
 
 
-RESIDENT_SIZES = [65537, 4096 * 17 - 1, 4096 * 17, 4096 * 17 + 1, 4096 * 100 + 33, (1 << 20) - 1, 1 << 20]
+RESIDENT_SIZES = [65537, 4096 * 17 - 1, 4096 * 17, 4096 * 17 + 1, 4096 * 64, 4096 * 64 + 1, 4096 * 100 + 33,
+                  (1 << 20) - 1, 1 << 20]
 
 
 @pytest.mark.parametrize("accum", ["f32", "kahan"])
@@ -458,8 +463,10 @@ def test_resident_plain_sizes_dtypes_and_repeats(accum):
     tagged sums): sizes at segment boundaries up to 2^20, FP32 / BF16 / FP16,
     three calls in a row on one context (each call's partials carry its own
     call number, so a later call never takes an earlier one's) with the same
-    bits each time, and the sum it leaves for nrm_get_last_sum."""
-    ctx = api.Context()
+    bits each time, and the sum it leaves for nrm_get_last_sum. resident_n =
+    2^20: up to 64 segments every block reads every partial, beyond that the
+    last block to arrive publishes the total."""
+    ctx = api.Context(resident_n=1 << 20)
     for n in RESIDENT_SIZES:
         x = synth.lognormal_f32(n, 300 + n % 89, 1.0)
         ref = oracle.normalize(x)
@@ -498,7 +505,7 @@ def test_resident_plain_matches_alternating_contexts_and_in_place():
     n = 4096 * 150 + 5
     x = synth.lognormal_f32(n, 320, 1.0)
     ref = oracle.normalize(x)
-    a, b = api.Context(), api.Context()
+    a, b = api.Context(resident_n=1 << 20), api.Context(resident_n=1 << 20)
     outs = [run_f32(x, c) for c in (a, b, a, b, a)]
     for o in outs:
         assert np.array_equal(o.view(np.uint32), outs[0].view(np.uint32))

@@ -365,9 +365,9 @@ def main():
 
 def bench_ragged(args):
     """Ragged batched workload: one step = one batched call over 4096 rows
-    (planner + phase 1 + phase 2, replayed from a captured hipGraph). Also
-    times the same rows as one plain normalize call per row (two kernel
-    launches each) for comparison."""
+    (planner, resident rows, tile phases, replayed from a captured hipGraph).
+    Also times the basic C form on the default context, and the same rows as
+    one plain normalize call per row, for comparison."""
     import ctypes
 
     import numpy as np
@@ -392,15 +392,33 @@ def bench_ragged(args):
     for _ in range(args.warmup):
         api.normalize_batched(out, inp, offs_d, ctx=ctx)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    for k in range(args.steps):
         api.normalize_batched(out, inp, offs_d, ctx=ctx)
-    e1.record(stream)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    per_step = step_stats([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
     if ctx.device_error() != L.NRM_OK:
         raise RuntimeError("device reported invalid rows")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the basic C form a C caller uses: normalize_batched(out, in, offsets,
+    # rows) on the default context with the library's own parameters and
+    # tuning (it reads offsets[rows] back, which synchronizes the null stream)
+    lib = L.lib()
+    raw = lambda: L.check(lib.normalize_batched(out.data_ptr(), inp.data_ptr(), offs_d.data_ptr(), rows),
+                          "normalize_batched")
+    for _ in range(max(4, args.warmup)):
+        raw()
+    torch.cuda.synchronize()
+    null = torch.cuda.default_stream(dev)
+    e0.record(null)
+    for _ in range(args.steps):
+        raw()
+    e1.record(null)
+    torch.cuda.synchronize()
+    raw_ms = e0.elapsed_time(e1) / args.steps
     # spot check: 64 rows against the definition
     pick = np.random.Generator(np.random.PCG64(1)).integers(0, rows, 64)
     o = out.cpu().numpy()
@@ -411,7 +429,6 @@ def bench_ragged(args):
         worst = max(worst, float(np.max(np.abs(o[b:e] - ref) / ref)))
     # one plain call per row, from the host, on the same stream
     pctx = api.Context()
-    lib = L.lib()
     s = stream.cuda_stream
     ip, op = inp.data_ptr(), out.data_ptr()
     bounds = [(int(offs[r]), int(offs[r + 1] - offs[r])) for r in range(rows)]
@@ -440,6 +457,10 @@ def bench_ragged(args):
                                "(seed 4), LogNormal(0,1) FP32, int64 CSR offsets, hipGraph replay; "
                                "model 12 B/element", "rows": rows, "elements": total,
                    "batch_params": ctx.get_batch_params()},
+        "per_step": per_step,
+        "basic_c_form": {"ms": round(raw_ms, 5), "vs_value_pct": round(100.0 * (raw_ms - ms) / ms, 2),
+                         "what": "normalize_batched(out, in, offsets, rows): default context and parameters, "
+                                 "null stream, offsets[rows] read back per call"},
         "per_row_launch": {"ms": round(per_row_ms, 4), "GBps": round(12.0 * total / (per_row_ms * 1e-3) / 1e9, 2),
                            "speedup_of_batched": round(per_row_ms / ms, 3)},
         "sample_max_rel_err": worst,

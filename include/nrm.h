@@ -133,7 +133,9 @@ typedef struct {
   int32_t short_regs;  /* 16-byte vectors per thread held in registers by a single-pass row:
                           1, 2, 4 or 8; rows with n <= block * short_regs * 4 take one pass
                           (one read, one write) */
-  int32_t graph;       /* 1: capture the launch sequence once in a hipGraph and replay it */
+  int32_t graph;       /* 1 (default): capture the launch sequence once per staging buffer in a
+                          hipGraph and replay it (captured on a stream of the library's own, on
+                          first use); 0: launch the kernels one by one */
   int32_t map_block;   /* threads per block of the divide phase: 64..1024, multiple of 64 */
   int32_t map_grid;    /* persistent blocks G of the divide phase: the long rows' concatenation is
                           cut into about G * m equal chunks of at most about one tile each, so

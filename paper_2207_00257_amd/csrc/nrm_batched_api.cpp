@@ -46,7 +46,7 @@ nrm_batch_params default_batch_params() {
   p.grid = 2048;
   p.tile_log2 = 15;
   p.short_regs = 4;
-  p.graph = 0;
+  p.graph = 1;  // replay captured graphs (one per staging buffer and reduction kind)
   p.map_block = 1024;
   p.map_grid = 1024;
   p.keep_mib = 256;

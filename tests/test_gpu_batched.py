@@ -62,6 +62,7 @@ def test_mixed_lengths_short_and_tiled(accum):
 
 BATCH_PARAMS = [
     dict(),
+    dict(graph=0),                      # the kernels launched one by one
     dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7),
     dict(block=1024, unroll=8, map_unroll=8, short_regs=8, tile_log2=20, grid=256),
     dict(block=512, unroll=2, map_unroll=4, short_regs=2, tile_log2=14, grid=3000),
@@ -344,7 +345,8 @@ def test_random_batches_match_oracle(seed):
     one element, the single-pass limit, whole tiles and one element either
     side), random launch shapes, graph replay or not."""
     rng = np.random.default_rng(1000 + seed)
-    shapes = [dict(), dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7, resident_segments=0),
+    shapes = [dict(), dict(block=64, unroll=1, map_unroll=1, short_regs=1, tile_log2=10, grid=7, resident_segments=0,
+                           graph=0),
               dict(block=512, unroll=2, short_regs=2, tile_log2=13, map_grid=33, resident_segments=2),
               dict(graph=1, tile_log2=12, resident_segments=5, resident_grid=9),
               dict(keep_mib=0, map_block=256, map_unroll=8, grid=100, resident_segments=0),

@@ -119,10 +119,6 @@ typedef struct {
                            (all n / 4096 blocks must be able to run at once: one per CU). Up to 64
                            blocks every block reads every block's sum; beyond, the last block to
                            arrive publishes the total. Default 2^18; 0: never */
-  int32_t fused_log2;   /* 0, or 20..40: n >= 2^fused_log2 (when out is aligned like in) runs as
-                           one cooperative kernel: the reduce, an exchange of block sums, then the
-                           map, each block keeping the first chunk it summed (2^13 16-byte vectors)
-                           in registers for the map (a read fewer). 0: never */
 } nrm_params;
 
 /* Launch parameters of the ragged batched path. Start from

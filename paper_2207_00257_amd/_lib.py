@@ -40,7 +40,6 @@ class NrmParams(ctypes.Structure):
         ("fused_combine", ctypes.c_int32),
         ("small_n", ctypes.c_int32),
         ("resident_n", ctypes.c_int32),
-        ("fused_log2", ctypes.c_int32),
     ]
 
 

@@ -86,7 +86,6 @@ int check_params(const nrm_params& p) {
   if (!ok_f(p.fused_combine)) return fail(NRM_EINVAL, "fused_combine must be 0 or 1");
   if (p.small_n < 0 || p.small_n > (1 << 16)) return fail(NRM_EINVAL, "small_n must be 0..2^16");
   if (p.resident_n < 0 || p.resident_n > (1 << 20)) return fail(NRM_EINVAL, "resident_n must be 0..2^20");
-  if (p.fused_log2 != 0 && (p.fused_log2 < 20 || p.fused_log2 > 40)) return fail(NRM_EINVAL, "fused_log2 must be 0 or 20..40");
   return NRM_OK;
 }
 
@@ -146,26 +145,6 @@ int ensure_partials(nrm_ctx* c, int64_t entries) {
 
 
 bool valid_dtype(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
-
-// The one-kernel form's workspace, allocated on its first use.
-int ensure_fused(nrm_ctx* c) {
-  if (c->fused_mem) return NRM_OK;
-  void* m = nullptr;
-  hipError_t e = hipMalloc(&m, nrm::FUSED_WS_BYTES);
-  if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("fused workspace hipMalloc: ") + hipGetErrorString(e));
-  e = hipMemset(m, 0, nrm::FUSED_WS_BYTES);
-  if (e != hipSuccess) {
-    (void)hipFree(m);
-    return hip_fail(e, "hipMemset");
-  }
-  char* b = static_cast<char*>(m);
-  const size_t small = 16 * nrm::FUSED_MAX_BLOCKS;
-  c->fused = nrm::FusedWs{reinterpret_cast<unsigned long long*>(b), reinterpret_cast<unsigned long long*>(b + small),
-                          reinterpret_cast<unsigned*>(b + small + 64), reinterpret_cast<unsigned*>(b + small + 68),
-                          reinterpret_cast<unsigned long long*>(b + small + 128), c->dev_error, c->sum};
-  c->fused_mem = m;
-  return NRM_OK;
-}
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -456,7 +435,6 @@ int nrm_destroy(nrm_ctx* c) {
   nrm::batch_free(c);
   if (c->partials) (void)hipFree(c->partials);
   if (c->ticket) (void)hipFree(c->ticket);
-  if (c->fused_mem) (void)hipFree(c->fused_mem);
   delete c;
   return NRM_OK;
 }
@@ -594,24 +572,6 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
   int st = nrm::plan_plain(q, out, out_dtype, in, in_dtype, n, accum, &plan);
   if (st != NRM_OK) return st;
   DeviceGuard g(c->device);
-  if (q.fused_log2 && n >= (int64_t(1) << q.fused_log2) && plan.vector_map) {
-    st = ensure_fused(c);
-    if (st != NRM_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipEvent_t* ev = nullptr;
-    if (c->timing) {
-      ev = &c->events[3 * (c->timed_calls % kTimingRing)];
-      c->timed_calls++;
-      (void)hipEventRecord(ev[0], s);
-    }
-    hipError_t e = nrm::launch_fused(plan, c->fused, 0, s);
-    if (e != hipSuccess) return hip_fail(e, "one-kernel normalize cooperative launch");
-    if (ev) {
-      (void)hipEventRecord(ev[1], s);
-      (void)hipEventRecord(ev[2], s);
-    }
-    return NRM_OK;
-  }
   st = ensure_partials(c, plan.grid);
   if (st != NRM_OK) return st;
   nrm::PlainWorkspace ws{c->partials, c->ticket, c->sum};

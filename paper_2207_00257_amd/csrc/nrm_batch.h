@@ -43,7 +43,7 @@ enum {
   NRM_DEVERR_ROW = 2,       // a table row with n < 0, bad dtype, NULL pointer, or too many tiles
   NRM_DEVERR_CAPACITY = 4,  // more rows or work items than the workspace holds
   NRM_DEVERR_TARGET = 8,    // NLL loss: a target outside [0, C) that is not ignore_index
-  NRM_DEVERR_STALL = 16,    // an exchange of sums between blocks (resident rows, the one-kernel form) did not complete within the spin limit
+  NRM_DEVERR_STALL = 16,    // a resident row's segments did not all arrive within the spin limit
 };
 
 constexpr int64_t MAX_ROW_TILES = 65536;  // partials the per-row combine merges

@@ -102,8 +102,6 @@ struct nrm_ctx {
   int* dev_error = nullptr;  // device error word of the non-batched kernels (NLL targets)
   float* sum = nullptr;      // 2 floats
   nrm::PlainResidentWs res{};  // the single-launch mid-size form's exchange
-  nrm::FusedWs fused{};        // the one-kernel large form's workspace (fused_mem, on first use)
-  void* fused_mem = nullptr;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // 3 per recorded call

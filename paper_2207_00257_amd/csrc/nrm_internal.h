@@ -129,25 +129,6 @@ int64_t plain_resident_capacity();
 hipError_t launch_plain_resident(const void* in, int in_dt, void* out, int out_dt, int64_t n, int acc,
                                  const PlainResidentWs& w, hipStream_t s);
 
-// normalize in one cooperative kernel for large n (nrm_fused.hip), at most
-// FUSED_MAX_BLOCKS blocks. Workspace, zero-initialized: the blocks' tagged
-// sums (2 words each), the tagged total, the arrival and done counters (0
-// between calls), the call number; the error word and the sum for
-// nrm_get_last_sum are the context's.
-constexpr int64_t FUSED_MAX_BLOCKS = 1024;
-struct FusedWs {
-  unsigned long long* slots;  // 2 x FUSED_MAX_BLOCKS
-  unsigned long long* total;  // 2
-  unsigned* arrivals;
-  unsigned* done;
-  unsigned long long* call;
-  int* error;
-  float* sum_out;
-};
-constexpr size_t FUSED_WS_BYTES = 16 * FUSED_MAX_BLOCKS + 256;
-// max_grid > 0 caps the grid (else: every block the device holds at once).
-hipError_t launch_fused(const PlainPlan& p, const FusedWs& w, int64_t max_grid, hipStream_t s);
-
 // The Fig. 9-shaped tile kernel in one of its three forms (nrm_layerforward.hip).
 hipError_t launch_layerforward(int form, float* hidden, const float* input, float* output, int64_t rows,
                                hipStream_t s);

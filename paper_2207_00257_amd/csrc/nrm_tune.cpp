@@ -214,7 +214,7 @@ bool set_field(nrm_params* p, const std::string& k, int64_t v) {
       {"map_nt", &nrm_params::map_nt},         {"reverse_map", &nrm_params::reverse_map},
       {"reduce_keep_mib", &nrm_params::reduce_keep_mib}, {"tile_log2", &nrm_params::tile_log2},
       {"fused_combine", &nrm_params::fused_combine},     {"small_n", &nrm_params::small_n},
-      {"resident_n", &nrm_params::resident_n},        {"fused_log2", &nrm_params::fused_log2},
+      {"resident_n", &nrm_params::resident_n},
   };
   for (const F& f : fields)
     if (k == f.name) {

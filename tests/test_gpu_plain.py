@@ -53,7 +53,7 @@ SMALL_CTX = {}
 
 
 MODES = {"default": {}, "two_kernels": dict(small_n=0, resident_n=0), "resident_2p20": dict(small_n=0, resident_n=1 << 20),
-         "small": dict(small_n=65536, resident_n=0), "one_kernel_2p20": dict(resident_n=0, fused_log2=20)}
+         "small": dict(small_n=65536, resident_n=0)}
 
 
 @pytest.mark.parametrize("mode", list(MODES))
@@ -65,8 +65,7 @@ def test_sizes_and_ragged_tails(n, mode):
     elements, each held in registers across the exchange of sums; above: two
     kernels), with both one-launch forms off (two kernels), with the
     resident form up to 2^20 (the single published total beyond 64
-    segments), with the one-block form (n <= 2^16), and with the one-kernel
-    large form from 2^20 on."""
+    segments), and with the one-block form (n <= 2^16)."""
     if mode not in SMALL_CTX:
         SMALL_CTX[mode] = api.Context(**MODES[mode])
     x = synth.lognormal_f32(n, 10 + n % 97, 1.0)
@@ -350,8 +349,7 @@ def test_parameter_validation():
                 dict(layout=3), dict(map_layout=-1), dict(max_height=23), dict(max_height=41),
                 dict(reverse_map=2), dict(map_nt=-1), dict(tile_log2=9), dict(tile_log2=23),
                 dict(fused_combine=2), dict(small_n=-1), dict(reduce_keep_mib=-1), dict(reduce_keep_mib=4097),
-                dict(resident_n=-1), dict(resident_n=(1 << 20) + 1), dict(fused_log2=19), dict(fused_log2=41),
-                dict(fused_log2=-1)):
+                dict(resident_n=-1), dict(resident_n=(1 << 20) + 1)):
         with pytest.raises(L.NrmError):
             ctx.set_params(**bad)
         assert ctx.get_params() == good, bad
@@ -518,87 +516,3 @@ def test_resident_plain_matches_alternating_contexts_and_in_place():
     assert np.array_equal(t.cpu().numpy().view(np.uint32), outs[0].view(np.uint32)), "in place differs"
     a.close()
     b.close()
-
-
-FUSED_SIZES = [1 << 20, (1 << 20) + 1, 5 * 65536 + 12345 + (1 << 20), 16 * 65536 + 32768 + 3, 37 * 65536 - 1,
-               3000017]
-
-
-@pytest.mark.parametrize("accum", ["f32", "kahan"])
-def test_one_kernel_large_form(accum):
-    """The one-kernel form for large n (chunks of 2^14 16-byte vectors summed
-    into tagged chunk sums; the last block to arrive merges them in chunk
-    order and publishes the total; each block divides the half chunk it kept
-    in registers, then takes chunks from the end down): sizes that end on,
-    just past, and inside the held half of a chunk, FP32 / BF16 / FP16, three
-    calls in a row with the same bits (the merge order depends on n only),
-    an unaligned start, and the sum it leaves for nrm_get_last_sum."""
-    ctx = api.Context(resident_n=0, fused_log2=20)
-    for n in FUSED_SIZES:
-        x = synth.lognormal_f32(n, 400 + n % 83, 1.0)
-        ref = oracle.normalize(x)
-        first = None
-        for _ in range(3):
-            got = run_f32(x, ctx, accum=accum)
-            assert_f32_close(got, ref, what="one kernel n=%d %s" % (n, accum))
-            if first is None:
-                first = got
-            assert np.array_equal(got.view(np.uint32), first.view(np.uint32)), "repeat differs at n=%d" % n
-        s = ctypes.c_float()
-        L.check(L.lib().nrm_get_last_sum(ctx.handle, None, ctypes.byref(s)), "nrm_get_last_sum")
-        S = float(np.sum(x, dtype=np.float64))
-        assert abs(s.value - S) <= 4e-6 * S, (n, s.value, S)
-    # unaligned start: in and out at the same offset of one element
-    n = (1 << 21) + 77
-    x = synth.lognormal_f32(n + 1, 411, 1.0)
-    inp = gpu(x)
-    out = torch.zeros_like(inp)
-    L.check(L.lib().nrm_normalize_ex(ctx.handle, ctypes.c_void_p(out.data_ptr() + 4), L.NRM_F32,
-                                     ctypes.c_void_p(inp.data_ptr() + 4), L.NRM_F32, n,
-                                     L.NRM_ACC_KAHAN if accum == "kahan" else L.NRM_ACC_F32, None),
-            "nrm_normalize_ex")
-    torch.cuda.synchronize()
-    got = out.cpu().numpy()
-    assert got[0] == 0.0
-    assert_f32_close(got[1:], oracle.normalize(x[1:]), what="one kernel unaligned")
-    bits = synth.lognormal_bf16((1 << 22) + 9, 412, 2.0)
-    inp = gpu(bits.view(np.int16)).view(torch.bfloat16)
-    ref = oracle.normalize(bits, "bf16")
-    out = torch.empty_like(inp)
-    api.normalize(out, inp, accum=accum, ctx=ctx)
-    out32 = torch.empty(inp.numel(), dtype=torch.float32, device=DEV)
-    api.normalize(out32, inp, accum=accum, ctx=ctx)
-    torch.cuda.synchronize()
-    got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
-    assert_within_ulp(got, ref, ulp_bf16, what="one kernel bf16")
-    assert_f32_close(out32.cpu().numpy(), ref, what="one kernel bf16->f32")
-    h = synth.f32_to_f16_bits(synth.lognormal_f32((1 << 21) + 3, 413, 1.0))
-    inp = gpu(h.view(np.int16)).view(torch.float16)
-    out = torch.empty_like(inp)
-    api.normalize(out, inp, accum=accum, ctx=ctx)
-    torch.cuda.synchronize()
-    assert_within_ulp(out.cpu().numpy().astype(np.float64), oracle.normalize(h, "f16"), ulp_f16, what="one kernel f16")
-    assert ctx.device_error() == L.NRM_OK
-    ctx.close()
-
-
-def test_one_kernel_matches_two_kernels_within_bound_and_in_place():
-    """The one-kernel form against the two kernels on the same input (both
-    within the binary32 bound of the oracle; their sums may differ in the
-    last bits, since the trees differ), alternating between the two, and in
-    place."""
-    n = (1 << 22) + 4097
-    x = synth.uniform_f32(n, 420)
-    ref = oracle.normalize(x)
-    one, two = api.Context(resident_n=0, fused_log2=20), api.Context(resident_n=0)
-    outs = [run_f32(x, c) for c in (one, two, one, two, one)]
-    for o in outs:
-        assert_f32_close(o, ref, what="alternating one/two kernels")
-    assert np.array_equal(outs[0].view(np.uint32), outs[2].view(np.uint32))
-    assert np.array_equal(outs[0].view(np.uint32), outs[4].view(np.uint32))
-    t = gpu(x)
-    api.normalize(t, t, ctx=one)
-    torch.cuda.synchronize()
-    assert np.array_equal(t.cpu().numpy().view(np.uint32), outs[0].view(np.uint32)), "in place differs"
-    one.close()
-    two.close()

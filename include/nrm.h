@@ -324,7 +324,8 @@ int nrm_normalize_batched_ex(nrm_ctx* ctx, void* out, int out_dtype, const void*
  * The invariant pair is a base-2 exponent k >= every in[j] log2(e) and the
  * sum s of exp2(in[j] log2(e) - k), each term in (0, 1], reduced with exact
  * power-of-two rescaling (no rounding added when the maximum moves); then
- * out[i] = exp2(in[i] log2(e) - k) / s and lse[r] = (k + log2 s) ln 2.
+ * out[i] = exp2(in[i] log2(e) - k) times the correctly rounded 1/s, and
+ * lse[r] = (k + log2 s) ln 2.
  *   in, out:  device binary32, `capacity` elements each (capacity < 0: read
  *             offsets[rows] back, which synchronizes `stream`); in == out
  *             computes in place, any other overlap is NRM_EOVERLAP.
@@ -333,7 +334,7 @@ int nrm_normalize_batched_ex(nrm_ctx* ctx, void* out, int out_dtype, const void*
  *   lse:      device float[rows], or NULL; empty rows get -inf. It must not
  *             overlap in or out.
  * Inputs are finite with |in| < 1e38. Accuracy (u = 2^-24): each output is
- * within a relative (2|x| + |x - m| + 4) u + e_s of the exact value (x its
+ * within a relative (2|x| + |x - m| + 7) u + e_s of the exact value (x its
  * input, m the row maximum), where e_s, the relative error of s, is at most
  * the same quantity averaged over the row with the softmax weights plus
  * gamma_62 (the summation tree's height bound); lse within e_s + 4 u (|lse| + 1).

@@ -92,10 +92,11 @@ __device__ __forceinline__ void store_quotients(char* out_seg, int64_t head, int
 
 // ---- the element-wise map of a row ---------------------------------------------------
 
-// normalize: x / S with the row's sum. softmax: exp2(x log2(e) - k) / s with
-// the row's exponent and scaled sum; the exponent argument is one fused
-// multiply-add (one rounding), the same expression as in the softmax chains'
-// terms. Both divisions are correctly rounded binary32.
+// normalize: x / S with the row's sum, a correctly rounded binary32 division.
+// softmax: exp2(x log2(e) - k) times 1/s (the correctly rounded reciprocal of
+// the row's scaled sum, formed once per block) with the row's exponent k; the
+// exponent argument is one fused multiply-add (one rounding), the same
+// expression as in the softmax chains' terms.
 template <int ACC>
 struct RowMap {
   float S;
@@ -107,12 +108,13 @@ struct RowMap {
 
 template <>
 struct RowMap<ACC_SOFTMAX> {
-  float k, s;
-  __device__ __forceinline__ static RowMap of(const Acc<ACC_SOFTMAX>& acc) { return RowMap{acc.k, acc.s}; }
-  __device__ __forceinline__ static RowMap of(const RowRes& r) { return RowMap{r.a, r.b}; }
+  float k, s, rs;
+  __device__ __forceinline__ static RowMap make(float k, float s) { return RowMap{k, s, 1.0f / s}; }
+  __device__ __forceinline__ static RowMap of(const Acc<ACC_SOFTMAX>& acc) { return make(acc.k, acc.s); }
+  __device__ __forceinline__ static RowMap of(const RowRes& r) { return make(r.a, r.b); }
   __device__ __forceinline__ RowRes result() const { return RowRes{k, s}; }
   __device__ __forceinline__ float operator()(float x) const {
-    return __builtin_amdgcn_exp2f(__builtin_fmaf(x, LOG2E_F, -k)) / s;
+    return __builtin_amdgcn_exp2f(__builtin_fmaf(x, LOG2E_F, -k)) * rs;
   }
   // log of the row's sum of exponentials: (k + log2 s) ln 2
   __device__ __forceinline__ float lse() const { return (k + __builtin_amdgcn_logf(s)) * LN2_F; }
@@ -513,6 +515,55 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   }
 }
 
+// Softmax chains of one thread that share one exponent k (every chain's k is
+// the same): raised once per loop iteration to cover the iteration's largest
+// element, the chains' sums rescaled exactly, so that each element then costs
+// one fused multiply-add, one exp2 and one addition instead of a compare and
+// a branch of its own.
+template <int NA>
+__device__ __forceinline__ void raise_shared(Acc<ACC_SOFTMAX> (&acc)[NA], float m) {
+  const float y = m * LOG2E_F;
+  if (y > acc[0].k) {
+    const float kn = __builtin_ceilf(y), d = acc[0].k - kn;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      acc[j].s = scale_pow2(acc[j].s, d);
+      acc[j].k = kn;
+    }
+  }
+}
+
+// A thread's held vectors r[k] (those with first + k * stride < nvec) into
+// softmax chains that share one exponent: one maximum over all of them, one
+// raise (raise_shared), then per element a fused multiply-add, an exp2 and an
+// addition.
+template <int DTI, int NA, int KB>
+__device__ __forceinline__ void softmax_add_held(Acc<ACC_SOFTMAX> (&acc)[NA], const u4 (&r)[KB], int64_t first,
+                                                 int64_t stride, int64_t nvec) {
+  constexpr int VEC = Elem<DTI>::VEC;
+  float m = -3.0e38f;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    if (first + (int64_t)k * stride < nvec) {
+      float x[VEC];
+      widen<DTI>(r[k], x);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) m = fmaxf(m, x[c]);
+    }
+  }
+  raise_shared<NA>(acc, m);
+  const float nk = -acc[0].k;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    if (first + (int64_t)k * stride < nvec) {
+      float x[VEC];
+      widen<DTI>(r[k], x);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].s += __builtin_amdgcn_exp2f(__builtin_fmaf(x[c], LOG2E_F, nk));
+    }
+  }
+}
+
 // ---- single-pass rows (held in registers) --------------------------------------------
 
 template <int DTI, int DTO, int ACC, int KB>
@@ -532,13 +583,17 @@ __device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, R
   Acc<ACC> acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k].zero();
+  if constexpr (ACC == ACC_SOFTMAX) {
+    softmax_add_held<DTI, NA, KB>(acc, r, t, B, g.nvec);
+  } else {
 #pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    if (t + (int64_t)k * B < g.nvec) {
-      float x[VEC];
-      widen<DTI>(r[k], x);
+    for (int k = 0; k < KB; ++k) {
+      if (t + (int64_t)k * B < g.nvec) {
+        float x[VEC];
+        widen<DTI>(r[k], x);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(x[c]);
+        for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(x[c]);
+      }
     }
   }
   if (t < g.head) acc[0].add(load_one<DTI>(d.in, t));
@@ -574,24 +629,6 @@ __device__ __forceinline__ void single_pass(const RowDesc& d, Acc<ACC>* slots, R
 }
 
 // ---- tiles of long rows ------------------------------------------------------------
-
-// Softmax chains of one thread that share one exponent k (every chain's k is
-// the same): raised once per loop iteration to cover the iteration's largest
-// element, the chains' sums rescaled exactly, so that each element then costs
-// one fused multiply-add, one exp2 and one addition instead of a compare and
-// a branch of its own.
-template <int NA>
-__device__ __forceinline__ void raise_shared(Acc<ACC_SOFTMAX> (&acc)[NA], float m) {
-  const float y = m * LOG2E_F;
-  if (y > acc[0].k) {
-    const float kn = __builtin_ceilf(y), d = acc[0].k - kn;
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      acc[j].s = scale_pow2(acc[j].s, d);
-      acc[j].k = kn;
-    }
-  }
-}
 
 // Sum of elements [b, e) of a row; valid in thread 0. NT: non-temporal loads
 // (a temporal tile stays in the last-level cache for phase 2).
@@ -997,13 +1034,17 @@ __device__ __forceinline__ void resident_unit(const RowDesc& d, int seg, const R
   Acc<ACC> acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k].zero();
+  if constexpr (ACC == ACC_SOFTMAX) {
+    softmax_add_held<DTI, NA, KB>(acc, r, t, BLOCK, g.nvec);
+  } else {
 #pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    if (t + (int64_t)k * BLOCK < g.nvec) {
-      float xv[VEC];
-      widen<DTI>(r[k], xv);
+    for (int k = 0; k < KB; ++k) {
+      if (t + (int64_t)k * BLOCK < g.nvec) {
+        float xv[VEC];
+        widen<DTI>(r[k], xv);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(xv[c]);
+        for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(xv[c]);
+      }
     }
   }
   if (has_head) acc[0].add(xh);

@@ -5,7 +5,7 @@ seeded input, within the library's stated bound (include/nrm.h): with
 u = 2^-24, m the row maximum and w the exact softmax weights,
     d_i = (2|x_i| + |x_i - m| + 4) u          (one term exp2(x log2 e - k))
     e_s = sum_i w_i d_i + gamma_62            (the row's scaled sum)
-    |out_i - ref_i| <= (d_i + e_s + 2u) ref_i + 2^-125,
+    |out_i - ref_i| <= (d_i + e_s + 3u) ref_i + 2^-125,
     |lse - ref| <= e_s + 4u (|ref| + 1).
 """
 import numpy as np
@@ -48,7 +48,7 @@ def check(x, offs, got, got_lse, what=""):
         m = xr.max()
         d = (2 * np.abs(xr) + np.abs(xr - m) + 4) * U
         e_s = float(np.sum(rr * d)) + GAMMA62
-        tol = (d + e_s + 2 * U) * rr + 2.0 ** -125  # terms below 2^-126 flush; s >= 1/2
+        tol = (d + e_s + 3 * U) * rr + 2.0 ** -125  # terms below 2^-126 flush; s >= 1/2
         err = np.abs(got[b:e].astype(np.float64) - rr)
         bad = np.nonzero(err > tol)[0]
         assert bad.size == 0, "%s row %d (n=%d): element %d got %r ref %r tol %r" % (

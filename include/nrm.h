@@ -32,7 +32,11 @@
  *    ticket, the sum), held by a context; workspace grows on demand with
  *    hipMalloc, which is stream-synchronizing the first time a size is seen.
  *  - Calls that share a context must be ordered (same stream, or synchronized
- *    between streams): they share its workspace.
+ *    between streams): they share its workspace. A context's host-side state
+ *    is locked for the duration of each call, so host threads may share a
+ *    context (the default context of a device is shared by every thread that
+ *    passes ctx NULL); the ordering rule still applies to their device work
+ *    (the basic forms all use the null stream, which orders them).
  *  - Floating point: IEEE binary32 accumulation (or compensated binary32), a
  *    correctly rounded binary32 division, round-to-nearest-even conversions to
  *    BF16/FP16. No FP64 on the GPU. For non-negative inputs the relative error

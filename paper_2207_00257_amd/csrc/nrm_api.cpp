@@ -301,6 +301,7 @@ int nrm_nll_loss(nrm_ctx* c, float* out, float* total_weight, const float* logp,
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
+  nrm::CtxLock lk(c->mu);
   DeviceGuard g(c->device);
   nrm::NllPlan p;
   p.logp = logp;
@@ -447,6 +448,7 @@ int nrm_default_params(nrm_params* params) {
 
 int nrm_set_params(nrm_ctx* c, const nrm_params* params) {
   if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  nrm::CtxLock lk(c->mu);
   int st = check_params(*params);
   if (st != NRM_OK) return st;
   c->params = *params;
@@ -456,12 +458,14 @@ int nrm_set_params(nrm_ctx* c, const nrm_params* params) {
 
 int nrm_get_params(const nrm_ctx* c, nrm_params* params) {
   if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  nrm::CtxLock lk(c->mu);
   *params = c->params;
   return NRM_OK;
 }
 
 int nrm_set_timing(nrm_ctx* c, int enable) {
   if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  nrm::CtxLock lk(c->mu);
   if (enable && c->events.empty()) {
     DeviceGuard g(c->device);
     c->events.resize(3 * kTimingRing);
@@ -483,6 +487,7 @@ int nrm_set_timing(nrm_ctx* c, int enable) {
 
 int nrm_kernel_times(nrm_ctx* c, double* reduce_ms, double* map_ms, int64_t* calls) {
   if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  nrm::CtxLock lk(c->mu);
   double r = 0, m = 0;
   int64_t k = std::min<int64_t>(c->timed_calls, kTimingRing);
   for (int64_t i = 0; i < k; ++i) {
@@ -531,6 +536,7 @@ int nrm_normalize_ex(nrm_ctx* c, void* out, int out_dtype, const void* in, int i
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
+  nrm::CtxLock lk(c->mu);
   const nrm_params& q = call_params(c, in_dtype, out_dtype, accum, n);
   if (n <= q.small_n && n <= nrm::small_capacity(in_dtype)) {
     // one block, the input held in registers: one read, one write, one launch
@@ -597,6 +603,7 @@ int nrm_get_last_sum(nrm_ctx* c, void* stream, float* sum) {
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
+  nrm::CtxLock lk(c->mu);
   DeviceGuard g(c->device);
   hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
   if (e == hipSuccess) e = hipMemcpy(sum, c->sum, sizeof(float), hipMemcpyDeviceToHost);

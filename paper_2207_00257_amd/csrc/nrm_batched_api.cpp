@@ -372,6 +372,7 @@ int nrm_default_batch_params(nrm_batch_params* params) {
 
 int nrm_set_batch_params(nrm_ctx* c, const nrm_batch_params* params) {
   if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  nrm::CtxLock lk(c->mu);
   int st = check_batch_params(*params);
   if (st != NRM_OK) return st;
   if (std::memcmp(params, &c->bparams, sizeof(*params)) != 0) {
@@ -388,12 +389,14 @@ int nrm_set_batch_params(nrm_ctx* c, const nrm_batch_params* params) {
 
 int nrm_get_batch_params(const nrm_ctx* c, nrm_batch_params* params) {
   if (!c || !params) return fail(NRM_EINVAL, "NULL argument");
+  nrm::CtxLock lk(c->mu);
   *params = c->bparams;
   return NRM_OK;
 }
 
 int nrm_batch_reserve(nrm_ctx* c, int64_t max_rows, int64_t max_elems) {
   if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  nrm::CtxLock lk(c->mu);
   if (max_rows < 0 || max_elems < 0) return fail(NRM_EINVAL, "negative reservation");
   if (max_rows > INT32_MAX) return fail(NRM_EINVAL, "more than 2^31 - 1 rows");
   DeviceGuard g(c->device);
@@ -449,6 +452,7 @@ int run_csr(nrm_ctx* c, void* out, int out_dtype, const void* in, int in_dtype, 
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
+  nrm::CtxLock lk(c->mu);
   DeviceGuard g(c->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (capacity < 0) {
@@ -527,6 +531,7 @@ int nrm_normalize_rows(nrm_ctx* c, const nrm_row* rows, int64_t nrows, int accum
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
+  nrm::CtxLock lk(c->mu);
   if (longest > (int64_t(1) << c->bparams.tile_log2) * nrm::MAX_ROW_TILES)
     return fail(NRM_EINVAL, "row too long for the batched path's tile size");
   DeviceGuard g(c->device);
@@ -544,6 +549,7 @@ int nrm_get_device_error(nrm_ctx* c, void* stream) {
     int st = nrm::default_ctx(&c);
     if (st != NRM_OK) return st;
   }
+  nrm::CtxLock lk(c->mu);
   DeviceGuard g(c->device);
   hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -578,6 +584,7 @@ int nrm_get_device_error(nrm_ctx* c, void* stream) {
 
 int nrm_batch_times(nrm_ctx* c, double* total_ms, int64_t* calls) {
   if (!c) return fail(NRM_EINVAL, "ctx is NULL");
+  nrm::CtxLock lk(c->mu);
   BatchWorkspace& w = c->batch;
   double t = 0;
   int64_t k = std::min<int64_t>(w.timed_calls, nrm::kTimingRing);

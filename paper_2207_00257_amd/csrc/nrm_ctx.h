@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -87,6 +88,11 @@ struct BatchWorkspace {
 }  // namespace nrm
 
 struct nrm_ctx {
+  // held by every entry point for its host-side work on the context (the
+  // tuned-parameter map, workspace growth, the staging ring, the timing
+  // ring), so that host threads sharing a context, the default one included,
+  // do not race on them; recursive for entry points that call others
+  mutable std::recursive_mutex mu;
   nrm_batch_params bparams{};
   nrm::BatchWorkspace batch;
   int device = 0;
@@ -125,4 +131,7 @@ void batch_free(nrm_ctx* c);
 std::string device_arch(int device);
 // Overlay the tuning cache's entry for this call's key on *p; false if none.
 bool tuned_plain(const std::string& arch, int in_dt, int out_dt, int acc, int64_t n, nrm_params* p);
+// The context's lock for the rest of an entry point.
+using CtxLock = std::lock_guard<std::recursive_mutex>;
+
 }  // namespace nrm

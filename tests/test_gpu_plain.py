@@ -516,3 +516,37 @@ def test_resident_plain_matches_alternating_contexts_and_in_place():
     assert np.array_equal(t.cpu().numpy().view(np.uint32), outs[0].view(np.uint32)), "in place differs"
     a.close()
     b.close()
+
+
+def test_default_context_shared_by_host_threads():
+    """Four host threads call normalize through the default context (ctx NULL)
+    on the null stream at once, each with its own size (so each first call
+    adds its own tuning-cache key and may grow the shared workspace): the
+    context's host state is locked per call and the null stream orders the
+    device work, so every thread's result matches the oracle."""
+    import threading
+
+    sizes = [(1 << 19) + 3, (1 << 21) + 5, (1 << 22) + 7, (1 << 23) + 11]
+    xs = [synth.lognormal_f32(n, 500 + i, 1.0) for i, n in enumerate(sizes)]
+    ins = [gpu(x) for x in xs]
+    outs = [torch.empty_like(t) for t in ins]
+    errors = []
+    start = threading.Barrier(len(sizes))
+
+    def work(i):
+        try:
+            start.wait()
+            for _ in range(30):
+                api.normalize(outs[i], ins[i], stream=0)
+        except Exception as e:  # reported below, on the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(sizes))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for i, x in enumerate(xs):
+        assert_f32_close(outs[i].cpu().numpy(), oracle.normalize(x), what="thread %d n=%d" % (i, sizes[i]))

@@ -40,9 +40,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_bytes_elem_in: int, n: int):
+def measured_traffic(n_bytes_elem_in: int, n: int, params: dict):
     """HBM bytes per map launch from the committed rocprofv3 counter summary,
-    or None when absent or taken on a different kernel source."""
+    or None when absent, taken on a different kernel source, or taken with
+    other launch parameters than `params` (the call's)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -52,6 +53,11 @@ def measured_traffic(n_bytes_elem_in: int, n: int):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        if json.loads(vals.get("launch_params", "null")) != params:
+            return None
+    except ValueError:
         return None
     try:
         return float(vals["map_hbm_bytes_per_launch"])
@@ -307,7 +313,7 @@ def main():
     map_bytes = 8.0 * n
     map_gbs = map_bytes / (map_ms * 1e-3) / 1e9
     red_gbs = 4.0 * n / (red_ms * 1e-3) / 1e9
-    traffic = measured_traffic(4, n)
+    traffic = measured_traffic(4, n, ctx.get_params())
 
     # this machine's HBM ceilings over the same bytes, in the same run
     ceil = gpu_ceilings(inp, out, stream)

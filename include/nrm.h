@@ -423,6 +423,23 @@ typedef struct {
   int64_t max_batch_rows;    /* requests per batch */
   int64_t max_batch_elems;   /* elements per batch (a single larger request still runs alone) */
   nrm_batch_params batch_params;
+  int32_t device_queue;      /* 1: no launch per request: one persistent kernel polls a ring of
+                                published requests in pinned host memory and runs each one as it
+                                arrives (batching, graph, single_plain, spread, min_batch_rows and
+                                batch_params do not apply); each request of n <= 2^20 elements
+                                crosses HBM twice, a longer one three times; n <= 2^25; slots
+                                (1..64) bounds the requests in flight. 0: launches per batch or
+                                request as above */
+  int32_t dq_blocks;         /* device queue: persistent blocks of 512 threads (0: two per compute
+                                unit); at least 64 must be able to run at once */
+  int64_t dq_idle_us;        /* device queue: the kernel ends after this long (1..10^7 us) without a
+                                new request and is started again by the next one */
+  int64_t dq_plain_above;    /* device queue: a request of more elements than this (1..2^25) runs
+                                as the plain two-kernel call on its slot's own stream instead (the
+                                default, 2^20, keeps in the kernel the requests it holds in
+                                registers, which it serves fastest); 2^25: every request in the
+                                kernel. dq_blocks 0 then means one block per compute unit, which
+                                leaves room for those calls, and two when every request stays */
 } nrm_server_config;
 
 typedef struct {

@@ -110,6 +110,10 @@ class NrmServerConfig(ctypes.Structure):
         ("max_batch_rows", ctypes.c_int64),
         ("max_batch_elems", ctypes.c_int64),
         ("batch_params", NrmBatchParams),
+        ("device_queue", ctypes.c_int32),
+        ("dq_blocks", ctypes.c_int32),
+        ("dq_idle_us", ctypes.c_int64),
+        ("dq_plain_above", ctypes.c_int64),
     ]
 
 

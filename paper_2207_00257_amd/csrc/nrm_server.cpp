@@ -18,6 +18,14 @@
 // soon as a slot and memory free up; several slots run concurrently.
 // A replay thread can submit a whole trace at its scheduled arrival times
 // (open loop); latency is measured from the scheduled arrival.
+//
+// With the device queue (device_queue = 1) nothing is launched per request:
+// a slot holds one request, which the executor publishes into a ring in
+// pinned host memory; one persistent kernel (nrm_dq.h) picks it up, runs it,
+// and writes the slot's completion word into that memory, which query()
+// reads. The kernel ends after dq_idle_us without new requests and is
+// started again by the next one (or, should it have ended just as a request
+// was published, by the next query that finds it gone with work pending).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +40,7 @@
 #include <vector>
 
 #include "nrm_ctx.h"
+#include "nrm_dq.h"
 #include "nrm_sched.h"
 
 using nrm::DeviceGuard;
@@ -96,6 +105,179 @@ class HipExecutor : public nrm::Executor {
   std::string message() override { return msg; }
 };
 
+// The device queue's side of the scheduler: slot k's request lives in ring
+// entry k of the pinned block until it completes. A request longer than
+// plain_above runs instead as the plain call on slot k's own stream (plain).
+class DqExecutor : public nrm::Executor {
+ public:
+  HipExecutor plain;                // per slot: context, stream, event for the long requests
+  int64_t plain_above = int64_t(1) << 20;
+  std::vector<char> on_plain;       // per slot: its request runs as a plain call
+  nrm::DqHost* host = nullptr;      // pinned, coherent (host address)
+  nrm::DqHost* host_dev = nullptr;  // the same memory's device address
+  nrm::DqDev* dev = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ended = nullptr;       // recorded after each launch of the kernel
+  bool launched = false;
+  uint64_t epoch = 0;               // launches so far
+  uint64_t seq = 0;                 // requests published so far
+  int64_t outstanding = 0;          // published, not yet seen complete
+  int64_t last_check_ns = 0;        // last time query() looked at the kernel
+  int accum = NRM_ACC_F32;
+  int64_t blocks = 0;
+  unsigned long long idle_ticks = 0;
+  char* arena_base = nullptr;
+  std::vector<uint64_t> tag;        // per slot: the completion word its request will write
+  std::vector<char> empty;          // per slot: an n == 0 request, complete at once
+  std::string msg;
+
+  int allocate(int device, int slots, int64_t nblocks, int64_t idle_us) {
+    int rate_khz = 0;
+    hipError_t e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute (wall clock rate)");
+    idle_ticks = (unsigned long long)idle_us * (unsigned long long)(rate_khz > 0 ? rate_khz : 100000) / 1000ull;
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute (compute units)");
+    // one block per compute unit leaves room for the plain calls' blocks;
+    // with every request in the kernel, two
+    blocks = nblocks > 0 ? nblocks : (plain_above < nrm::DQ_MAX_N ? 1 : 2) * (int64_t)cus;
+    if (blocks < nrm::RES_MAX_SEGMENTS) return fail(NRM_EINVAL, "dq_blocks must be at least 64");
+    e = hipHostMalloc(reinterpret_cast<void**>(&host), sizeof(nrm::DqHost), hipHostMallocCoherent | hipHostMallocMapped);
+    if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("device queue hipHostMalloc: ") + hipGetErrorString(e));
+    std::memset(host, 0, sizeof(nrm::DqHost));
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&host_dev), host, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipHostGetDevicePointer");
+    e = hipMalloc(reinterpret_cast<void**>(&dev), sizeof(nrm::DqDev));
+    if (e != hipSuccess) return fail(NRM_ENOMEM, std::string("device queue hipMalloc: ") + hipGetErrorString(e));
+    e = hipMemset(dev, 0, sizeof(nrm::DqDev));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ended, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "device queue setup");
+    tag.assign((size_t)slots, 0);
+    empty.assign((size_t)slots, 0);
+    on_plain.assign((size_t)slots, 0);
+    plain.arena_base = arena_base;
+    plain.accum = accum;
+    plain.slots.resize((size_t)(plain_above < nrm::DQ_MAX_N ? slots : 0));
+    for (HipExecutor::SlotRes& sl : plain.slots) {
+      int st = nrm_create(&sl.ctx, device);
+      if (st == NRM_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
+        st = fail(NRM_EHIP, "hipStreamCreate");
+      if (st == NRM_OK && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+        st = fail(NRM_EHIP, "hipEventCreate");
+      if (st != NRM_OK) return st;
+    }
+    return NRM_OK;
+  }
+
+  // Start the kernel unless it is running.
+  int ensure_running() {
+    if (launched) {
+      hipError_t e = hipEventQuery(ended);
+      if (e == hipErrorNotReady) return NRM_OK;
+      if (e != hipSuccess) return hip_fail(e, "hipEventQuery (device queue)");
+    }
+    epoch += 1;
+    const nrm::DqArgs a{host_dev, dev, epoch, idle_ticks};
+    hipError_t e = nrm::launch_dq(a, accum, blocks, stream);
+    if (e == hipSuccess) e = hipEventRecord(ended, stream);
+    if (e != hipSuccess) return hip_fail(e, "device queue launch");
+    launched = true;
+    return NRM_OK;
+  }
+
+  int launch(int k, const nrm_row* rows, int64_t count, bool) override {
+    for (int64_t i = 0; i < count; ++i) {  // the scheduler gives this executor one row per slot
+      const nrm_row& r = rows[i];
+      if (r.n == 0) {
+        empty[(size_t)k] = 1;
+        continue;
+      }
+      if (r.n > plain_above) {
+        on_plain[(size_t)k] = 1;
+        const int st = plain.launch(k, &r, 1, false);
+        if (st != NRM_OK) msg = plain.message();
+        return st;
+      }
+      // four words, each with the request's tag above bit 48 (addresses and
+      // n are checked to fit below it when the request is submitted)
+      const uint64_t t = nrm::dq_pub_tag(seq) << nrm::DQ_TAG_SHIFT;
+      uint64_t* w = host->pub[seq % nrm::DQ_PUB].w;
+      const uint64_t words[4] = {reinterpret_cast<uint64_t>(r.in) | t,
+                                 reinterpret_cast<uint64_t>(arena_base + reinterpret_cast<int64_t>(r.out)) | t,
+                                 (uint64_t)r.n | t,
+                                 ((uint64_t)r.in_dtype | (uint64_t)r.out_dtype << 8 | (uint64_t)k << 16) | t};
+      for (int j = 0; j < 4; ++j) __atomic_store_n(w + j, words[j], __ATOMIC_RELEASE);
+      tag[(size_t)k] = nrm::dq_tag(seq);
+      seq += 1;
+      outstanding += 1;
+    }
+    const int st = ensure_running();
+    if (st != NRM_OK) msg = nrm_last_error();
+    return st;
+  }
+
+  int query(int k) override {
+    if (empty[(size_t)k]) {
+      empty[(size_t)k] = 0;
+      return 1;
+    }
+    if (on_plain[(size_t)k]) {
+      const int q = plain.query(k);
+      if (q != 0) on_plain[(size_t)k] = 0;
+      if (q < 0) msg = plain.message();
+      return q;
+    }
+    const uint64_t v = __atomic_load_n(&host->done[k], __ATOMIC_ACQUIRE);
+    if (v == tag[(size_t)k]) {
+      tag[(size_t)k] = 0;
+      outstanding -= 1;
+      if (__atomic_load_n(&host->stalled[k], __ATOMIC_ACQUIRE) == v) {
+        msg = "device queue: a wait for a request's partial sums gave up (its output is not valid)";
+        return NRM_EDEVICE;
+      }
+      return 1;
+    }
+    // A kernel that ended on its idle limit just as a request was published
+    // has not seen it: look (at most every 100 us) and start it again.
+    const int64_t t = now_ns();
+    if (t - last_check_ns > 100000) {
+      last_check_ns = t;
+      const int st = ensure_running();
+      if (st != NRM_OK) {
+        msg = nrm_last_error();
+        return st;
+      }
+    }
+    return 0;
+  }
+
+  std::string message() override { return msg; }
+
+  // End the kernel (it stops once nothing new is published) and free.
+  void shutdown() {
+    if (host) __atomic_store_n(&host->stop, 1, __ATOMIC_RELEASE);
+    if (stream) (void)hipStreamSynchronize(stream);  // teardown: the kernel's end is all that is awaited
+    for (HipExecutor::SlotRes& sl : plain.slots) {
+      if (sl.stream) (void)hipStreamSynchronize(sl.stream);  // teardown: errors were reported per request
+      if (sl.done) (void)hipEventDestroy(sl.done);
+      if (sl.stream) (void)hipStreamDestroy(sl.stream);
+      if (sl.ctx) nrm_destroy(sl.ctx);
+    }
+    plain.slots.clear();
+    if (ended) (void)hipEventDestroy(ended);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (dev) (void)hipFree(dev);
+    if (host) (void)hipHostFree(host);
+    ended = nullptr;
+    stream = nullptr;
+    dev = nullptr;
+    host = nullptr;
+  }
+};
+
 bool valid_dtype(int dt) { return dt == NRM_F32 || dt == NRM_BF16 || dt == NRM_F16; }
 
 int check_request(const nrm_request& r) {
@@ -111,6 +293,8 @@ struct nrm_server {
   nrm_server_config cfg{};
   int device = 0;
   HipExecutor ex;
+  DqExecutor dq;
+  char* arena_base = nullptr;
   nrm::Scheduler* core = nullptr;
   std::mutex wake_mu;                 // with cv: wakes the scheduler thread
   std::condition_variable cv;
@@ -158,6 +342,10 @@ int nrm_server_default_config(nrm_server_config* cfg) {
   cfg->spread = 1;
   cfg->idle_spin_us = 1000;
   cfg->min_batch_rows = 4;  // the best balance of p50 and p99 over 20k-200k requests/s on MI355X
+  cfg->device_queue = 0;
+  cfg->dq_blocks = 0;
+  cfg->dq_idle_us = 100000;
+  cfg->dq_plain_above = int64_t(1) << 20;
   return NRM_OK;
 }
 
@@ -177,6 +365,15 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
   if (cfg->spread != 0 && cfg->spread != 1) return fail(NRM_EINVAL, "spread must be 0 or 1");
   if (cfg->idle_spin_us < 0 || cfg->idle_spin_us > 1000000) return fail(NRM_EINVAL, "idle_spin_us must be 0..10^6");
   if (cfg->min_batch_rows < 1 || cfg->min_batch_rows > (1 << 20)) return fail(NRM_EINVAL, "min_batch_rows must be 1..2^20");
+  if (cfg->device_queue != 0 && cfg->device_queue != 1) return fail(NRM_EINVAL, "device_queue must be 0 or 1");
+  if (cfg->device_queue) {
+    if (cfg->slots > nrm::DQ_RING) return fail(NRM_EINVAL, "device queue: slots must be 1..64");
+    if (cfg->dq_blocks != 0 && (cfg->dq_blocks < nrm::RES_MAX_SEGMENTS || cfg->dq_blocks > (1 << 16)))
+      return fail(NRM_EINVAL, "dq_blocks must be 0 or 64..65536");
+    if (cfg->dq_idle_us < 1 || cfg->dq_idle_us > 10000000) return fail(NRM_EINVAL, "dq_idle_us must be 1..10^7");
+    if (cfg->dq_plain_above < 1 || cfg->dq_plain_above > nrm::DQ_MAX_N)
+      return fail(NRM_EINVAL, "dq_plain_above must be 1..2^25");
+  }
   if (device < 0) {
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -188,13 +385,21 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
   // outputs live in the arena; a request's output is at most two thirds of
   // its budget (FP32 out of a 2-byte input), which sizes the default arena
   const int64_t arena = cfg->arena_bytes > 0 ? cfg->arena_bytes : cfg->budget_bytes * 2 / 3 + (int64_t(1) << 20);
-  hipError_t e = hipMalloc(&s->ex.arena_base, (size_t)arena);
+  hipError_t e = hipMalloc(&s->arena_base, (size_t)arena);
   if (e != hipSuccess) {
     delete s;
     return fail(NRM_ENOMEM, std::string("server arena hipMalloc: ") + hipGetErrorString(e));
   }
+  s->ex.arena_base = s->arena_base;
   s->ex.accum = cfg->accum;
-  s->ex.slots.resize(cfg->slots);
+  s->dq.arena_base = s->arena_base;
+  if (cfg->device_queue && ((reinterpret_cast<uint64_t>(s->arena_base) + (uint64_t)arena) >> nrm::DQ_TAG_SHIFT) != 0) {
+    (void)hipFree(s->arena_base);
+    delete s;
+    return fail(NRM_EUNSUPPORTED, "device queue: output arena above 2^48");
+  }
+  s->dq.accum = cfg->accum;
+  s->dq.plain_above = cfg->dq_plain_above;
   nrm::SchedConfig sc;
   sc.slots = cfg->slots;
   sc.batching = cfg->batching != 0;
@@ -205,6 +410,21 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
   sc.max_batch_rows = cfg->max_batch_rows;
   sc.max_batch_elems = cfg->max_batch_elems;
   sc.budget_bytes = cfg->budget_bytes;
+  if (cfg->device_queue) {
+    // one request per slot, published to the kernel as soon as admitted
+    sc.batching = false;
+    sc.max_batch_rows = 1;
+    s->core = new nrm::Scheduler(sc, arena, &s->dq);
+    const int st = s->dq.allocate(device, cfg->slots, cfg->dq_blocks, cfg->dq_idle_us);
+    if (st != NRM_OK) {
+      nrm_server_destroy(s);
+      return st;
+    }
+    s->scheduler = std::thread([s] { s->run(); });
+    *out = s;
+    return NRM_OK;
+  }
+  s->ex.slots.resize(cfg->slots);
   s->core = new nrm::Scheduler(sc, arena, &s->ex);
   for (HipExecutor::SlotRes& sl : s->ex.slots) {
     int st = nrm_create(&sl.ctx, device);
@@ -237,6 +457,10 @@ int nrm_server_submit(nrm_server* s, const nrm_request* reqs, int64_t count) {
     if (st != NRM_OK) return st;
     if (nrm::Scheduler::need_of(reqs[i]) > s->cfg.budget_bytes)
       return fail(NRM_EINVAL, "request larger than the server's budget");
+    if (s->cfg.device_queue && reqs[i].n > nrm::DQ_MAX_N)
+      return fail(NRM_EINVAL, "device queue: request larger than 2^25 elements");
+    if (s->cfg.device_queue && (reinterpret_cast<uint64_t>(reqs[i].in) >> nrm::DQ_TAG_SHIFT) != 0)
+      return fail(NRM_EINVAL, "device queue: input address above 2^48");
   }
   const int64_t t = now_ns();
   std::vector<int64_t> arrival((size_t)count);
@@ -253,6 +477,12 @@ int nrm_server_replay(nrm_server* s, const nrm_request* reqs, int64_t count, int
     int st = check_request(reqs[i]);
     if (st != NRM_OK) return st;
     if (i > 0 && reqs[i].t_arrival_ns < reqs[i - 1].t_arrival_ns) return fail(NRM_EINVAL, "arrivals out of order");
+    if (nrm::Scheduler::need_of(reqs[i]) > s->cfg.budget_bytes)
+      return fail(NRM_EINVAL, "request larger than the server's budget");
+    if (s->cfg.device_queue && reqs[i].n > nrm::DQ_MAX_N)
+      return fail(NRM_EINVAL, "device queue: request larger than 2^25 elements");
+    if (s->cfg.device_queue && (reinterpret_cast<uint64_t>(reqs[i].in) >> nrm::DQ_TAG_SHIFT) != 0)
+      return fail(NRM_EINVAL, "device queue: input address above 2^48");
   }
   if (s->replayer.joinable()) s->replayer.join();
   std::vector<nrm_request> trace(reqs, reqs + count);
@@ -286,7 +516,7 @@ int nrm_server_replay(nrm_server* s, const nrm_request* reqs, int64_t count, int
 
 int nrm_server_poll(nrm_server* s, nrm_completion* out, int64_t max, int64_t* count) {
   if (!s || !count || max < 0 || (max > 0 && !out)) return fail(NRM_EINVAL, "bad arguments");
-  *count = s->core->take_done(out, max, reinterpret_cast<int64_t>(s->ex.arena_base));
+  *count = s->core->take_done(out, max, reinterpret_cast<int64_t>(s->arena_base));
   return NRM_OK;
 }
 
@@ -319,13 +549,14 @@ int nrm_server_destroy(nrm_server* s) {
   if (s->replayer.joinable()) s->replayer.join();
   if (s->scheduler.joinable()) s->scheduler.join();
   DeviceGuard g(s->device);
+  s->dq.shutdown();
   for (HipExecutor::SlotRes& sl : s->ex.slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);  // teardown: errors were reported per request
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.ctx) nrm_destroy(sl.ctx);
   }
-  if (s->ex.arena_base) (void)hipFree(s->ex.arena_base);
+  if (s->arena_base) (void)hipFree(s->arena_base);
   delete s->core;
   delete s;
   return NRM_OK;

@@ -24,7 +24,9 @@ class Server:
     def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, batching: bool = True, graph: bool = True,
                  hold_outputs: bool = False, max_batch_rows: int = 256, max_batch_elems: int = 1 << 27,
                  accum: str = "f32", batch_params: Optional[dict] = None, arena_bytes: int = 0, device: int = -1,
-                 single_plain: bool = True, spread: bool = True, idle_spin_us: int = 1000, min_batch_rows: int = 4):
+                 single_plain: bool = True, spread: bool = True, idle_spin_us: int = 1000, min_batch_rows: int = 4,
+                 device_queue: bool = False, dq_blocks: int = 0, dq_idle_us: int = 100000,
+                 dq_plain_above: int = 1 << 20):
         lib = L.lib()
         cfg = L.NrmServerConfig()
         L.check(lib.nrm_server_default_config(ctypes.byref(cfg)), "nrm_server_default_config")
@@ -41,6 +43,10 @@ class Server:
         cfg.spread = int(spread)
         cfg.idle_spin_us = int(idle_spin_us)
         cfg.min_batch_rows = int(min_batch_rows)
+        cfg.device_queue = int(device_queue)
+        cfg.dq_blocks = int(dq_blocks)
+        cfg.dq_idle_us = int(dq_idle_us)
+        cfg.dq_plain_above = int(dq_plain_above)
         if batch_params:
             lib.nrm_default_batch_params(ctypes.byref(cfg.batch_params))
             for k, v in batch_params.items():

@@ -154,9 +154,20 @@ def test_server_config_validation_before_any_hip_call(lib):
     for field, bad in (("slots", 0), ("slots", 65), ("budget_bytes", 0), ("max_batch_rows", 0),
                        ("max_batch_elems", 0), ("batching", 2), ("graph", 5), ("accum", 3),
                        ("hold_outputs", 7), ("use_batch_params", 2), ("single_plain", 2), ("spread", -1),
-                       ("idle_spin_us", -1), ("idle_spin_us", 1000001), ("min_batch_rows", 0)):
+                       ("idle_spin_us", -1), ("idle_spin_us", 1000001), ("min_batch_rows", 0),
+                       ("device_queue", 2)):
         c = L.NrmServerConfig()
         lib.nrm_server_default_config(ctypes.byref(c))
+        setattr(c, field, bad)
+        assert lib.nrm_server_create(ctypes.byref(h), 0, ctypes.byref(c)) == L.NRM_EINVAL, field
+    # the device queue's own limits (checked with device_queue = 1)
+    assert cfg.device_queue == 0 and cfg.dq_blocks == 0 and cfg.dq_idle_us == 100000
+    assert cfg.dq_plain_above == 1 << 20
+    for field, bad in (("dq_blocks", 63), ("dq_blocks", (1 << 16) + 1), ("dq_idle_us", 0),
+                       ("dq_idle_us", 10000001), ("dq_plain_above", 0), ("dq_plain_above", (1 << 25) + 1)):
+        c = L.NrmServerConfig()
+        lib.nrm_server_default_config(ctypes.byref(c))
+        c.device_queue = 1
         setattr(c, field, bad)
         assert lib.nrm_server_create(ctypes.byref(h), 0, ctypes.byref(c)) == L.NRM_EINVAL, field
     assert lib.nrm_server_create(None, 0, ctypes.byref(cfg)) == L.NRM_EINVAL

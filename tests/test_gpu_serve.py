@@ -156,3 +156,112 @@ def test_single_request_plain_policy_matches_oracle():
                              "grouped %d" % i)
         srv.release(i)
     srv.close()
+
+
+# ---- device queue (one persistent kernel, no launch per request) ------------------------
+
+
+def dq_requests(count, seed, hi=1 << 22):
+    """Sizes log-uniform in [1, hi] (requests above 2^20 take the two-pass
+    long form), 70 % FP32 / 30 % BF16."""
+    tr = serve.make_trace(rate=1e6, duration_s=count / 1e6 * 1.5, seed=seed, lo=1, hi=hi)
+    k = min(count, tr["n"].size)
+    return tr["n"][:k], tr["in_dt"][:k]
+
+
+# dq_plain_above: 2^20 (the default) runs the requests above 2^20 as plain
+# calls beside the kernel; 2^25 keeps every request in the kernel (the
+# two-pass long form)
+@pytest.mark.parametrize("accum,plain_above", [("f32", 1 << 20), ("kahan", 1 << 20), ("f32", 1 << 25),
+                                               ("kahan", 1 << 25)])
+def test_device_queue_mix_matches_oracle_and_alone(accum, plain_above):
+    ns, dts = dq_requests(150, 41)
+    # the boundaries of the two forms: one element, one resident segment, the
+    # largest resident request, the smallest long one, a ragged long one
+    edge = np.array([1, 1 << 14, 1 << 20, (1 << 20) + 1, 3 * (1 << 20) + 17], np.int64)
+    ns = np.concatenate([ns, edge])
+    dts = np.concatenate([dts, np.full(edge.size, L.NRM_F32, np.int32)])
+    pool = serve.InputPool(int(ns.max()), 42)
+    offs = pool.offsets(ns, 43)
+    offs[-1] += 5  # an input that does not start on a 16-byte boundary
+    ptrs = pool.pointers(dts, offs)
+    ids = np.arange(ns.size)
+    srv = serve.Server(slots=16, hold_outputs=True, device_queue=True, accum=accum, dq_plain_above=plain_above)
+    srv.submit(ids, ptrs, ns, dts, dts)
+    comps = srv.wait_all(ns.size, timeout_s=120)
+    assert sorted(c[0] for c in comps) == list(ids)
+    mixed = {}
+    for c in comps:
+        i = c[0]
+        assert c[5] == L.NRM_OK, "request %d status %d" % (i, c[5])
+        mixed[i] = read_out(c[1], int(ns[i]), int(dts[i]))
+        check_against_oracle(pool, int(ns[i]), int(dts[i]), int(offs[i]), mixed[i], "request %d (n=%d)" % (i, ns[i]))
+        srv.release(i)
+    assert srv.stats()["budget_used"] == 0
+    srv.close()
+    solo = serve.Server(slots=1, hold_outputs=True, device_queue=True, accum=accum, dq_plain_above=plain_above)
+    for i in list(range(0, ns.size, 9)) + list(range(ns.size - edge.size, ns.size)):
+        solo.submit([i], [ptrs[i]], [ns[i]], [dts[i]], [dts[i]])
+        (c,) = solo.wait_all(1, timeout_s=60)
+        alone = read_out(c[1], int(ns[i]), int(dts[i]))
+        assert np.array_equal(alone, mixed[i]), "request %d differs alone and in the mix" % i
+        solo.release(i)
+    solo.close()
+
+
+@pytest.mark.parametrize("plain_above", [1 << 20, 1 << 25])
+def test_device_queue_largest_request_and_empty(plain_above):
+    """n = 2^25 (in the kernel: 1024 parts, the largest request) and n = 0; a
+    request above 2^25 is rejected before it is queued."""
+    n = 1 << 25
+    pool = serve.InputPool(n, 44, span=n)
+    srv = serve.Server(slots=2, hold_outputs=True, device_queue=True, dq_plain_above=plain_above)
+    srv.submit([0, 1], [pool.f32.data_ptr(), pool.f32.data_ptr()], [n, 0], [L.NRM_F32] * 2, [L.NRM_F32] * 2)
+    comps = {c[0]: c for c in srv.wait_all(2, timeout_s=60)}
+    assert comps[0][5] == L.NRM_OK and comps[1][5] == L.NRM_OK
+    got = read_out(comps[0][1], n, L.NRM_F32)
+    idx = np.random.Generator(np.random.PCG64(45)).integers(0, n, 4096)
+    ref = oracle.normalize(pool.host_f32[:n])
+    assert_f32_close(got[idx], ref[idx], what="n=2^25 sampled")
+    np.testing.assert_allclose(float(np.sum(got, dtype=np.float64)), 1.0, rtol=1e-5)
+    with pytest.raises(L.NrmError):
+        srv.submit([2], [pool.f32.data_ptr()], [n + 1], [L.NRM_F32], [L.NRM_F32])
+    srv.close()
+
+
+def test_device_queue_restarts_after_idle_exit():
+    """With a 2 ms idle limit the kernel ends between bursts; the next request
+    starts it again, and results stay exact across the restarts."""
+    ns, dts = dq_requests(30, 46, hi=1 << 21)
+    pool = serve.InputPool(int(ns.max()), 47)
+    offs = pool.offsets(ns, 48)
+    ptrs = pool.pointers(dts, offs)
+    srv = serve.Server(slots=4, hold_outputs=True, device_queue=True, dq_idle_us=2000, dq_plain_above=1 << 25)
+    import time
+
+    for burst in range(3):
+        sel = list(range(burst * 10, burst * 10 + 10))
+        srv.submit(sel, ptrs[sel], ns[sel], dts[sel], dts[sel])
+        for c in srv.wait_all(len(sel), timeout_s=60):
+            i = c[0]
+            assert c[5] == L.NRM_OK
+            check_against_oracle(pool, int(ns[i]), int(dts[i]), int(offs[i]), read_out(c[1], int(ns[i]), int(dts[i])),
+                                 "burst %d request %d" % (burst, i))
+            srv.release(i)
+        time.sleep(0.02)  # ten idle limits: the kernel has ended
+    srv.close()
+
+
+def test_device_queue_open_loop_replay():
+    tr = serve.make_trace(rate=20000, duration_s=0.2, seed=49, hi=1 << 22)
+    k = tr["n"].size
+    pool = serve.InputPool(int(tr["n"].max()), 50)
+    offs = pool.offsets(tr["n"], 51)
+    ptrs = pool.pointers(tr["in_dt"], offs)
+    srv = serve.Server(slots=16, device_queue=True)
+    srv.replay(np.arange(k), ptrs, tr["n"], tr["in_dt"], tr["out_dt"], tr["t_ns"])
+    comps = srv.wait_all(k, timeout_s=60)
+    stats = serve.latency_stats(comps)
+    assert stats["requests"] == k and stats["failed"] == 0
+    assert all(c[4] >= c[2] for c in comps)
+    srv.close()

@@ -671,10 +671,14 @@ def bench_barriers(args):
 def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=10.0, pairs=3):
     """Serving workload: an open-loop Poisson trace (20k req/s; n log-uniform
     in [2^8, 2^24]; 70% FP32 / 30% BF16 requests, BF16 in and out) replayed
-    into the continuous-batching server with a 64 GiB HBM budget, and into
-    the same server in per-request mode (one plain call per request).
-    Latency runs from each request's scheduled arrival to the observed
-    completion; statistics exclude the first warm_s seconds."""
+    with a 64 GiB HBM budget into the continuous-batching server with its
+    device queue (one persistent kernel runs the requests of up to 2^20
+    elements as they arrive, the longer ones run as plain calls beside it),
+    and into the same server in per-request mode (one plain call per request,
+    4 slots); three interleaved pairs of 10 s runs. The launch-batched server
+    (one batched call per admitted group) and a rate sweep are reported
+    beside them. Latency runs from each request's scheduled arrival to the
+    observed completion; statistics exclude the first warm_s seconds."""
     import numpy as np
     import torch
 
@@ -687,46 +691,48 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=10.0, pairs=3):
     pool = serve.InputPool(1 << 24, 7)
     offs = pool.offsets(trace["n"], 8)
     ptrs = pool.pointers(trace["in_dt"], offs)
-    ids = np.arange(k)
     bp = tune.load_batch_params(args.params, workload="serve")
     warm_ns = int(warm_s * 1e9)
+    modes = {
+        "device_queue": dict(slots=16, device_queue=True),
+        "per_request_launch": dict(slots=4, batching=False, batch_params=bp),
+        "launch_batched": dict(slots=4, batching=True, batch_params=bp),
+    }
 
-    def run(batching, budget=64 << 30, tr=trace, pt=ptrs, n_req=None, warm_ns=warm_ns, spread=True, idle_spin_us=1000):
-        n_req = tr["n"].size if n_req is None else n_req
-        srv = serve.Server(slots=4, budget_bytes=budget, batching=batching, batch_params=bp, spread=spread,
-                           idle_spin_us=idle_spin_us)
-        t0 = srv.replay(np.arange(n_req), pt[:n_req], tr["n"][:n_req], tr["in_dt"][:n_req], tr["out_dt"][:n_req],
-                        tr["t_ns"][:n_req])
+    def run(mode, budget=64 << 30, tr=trace, pt=ptrs, warm_ns=warm_ns):
+        n_req = tr["n"].size
+        srv = serve.Server(budget_bytes=budget, **modes[mode])
+        t0 = srv.replay(np.arange(n_req), pt, tr["n"], tr["in_dt"], tr["out_dt"], tr["t_ns"])
         comps = srv.wait_all(n_req, timeout_s=600)
         st = srv.stats()
         srv.close()
         meas = [c for c in comps if c[2] - t0 >= warm_ns]
         out = serve.latency_stats(meas)
-        out["batches"] = st["batches"]
-        out["launches"] = st["launches"]
+        lat = np.array([c[4] - c[2] for c in meas], np.float64) / 1e3
+        ns = np.array([tr["n"][c[0]] for c in meas])
+        out["p50_us_n_le_2p20"] = float(np.median(lat[ns <= (1 << 20)]))
+        out["p50_us_n_gt_2p23"] = float(np.median(lat[ns > (1 << 23)]))
+        out["library_calls"] = st["launches"]
         return out
 
-    # batched and per-request runs of the same trace, interleaved pair by pair
+    # device queue and per-request runs of the same trace, interleaved pair by pair
     pair_runs = []
     for _ in range(pairs):
-        pair_runs.append({"batched": run(True), "per_request_launch": run(False)})
-    batched = pair_runs[0]["batched"]
+        pair_runs.append({"device_queue": run("device_queue"), "per_request_launch": run("per_request_launch")})
+    dq = pair_runs[0]["device_queue"]
     per_req = pair_runs[0]["per_request_launch"]
+    launch_batched = run("launch_batched")
     short = serve.make_trace(rate, 3.0, seed=8)
     spt = pool.pointers(short["in_dt"], pool.offsets(short["n"], 11))
-    grouped = run(True, tr=short, pt=spt, spread=False)
-    blocking = run(True, tr=short, pt=spt, idle_spin_us=0)
-    stress = run(True, tr=short, pt=spt, budget=256 << 20)
+    stress = run("device_queue", tr=short, pt=spt, budget=256 << 20)
     sweep = []
     for r in (50000.0, 100000.0, 200000.0):
         tr = serve.make_trace(r, 1.2, seed=9)
         pt = pool.pointers(tr["in_dt"], pool.offsets(tr["n"], 10))
-        res_b = run(True, tr=tr, pt=pt, warm_ns=int(0.2e9))
-        res_g = run(True, tr=tr, pt=pt, warm_ns=int(0.2e9), spread=False)
-        res_p = run(False, tr=tr, pt=pt, warm_ns=int(0.2e9))
-        sweep.append({"offered_req_per_s": r, "batched": res_b, "batched_no_spread": res_g, "per_request": res_p})
+        sweep.append({"offered_req_per_s": r,
+                      **{m: run(m, tr=tr, pt=pt, warm_ns=int(0.2e9)) for m in modes}})
     # results of a sample of requests, held and checked against the oracle
-    srv = serve.Server(slots=4, hold_outputs=True, batch_params=bp)
+    srv = serve.Server(hold_outputs=True, **modes["device_queue"])
     sel = np.arange(0, k, max(1, k // 64))[:64]
     srv.submit(sel, ptrs[sel], trace["n"][sel], trace["in_dt"][sel], trace["out_dt"][sel])
     worst, worst_bf16 = 0.0, 0.0
@@ -752,20 +758,20 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=10.0, pairs=3):
         srv.release(i)
     srv.close()
     line = {
-        "metric": METRIC, "value": round(batched["req_per_s"], 1), "unit": "req/s",
-        "p50_ms": round(batched["p50_ms"], 4), "p99_ms": round(batched["p99_ms"], 4),
+        "metric": METRIC, "value": round(dq["req_per_s"], 1), "unit": "req/s",
+        "p50_ms": round(dq["p50_ms"], 4), "p99_ms": round(dq["p99_ms"], 4),
         "n_gpus": 1, "steps": None, "warmup": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": "serving: Poisson %.0f req/s for %.0f s (+%.0f s warm-up), n log-uniform in "
                                "[2^8, 2^24], 70%% FP32 / 30%% BF16 (BF16 in and out), inputs device-resident, "
-                               "64 GiB HBM admission budget, 4 slots, open-loop replay, latency from scheduled "
-                               "arrival" % (rate, measure_s, warm_s), "requests": int(k)},
+                               "64 GiB HBM admission budget, open-loop replay, latency from scheduled arrival; "
+                               "continuous batching through the device queue (16 slots) against one plain call "
+                               "per request (4 slots)" % (rate, measure_s, warm_s), "requests": int(k)},
         "pairs": pair_runs,
-        "batched_p99_below_per_request_in_every_pair": all(
-            r["batched"]["p99_ms"] < r["per_request_launch"]["p99_ms"] for r in pair_runs),
-        "batched": batched, "per_request_launch": per_req, "batched_no_spread": grouped,
-        "batched_scheduler_blocks_when_idle": blocking,
-        "budget_256MiB": stress, "rate_sweep": sweep,
+        "device_queue_p99_below_per_request_in_every_pair": all(
+            r["device_queue"]["p99_ms"] < r["per_request_launch"]["p99_ms"] for r in pair_runs),
+        "device_queue": dq, "per_request_launch": per_req, "launch_batched": launch_batched,
+        "device_queue_budget_256MiB": stress, "rate_sweep": sweep,
         "sample_max_rel_err_f32": worst, "sample_max_err_bf16_ulps": worst_bf16,
     }
     print(json.dumps(line), flush=True)

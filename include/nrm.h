@@ -428,8 +428,12 @@ typedef struct {
                                 arrives (batching, graph, single_plain, spread, min_batch_rows and
                                 batch_params do not apply); each request of n <= 2^20 elements
                                 crosses HBM twice, a longer one three times; n <= 2^25; slots
-                                (1..64) bounds the requests in flight. 0: launches per batch or
-                                request as above */
+                                (1..64) bounds the requests in flight. While the kernel is
+                                resident, a kernel the caller queues on a stream that shares its
+                                hardware queue (the runtime spreads streams over a few such
+                                queues) waits until it ends, dq_idle_us after the last request;
+                                the server's own streams are probed apart from it at creation.
+                                0: launches per batch or request as above */
   int32_t dq_blocks;         /* device queue: persistent blocks of 512 threads (0: two per compute
                                 unit); at least 64 must be able to run at once */
   int64_t dq_idle_us;        /* device queue: the kernel ends after this long (1..10^7 us) without a

@@ -1969,6 +1969,13 @@ __global__ void __launch_bounds__(RES_BLOCK) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
+__global__ void dq_hold_kernel(const DqHost* h, unsigned long long max_ticks) {
+  const unsigned long long t0 = dq_now();
+  while (ld_sys(&h->hold) == 0 && dq_now() - t0 < max_ticks) __builtin_amdgcn_s_sleep(20);
+}
+
+__global__ void dq_touch_kernel() {}
+
 __global__ void dq_reset_kernel(DqDev* q) {
   st_agent(&q->next_unit, ld_agent(&q->pub_units));
   st_agent(&q->exit_epoch, 0ull);
@@ -2018,6 +2025,16 @@ hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
     case ACC_SOFTMAX: return launch_phases<ACC_SOFTMAX>(p, a, s);
     default: return launch_phases<NRM_ACC_F32>(p, a, s);
   }
+}
+
+hipError_t launch_dq_hold(const DqHost* host, unsigned long long max_ticks, hipStream_t s) {
+  hipLaunchKernelGGL(dq_hold_kernel, dim3(1), dim3(1), 0, s, host, max_ticks);
+  return hipGetLastError();
+}
+
+hipError_t launch_dq_touch(hipStream_t s) {
+  hipLaunchKernelGGL(dq_touch_kernel, dim3(1), dim3(1), 0, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_dq(const DqArgs& a, int acc, int64_t blocks, hipStream_t s) {

@@ -325,11 +325,12 @@ __device__ __forceinline__ void fetch(const Acc<ACC_SOFTMAX>* p, int64_t i, Acc<
   v.s = f32_bits((u32)(w >> 32));
 }
 
-// Block barrier for LDS traffic only. __syncthreads() is a workgroup-scope
-// release and acquire over all memory, so every wavefront first waits for its
-// own global stores to complete (vmcnt(0)) before the barrier; where the
-// block's threads communicate through LDS alone that wait is not needed, and
-// in a loop that streams stores it costs a memory round trip per barrier.
+// Block barrier for LDS traffic only: workgroup-scope fences on the local
+// address space around s_barrier, which is all the block's threads exchange
+// where it is used. (On gfx950 a block's wavefronts share one CU, and the
+// compiler lowers even __syncthreads()'s fences to waits on LDS operations:
+// neither barrier waits for global stores; code that needs them complete
+// waits for them itself.)
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();

@@ -60,7 +60,8 @@ struct DqPubLine {
 };
 struct DqHost {
   uint64_t stop;                // host: 1 = end once nothing new is published
-  uint64_t pad0[15];
+  uint64_t hold;                // host: 1 = end dq_hold (the stream probe at set-up)
+  uint64_t pad0[14];
   DqPubLine pub[DQ_PUB];        // host
   uint64_t done[DQ_RING];       // per slot: tag of the last request completed there (device)
   uint64_t stalled[DQ_RING];    // per slot: tag of a request whose wait gave up (device)
@@ -102,5 +103,12 @@ __host__ __device__ inline uint32_t dq_tag(uint64_t seq) { return (uint32_t)(seq
 // Reset the ticket counter to the copied units and clear the exit flag, then
 // run the persistent kernel with `blocks` blocks of RES_BLOCK threads.
 hipError_t launch_dq(const DqArgs& a, int acc, int64_t blocks, hipStream_t s);
+
+// Set-up probe of which streams share the kernel's hardware queue (a kernel
+// queued behind the persistent one on a shared queue would wait for it to
+// end): dq_hold keeps stream s busy until host->hold is set or max_ticks of
+// the device clock pass; dq_touch is an empty kernel.
+hipError_t launch_dq_hold(const DqHost* host, unsigned long long max_ticks, hipStream_t s);
+hipError_t launch_dq_touch(hipStream_t s);
 
 }  // namespace nrm

@@ -38,8 +38,9 @@
 //                        tile in registers and runs the tree there; a block
 //                        holds 16 tiles.
 // Every form performs the same roundings in the same order: their results are
-// bitwise equal. The barriers are __syncthreads(), whose workgroup-scope
-// release also waits for the wavefront's outstanding global stores.
+// bitwise equal. The barriers are __syncthreads(); on gfx950 their
+// workgroup-scope fences wait for LDS operations (a block's wavefronts share
+// one CU), not for global stores.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

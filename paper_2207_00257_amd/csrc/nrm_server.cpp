@@ -113,6 +113,7 @@ class DqExecutor : public nrm::Executor {
   HipExecutor plain;                // per slot: context, stream, event for the long requests
   int64_t plain_above = int64_t(1) << 20;
   std::vector<char> on_plain;       // per slot: its request runs as a plain call
+  std::vector<hipStream_t> set_aside;  // streams found to share the kernel's hardware queue
   nrm::DqHost* host = nullptr;      // pinned, coherent (host address)
   nrm::DqHost* host_dev = nullptr;  // the same memory's device address
   nrm::DqDev* dev = nullptr;
@@ -163,13 +164,60 @@ class DqExecutor : public nrm::Executor {
     plain.slots.resize((size_t)(plain_above < nrm::DQ_MAX_N ? slots : 0));
     for (HipExecutor::SlotRes& sl : plain.slots) {
       int st = nrm_create(&sl.ctx, device);
-      if (st == NRM_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
-        st = fail(NRM_EHIP, "hipStreamCreate");
+      if (st == NRM_OK) st = separate_stream(rate_khz, &sl.stream);
       if (st == NRM_OK && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
         st = fail(NRM_EHIP, "hipEventCreate");
       if (st != NRM_OK) return st;
     }
     return NRM_OK;
+  }
+
+  // A new stream whose hardware queue is not the kernel's. Streams share the
+  // runtime's few hardware queues, and a kernel queued behind the persistent
+  // one on a shared queue waits until it ends (up to dq_idle_us), so each
+  // candidate is tried while a bounded one-thread kernel holds the kernel's
+  // stream: a candidate whose empty kernel does not finish within 5 ms shares
+  // the queue and is set aside (kept, so that it keeps its queue).
+  int separate_stream(int rate_khz, hipStream_t* out) {
+    *out = nullptr;
+    const unsigned long long hold_ticks = 20000ull * (unsigned long long)(rate_khz > 0 ? rate_khz : 100000) / 1000ull;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fail(NRM_EHIP, "hipEventCreate");
+    int st = NRM_OK;
+    for (int attempt = 0; attempt < 16 && !*out && st == NRM_OK; ++attempt) {
+      hipStream_t cand = nullptr;
+      if (hipStreamCreateWithFlags(&cand, hipStreamNonBlocking) != hipSuccess) {
+        st = fail(NRM_EHIP, "hipStreamCreate");
+        break;
+      }
+      __atomic_store_n(&host->hold, 0, __ATOMIC_RELEASE);
+      hipError_t e = nrm::launch_dq_hold(host_dev, hold_ticks, stream);
+      if (e == hipSuccess) e = nrm::launch_dq_touch(cand);
+      if (e == hipSuccess) e = hipEventRecord(ev, cand);
+      bool alone = false;
+      const int64_t t0 = now_ns();
+      while (e == hipSuccess && now_ns() - t0 < 5000000) {
+        e = hipEventQuery(ev);
+        if (e == hipSuccess) {
+          alone = true;
+          break;
+        }
+        if (e == hipErrorNotReady) e = hipSuccess;
+      }
+      __atomic_store_n(&host->hold, 1, __ATOMIC_RELEASE);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(cand);
+      if (e != hipSuccess) {
+        (void)hipStreamDestroy(cand);
+        st = hip_fail(e, "device queue stream probe");
+        break;
+      }
+      if (alone) *out = cand;
+      else set_aside.push_back(cand);
+    }
+    (void)hipEventDestroy(ev);
+    if (st == NRM_OK && !*out) st = fail(NRM_EHIP, "device queue: no stream apart from the kernel's hardware queue");
+    return st;
   }
 
   // Start the kernel unless it is running.
@@ -267,6 +315,8 @@ class DqExecutor : public nrm::Executor {
       if (sl.ctx) nrm_destroy(sl.ctx);
     }
     plain.slots.clear();
+    for (hipStream_t st : set_aside) (void)hipStreamDestroy(st);
+    set_aside.clear();
     if (ended) (void)hipEventDestroy(ended);
     if (stream) (void)hipStreamDestroy(stream);
     if (dev) (void)hipFree(dev);

@@ -265,3 +265,32 @@ def test_device_queue_open_loop_replay():
     assert stats["requests"] == k and stats["failed"] == 0
     assert all(c[4] >= c[2] for c in comps)
     srv.close()
+
+
+def test_device_queue_plain_calls_do_not_wait_behind_the_kernel():
+    """Requests above dq_plain_above run as plain calls on the slots' own
+    streams while the persistent kernel stays resident (a 2 s idle limit): a
+    slot stream on the kernel's hardware queue would hold its call until the
+    kernel ended, so every call finishing well inside the idle limit shows
+    the set-up probe kept them apart."""
+    import time
+
+    n = (1 << 21) + 3
+    pool = serve.InputPool(n, 52, span=n + 1024)
+    srv = serve.Server(slots=16, hold_outputs=True, device_queue=True, dq_idle_us=2000000)
+    srv.submit([0], [pool.f32.data_ptr()], [1 << 12], [L.NRM_F32], [L.NRM_F32])  # the kernel is resident
+    srv.wait_all(1, timeout_s=30)
+    srv.release(0)
+    for burst in range(3):
+        ids = list(range(1 + 16 * burst, 17 + 16 * burst))
+        t0 = time.perf_counter()
+        srv.submit(ids, [pool.f32.data_ptr()] * 16, [n] * 16, [L.NRM_F32] * 16, [L.NRM_F32] * 16)
+        comps = srv.wait_all(16, timeout_s=30)
+        took = time.perf_counter() - t0
+        assert took < 0.3, "burst %d took %.3f s: a plain call waited behind the kernel" % (burst, took)
+        for c in comps:
+            assert c[5] == L.NRM_OK
+            srv.release(c[0])
+    got = read_out(comps[0][1], n, L.NRM_F32)
+    assert_f32_close(got, oracle.normalize(pool.host_f32[:n]), what="plain call beside the kernel")
+    srv.close()

@@ -726,7 +726,7 @@ def bench_serve(args, rate=20000.0, warm_s=1.0, measure_s=10.0, pairs=3):
     spt = pool.pointers(short["in_dt"], pool.offsets(short["n"], 11))
     stress = run("device_queue", tr=short, pt=spt, budget=256 << 20)
     sweep = []
-    for r in (50000.0, 100000.0, 200000.0):
+    for r in (10000.0, 50000.0, 100000.0, 200000.0, 400000.0):
         tr = serve.make_trace(r, 1.2, seed=9)
         pt = pool.pointers(tr["in_dt"], pool.offsets(tr["n"], 10))
         sweep.append({"offered_req_per_s": r,

@@ -294,3 +294,48 @@ def test_device_queue_plain_calls_do_not_wait_behind_the_kernel():
     got = read_out(comps[0][1], n, L.NRM_F32)
     assert_f32_close(got, oracle.normalize(pool.host_f32[:n]), what="plain call beside the kernel")
     srv.close()
+
+
+def test_device_queue_every_dtype_pair():
+    """All nine input/output dtype pairs through the kernel (resident
+    segments and, with every request in the kernel, the two-pass form)."""
+    pairs = [(i, o) for i in (L.NRM_F32, L.NRM_BF16, L.NRM_F16) for o in (L.NRM_F32, L.NRM_BF16, L.NRM_F16)]
+    ns = np.array([1000, (1 << 14) + 7, (1 << 20) - 3, (1 << 21) + 11], np.int64)
+    x = np.random.Generator(np.random.PCG64(53)).random(int(ns.max()) + 64).astype(np.float32) + np.float32(0.5)
+    dev = {L.NRM_F32: torch.from_numpy(x).cuda(),
+           L.NRM_BF16: torch.from_numpy(x).to(torch.bfloat16).cuda(),
+           L.NRM_F16: torch.from_numpy(x).to(torch.float16).cuda()}
+    # the oracle sees each request's stored values: binary32, or the 2-byte bit patterns
+    host = {L.NRM_F32: (x, "f32"), L.NRM_BF16: (dev[L.NRM_BF16].cpu().view(torch.int16).numpy().view(np.uint16), "bf16"),
+            L.NRM_F16: (dev[L.NRM_F16].cpu().view(torch.int16).numpy().view(np.uint16), "f16")}
+    srv = serve.Server(slots=8, hold_outputs=True, device_queue=True, dq_plain_above=1 << 25)
+    rid = 0
+    for di, do in pairs:
+        ids = list(range(rid, rid + ns.size))
+        rid += ns.size
+        srv.submit(ids, [dev[di].data_ptr()] * ns.size, ns, [di] * ns.size, [do] * ns.size)
+        for c in srv.wait_all(ns.size, timeout_s=60):
+            assert c[5] == L.NRM_OK
+            n = int(ns[c[0] - ids[0]])
+            esz = 4 if do == L.NRM_F32 else 2
+            raw = np.empty(n * esz, np.uint8)
+            assert loaded_hip().hipMemcpy(raw.ctypes.data, c[1], n * esz, 2) == 0
+            if do == L.NRM_F32:
+                got = raw.view(np.float32).astype(np.float64)
+            elif do == L.NRM_BF16:
+                got = bf16_bits_to_f64(raw.view(np.uint16))
+            else:
+                got = raw.view(np.float16).astype(np.float64)
+            ref = oracle.normalize(host[di][0][:n], host[di][1])
+            # binary32 out: 4e-6 relative; a 2-byte output: one ulp of its
+            # format (FP16 below 2^-14 is subnormal, with spacing 2^-24)
+            if do == L.NRM_F32:
+                tol = 4e-6 * ref
+            elif do == L.NRM_BF16:
+                tol = ulp_bf16(ref)
+            else:
+                tol = np.maximum(np.exp2(np.floor(np.log2(ref)) - 10), 2.0 ** -24)
+            bad = np.abs(got - ref) > tol
+            assert not bad.any(), "pair %d->%d n=%d: %d outputs outside the bound" % (di, do, n, int(bad.sum()))
+            srv.release(c[0])
+    srv.close()

@@ -431,8 +431,9 @@ typedef struct {
                                 (1..64) bounds the requests in flight. While the kernel is
                                 resident, a kernel the caller queues on a stream that shares its
                                 hardware queue (the runtime spreads streams over a few such
-                                queues) waits until it ends, dq_idle_us after the last request;
-                                the server's own streams are probed apart from it at creation.
+                                queues) waits until it ends: dq_slice_us, or dq_idle_us after the
+                                last request if sooner; the server's own streams are probed apart
+                                from it at creation.
                                 0: launches per batch or request as above */
   int32_t dq_blocks;         /* device queue: persistent blocks of 512 threads (0: two per compute
                                 unit); at least 64 must be able to run at once */
@@ -444,6 +445,10 @@ typedef struct {
                                 registers, which it serves fastest); 2^25: every request in the
                                 kernel. dq_blocks 0 then means one block per compute unit, which
                                 leaves room for those calls, and two when every request stays */
+  int64_t dq_slice_us;       /* device queue: each launch of the kernel ends after this long (0: no
+                                limit; 0..10^7 us, default 10^4) and the next request starts the
+                                next, so that a kernel queued behind it on its hardware queue waits
+                                at most about this long */
 } nrm_server_config;
 
 typedef struct {

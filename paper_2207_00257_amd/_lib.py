@@ -114,6 +114,7 @@ class NrmServerConfig(ctypes.Structure):
         ("dq_blocks", ctypes.c_int32),
         ("dq_idle_us", ctypes.c_int64),
         ("dq_plain_above", ctypes.c_int64),
+        ("dq_slice_us", ctypes.c_int64),
     ]
 
 

@@ -1602,15 +1602,21 @@ __device__ __forceinline__ void dq_claim(const DqArgs& a, DqClaim* c, DqCache* m
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the previous poller's counts
         unsigned long long stop = 0;
         if (dq_copy_new(a, &stop)) continue;
-        unsigned long long last = 0, ex = 0;
+        unsigned long long last = 0, ex = 0, born = 0;
         if (lane == 0) {
           last = ld_agent(&q->last_seen);
           ex = ld_agent(&q->exit_epoch);
+          born = ld_agent(&q->launched_at);
         }
         last = uniform_u64(last);
         ex = uniform_u64(ex);
+        born = uniform_u64(born);
         const unsigned long long now = dq_now();
-        end = stop != 0 || ex == a.epoch || (now > last && now - last > a.idle_ticks);
+        // idle for idle_ticks, or this launch has run its slice (so that a
+        // kernel queued behind it on its hardware queue waits at most that
+        // long; the host starts the next launch)
+        end = stop != 0 || ex == a.epoch || (now > last && now - last > a.idle_ticks) ||
+              (a.slice_ticks != 0 && now > born && now - born > a.slice_ticks);
         if (!end) __builtin_amdgcn_s_sleep(2);
       } else if ((spin & 7) == 7) {
         unsigned long long ex = lane == 0 ? ld_agent(&q->exit_epoch) : 0;
@@ -1979,7 +1985,9 @@ __global__ void dq_touch_kernel() {}
 __global__ void dq_reset_kernel(DqDev* q) {
   st_agent(&q->next_unit, ld_agent(&q->pub_units));
   st_agent(&q->exit_epoch, 0ull);
-  st_agent(&q->last_seen, dq_now());
+  const unsigned long long now = dq_now();
+  st_agent(&q->last_seen, now);
+  st_agent(&q->launched_at, now);
 }
 
 }  // namespace

@@ -80,7 +80,8 @@ struct DqDev {
   unsigned long long stall;       // tag of the last request whose wait gave up
   int error;                      // NRM_DEVERR_* bits
   int pad;
-  unsigned long long pad1[9];
+  unsigned long long launched_at; // device clock when this launch began
+  unsigned long long pad1[8];
   DqReq ring[DQ_RING];                    // by slot, copied from the host's
   unsigned long long key[DQ_RING];        // ring[i].key, also read alone in the lookup
   unsigned arrivals[DQ_RING];             // parts or segments that have published (0 between requests)
@@ -94,6 +95,7 @@ struct DqArgs {
   DqDev* dev;
   unsigned long long epoch; // this launch's number (>= 1)
   unsigned long long idle_ticks;  // device clock ticks without new requests before the kernel ends
+  unsigned long long slice_ticks; // device clock ticks after which the launch ends (0: none)
 };
 
 // The tag of request seq in the exchange words (never 0, the value of a word

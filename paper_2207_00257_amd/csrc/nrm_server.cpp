@@ -127,16 +127,18 @@ class DqExecutor : public nrm::Executor {
   int accum = NRM_ACC_F32;
   int64_t blocks = 0;
   unsigned long long idle_ticks = 0;
+  unsigned long long slice_ticks = 0;
   char* arena_base = nullptr;
   std::vector<uint64_t> tag;        // per slot: the completion word its request will write
   std::vector<char> empty;          // per slot: an n == 0 request, complete at once
   std::string msg;
 
-  int allocate(int device, int slots, int64_t nblocks, int64_t idle_us) {
+  int allocate(int device, int slots, int64_t nblocks, int64_t idle_us, int64_t slice_us) {
     int rate_khz = 0;
     hipError_t e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute (wall clock rate)");
     idle_ticks = (unsigned long long)idle_us * (unsigned long long)(rate_khz > 0 ? rate_khz : 100000) / 1000ull;
+    slice_ticks = (unsigned long long)slice_us * (unsigned long long)(rate_khz > 0 ? rate_khz : 100000) / 1000ull;
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute (compute units)");
@@ -228,7 +230,7 @@ class DqExecutor : public nrm::Executor {
       if (e != hipSuccess) return hip_fail(e, "hipEventQuery (device queue)");
     }
     epoch += 1;
-    const nrm::DqArgs a{host_dev, dev, epoch, idle_ticks};
+    const nrm::DqArgs a{host_dev, dev, epoch, idle_ticks, slice_ticks};
     hipError_t e = nrm::launch_dq(a, accum, blocks, stream);
     if (e == hipSuccess) e = hipEventRecord(ended, stream);
     if (e != hipSuccess) return hip_fail(e, "device queue launch");
@@ -288,10 +290,11 @@ class DqExecutor : public nrm::Executor {
       }
       return 1;
     }
-    // A kernel that ended on its idle limit just as a request was published
-    // has not seen it: look (at most every 100 us) and start it again.
+    // A kernel that ended (its idle limit or its slice) just as a request
+    // was published has not seen it: look (at most every 20 us) and start it
+    // again.
     const int64_t t = now_ns();
-    if (t - last_check_ns > 100000) {
+    if (t - last_check_ns > 20000) {
       last_check_ns = t;
       const int st = ensure_running();
       if (st != NRM_OK) {
@@ -396,6 +399,7 @@ int nrm_server_default_config(nrm_server_config* cfg) {
   cfg->dq_blocks = 0;
   cfg->dq_idle_us = 100000;
   cfg->dq_plain_above = int64_t(1) << 20;
+  cfg->dq_slice_us = 10000;
   return NRM_OK;
 }
 
@@ -423,6 +427,7 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
     if (cfg->dq_idle_us < 1 || cfg->dq_idle_us > 10000000) return fail(NRM_EINVAL, "dq_idle_us must be 1..10^7");
     if (cfg->dq_plain_above < 1 || cfg->dq_plain_above > nrm::DQ_MAX_N)
       return fail(NRM_EINVAL, "dq_plain_above must be 1..2^25");
+    if (cfg->dq_slice_us < 0 || cfg->dq_slice_us > 10000000) return fail(NRM_EINVAL, "dq_slice_us must be 0..10^7");
   }
   if (device < 0) {
     hipError_t e = hipGetDevice(&device);
@@ -465,7 +470,7 @@ int nrm_server_create(nrm_server** out, int device, const nrm_server_config* cfg
     sc.batching = false;
     sc.max_batch_rows = 1;
     s->core = new nrm::Scheduler(sc, arena, &s->dq);
-    const int st = s->dq.allocate(device, cfg->slots, cfg->dq_blocks, cfg->dq_idle_us);
+    const int st = s->dq.allocate(device, cfg->slots, cfg->dq_blocks, cfg->dq_idle_us, cfg->dq_slice_us);
     if (st != NRM_OK) {
       nrm_server_destroy(s);
       return st;

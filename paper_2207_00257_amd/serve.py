@@ -26,7 +26,7 @@ class Server:
                  accum: str = "f32", batch_params: Optional[dict] = None, arena_bytes: int = 0, device: int = -1,
                  single_plain: bool = True, spread: bool = True, idle_spin_us: int = 1000, min_batch_rows: int = 4,
                  device_queue: bool = False, dq_blocks: int = 0, dq_idle_us: int = 100000,
-                 dq_plain_above: int = 1 << 20):
+                 dq_plain_above: int = 1 << 20, dq_slice_us: int = 10000):
         lib = L.lib()
         cfg = L.NrmServerConfig()
         L.check(lib.nrm_server_default_config(ctypes.byref(cfg)), "nrm_server_default_config")
@@ -47,6 +47,7 @@ class Server:
         cfg.dq_blocks = int(dq_blocks)
         cfg.dq_idle_us = int(dq_idle_us)
         cfg.dq_plain_above = int(dq_plain_above)
+        cfg.dq_slice_us = int(dq_slice_us)
         if batch_params:
             lib.nrm_default_batch_params(ctypes.byref(cfg.batch_params))
             for k, v in batch_params.items():

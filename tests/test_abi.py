@@ -162,9 +162,10 @@ def test_server_config_validation_before_any_hip_call(lib):
         assert lib.nrm_server_create(ctypes.byref(h), 0, ctypes.byref(c)) == L.NRM_EINVAL, field
     # the device queue's own limits (checked with device_queue = 1)
     assert cfg.device_queue == 0 and cfg.dq_blocks == 0 and cfg.dq_idle_us == 100000
-    assert cfg.dq_plain_above == 1 << 20
+    assert cfg.dq_plain_above == 1 << 20 and cfg.dq_slice_us == 10000
     for field, bad in (("dq_blocks", 63), ("dq_blocks", (1 << 16) + 1), ("dq_idle_us", 0),
-                       ("dq_idle_us", 10000001), ("dq_plain_above", 0), ("dq_plain_above", (1 << 25) + 1)):
+                       ("dq_idle_us", 10000001), ("dq_plain_above", 0), ("dq_plain_above", (1 << 25) + 1),
+                       ("dq_slice_us", -1), ("dq_slice_us", 10000001)):
         c = L.NrmServerConfig()
         lib.nrm_server_default_config(ctypes.byref(c))
         c.device_queue = 1

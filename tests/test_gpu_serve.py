@@ -277,7 +277,9 @@ def test_device_queue_plain_calls_do_not_wait_behind_the_kernel():
 
     n = (1 << 21) + 3
     pool = serve.InputPool(n, 52, span=n + 1024)
-    srv = serve.Server(slots=16, hold_outputs=True, device_queue=True, dq_idle_us=2000000)
+    # no slice: the kernel stays until its 2 s idle limit, so a call stuck
+    # behind it would show
+    srv = serve.Server(slots=16, hold_outputs=True, device_queue=True, dq_idle_us=2000000, dq_slice_us=0)
     srv.submit([0], [pool.f32.data_ptr()], [1 << 12], [L.NRM_F32], [L.NRM_F32])  # the kernel is resident
     srv.wait_all(1, timeout_s=30)
     srv.release(0)
@@ -338,4 +340,39 @@ def test_device_queue_every_dtype_pair():
             bad = np.abs(got - ref) > tol
             assert not bad.any(), "pair %d->%d n=%d: %d outputs outside the bound" % (di, do, n, int(bad.sum()))
             srv.release(c[0])
+    srv.close()
+
+
+def test_device_queue_slice_bounds_the_wait_of_other_streams():
+    """A kernel queued on a stream that shares the persistent kernel's
+    hardware queue waits for that launch to end: with a 2 ms slice (and a
+    2 s idle limit) work on a dozen fresh streams, one of which shares it on
+    this runtime, finishes within milliseconds, and requests keep
+    completing across the slices."""
+    import time
+
+    pool = serve.InputPool(1 << 16, 54, span=1 << 16)
+    srv = serve.Server(slots=4, hold_outputs=True, device_queue=True, dq_idle_us=2000000, dq_slice_us=2000)
+    srv.submit([0], [pool.f32.data_ptr()], [1 << 12], [L.NRM_F32], [L.NRM_F32])
+    srv.wait_all(1, timeout_s=30)
+    srv.release(0)
+    x = torch.rand(1 << 12, device="cuda")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for _ in range(12):
+        st = torch.cuda.Stream()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(st):
+            y = x * 2.0
+        st.synchronize()
+        worst = max(worst, time.perf_counter() - t0)
+        assert torch.equal(y, x * 2.0)
+    assert worst < 0.2, "a fresh stream waited %.3f s behind the kernel" % worst
+    for i in range(1, 41):  # requests across several slices
+        srv.submit([i], [pool.f32.data_ptr()], [1 << 15], [L.NRM_F32], [L.NRM_F32])
+        (c,) = srv.wait_all(1, timeout_s=30)
+        assert c[5] == L.NRM_OK
+        check_against_oracle(pool, 1 << 15, L.NRM_F32, 0, read_out(c[1], 1 << 15, L.NRM_F32), "request %d" % i)
+        srv.release(i)
+        time.sleep(0.001)
     srv.close()

@@ -122,8 +122,12 @@ class DqExecutor : public nrm::Executor {
   bool launched = false;
   uint64_t epoch = 0;               // launches so far
   uint64_t seq = 0;                 // requests published so far
-  int64_t outstanding = 0;          // published, not yet seen complete
   int64_t last_check_ns = 0;        // last time query() looked at the kernel
+  // The first failure to start or observe the kernel, kept: a request stays
+  // published in the ring, so once its slot has completed with an error (and
+  // its output memory gone back to the arena) no kernel may run again.
+  int broken = NRM_OK;
+  std::string broken_msg;
   int accum = NRM_ACC_F32;
   int64_t blocks = 0;
   unsigned long long idle_ticks = 0;
@@ -224,18 +228,25 @@ class DqExecutor : public nrm::Executor {
 
   // Start the kernel unless it is running.
   int ensure_running() {
+    if (broken != NRM_OK) return fail(broken, broken_msg);
+    hipError_t e = hipSuccess;
     if (launched) {
-      hipError_t e = hipEventQuery(ended);
+      e = hipEventQuery(ended);
       if (e == hipErrorNotReady) return NRM_OK;
-      if (e != hipSuccess) return hip_fail(e, "hipEventQuery (device queue)");
     }
-    epoch += 1;
-    const nrm::DqArgs a{host_dev, dev, epoch, idle_ticks, slice_ticks};
-    hipError_t e = nrm::launch_dq(a, accum, blocks, stream);
-    if (e == hipSuccess) e = hipEventRecord(ended, stream);
-    if (e != hipSuccess) return hip_fail(e, "device queue launch");
-    launched = true;
-    return NRM_OK;
+    if (e == hipSuccess) {
+      epoch += 1;
+      const nrm::DqArgs a{host_dev, dev, epoch, idle_ticks, slice_ticks};
+      e = nrm::launch_dq(a, accum, blocks, stream);
+      if (e == hipSuccess) e = hipEventRecord(ended, stream);
+      if (e == hipSuccess) {
+        launched = true;
+        return NRM_OK;
+      }
+    }
+    broken = hip_fail(e, "device queue launch");
+    broken_msg = nrm_last_error();
+    return broken;
   }
 
   int launch(int k, const nrm_row* rows, int64_t count, bool) override {
@@ -246,10 +257,17 @@ class DqExecutor : public nrm::Executor {
         continue;
       }
       if (r.n > plain_above) {
-        on_plain[(size_t)k] = 1;
         const int st = plain.launch(k, &r, 1, false);
-        if (st != NRM_OK) msg = plain.message();
-        return st;
+        if (st != NRM_OK) {
+          msg = plain.message();
+          return st;
+        }
+        on_plain[(size_t)k] = 1;
+        return NRM_OK;
+      }
+      if (broken != NRM_OK) {  // nothing more is published once the kernel failed
+        msg = broken_msg;
+        return fail(broken, broken_msg);
       }
       // four words, each with the request's tag above bit 48 (addresses and
       // n are checked to fit below it when the request is submitted)
@@ -262,7 +280,6 @@ class DqExecutor : public nrm::Executor {
       for (int j = 0; j < 4; ++j) __atomic_store_n(w + j, words[j], __ATOMIC_RELEASE);
       tag[(size_t)k] = nrm::dq_tag(seq);
       seq += 1;
-      outstanding += 1;
     }
     const int st = ensure_running();
     if (st != NRM_OK) msg = nrm_last_error();
@@ -283,7 +300,6 @@ class DqExecutor : public nrm::Executor {
     const uint64_t v = __atomic_load_n(&host->done[k], __ATOMIC_ACQUIRE);
     if (v == tag[(size_t)k]) {
       tag[(size_t)k] = 0;
-      outstanding -= 1;
       if (__atomic_load_n(&host->stalled[k], __ATOMIC_ACQUIRE) == v) {
         msg = "device queue: a wait for a request's partial sums gave up (its output is not valid)";
         return NRM_EDEVICE;

@@ -1460,8 +1460,9 @@ hipError_t plain_resident_acc(const RowDesc& d, const PlainResidentWs& w, hipStr
 // publishes before it waits; a long request's dividing units wait only on
 // its summing units, all of which were taken before them. Every wait is
 // bounded: the exchange waits by RES_SPIN_LIMIT polls, the poller by the idle
-// limit (or the host's stop word), and a waiting block by the exit word the
-// poller sets when it ends, or by four idle limits of its own.
+// limit, the launch's slice or the host's stop word, and a waiting block by
+// the exit word the poller sets when it ends, or by four idle limits of its
+// own.
 
 // Blocks whose ticket is more than this many units past the published count
 // poll it at the slowest rate.
@@ -1494,17 +1495,31 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// What a block remembers between its claims (in LDS, written by lane 0 of
+// wavefront 0): the largest published unit count it has seen, and the
+// request of its last unit. Unit numbers are never reused, so a unit inside
+// the remembered request's range belongs to it, and that request cannot have
+// completed while one of its units is still to run.
+struct DqCache {
+  unsigned long long pub;
+  unsigned long long first, units;
+  unsigned long long w[7];  // the request's ring entry: in, out, n, dtypes, key, seq, slot
+  int slot;
+  int pad;
+};
+
 // The poller (wavefront 0 of the block holding the ticket equal to the
 // published unit count): read the next DQ_BATCH lines of the publish ring and
 // the host's stop word in one round trip (lane 4 i + k: word k of request
 // pub_reqs + i; lane 4 DQ_BATCH: the stop word), take the leading requests
 // whose four words all carry their tag, copy them into the device ring with
-// their unit numbers, then publish the new unit count. Returns whether there
-// were any; *stop receives the stop word.
+// their unit numbers, then publish the new unit count. The first of them
+// holds the poller's own unit: it goes into the block's cache, which spares
+// the lookup. Returns whether there were any; *stop receives the stop word.
 constexpr int DQ_BATCH = 15;
 static_assert(4 * DQ_BATCH < 64, "one wavefront reads the lines and the stop word");
 
-__device__ __forceinline__ bool dq_copy_new(const DqArgs& a, unsigned long long* stop) {
+__device__ __forceinline__ bool dq_copy_new(const DqArgs& a, unsigned long long* stop, DqCache* m) {
   DqDev* q = a.dev;
   const DqHost* h = a.host;
   const int lane = threadIdx.x;
@@ -1555,29 +1570,36 @@ __device__ __forceinline__ bool dq_copy_new(const DqArgs& a, unsigned long long*
       __hip_atomic_store(&q->finished[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
+  // request 0's entry, as the lanes of request 0 wrote it to the ring
+  const unsigned long long w0 = uniform_u64(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(low >> 32), 0) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 0));
+  const unsigned long long w1 = uniform_u64(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(low >> 32), 1) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 1));
+  const unsigned long long w2 = uniform_u64(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(low >> 32), 2) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 2));
+  const unsigned long long w3 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 3);
+  const unsigned long long first0 = uniform_u64(ld_agent(&q->pub_units));
+  const unsigned long long units0 = (unsigned long long)dq_units((int64_t)w2);
   // the copies before the counts: a block that sees the new unit count finds
   // its request in the ring
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (lane == 0) {
+    m->w[0] = w0;
+    m->w[1] = w1;
+    m->w[2] = w2;
+    m->w[3] = (w3 & 0xFF) | ((w3 >> 8) & 0xFF) << 32;
+    m->w[offsetof(DqReq, key) / 8] = (first0 << DQ_KEY_UNIT_BITS) | units0;
+    m->w[offsetof(DqReq, seq) / 8] = done;
+    m->w[offsetof(DqReq, slot) / 8] = (w3 >> 16) & (DQ_RING - 1);
+    m->first = first0;
+    m->units = units0;
+    m->slot = (int)((w3 >> 16) & (DQ_RING - 1));
     st_agent(&q->pub_reqs, done + cnt);
     st_agent(&q->last_seen, dq_now());
     __hip_atomic_store(&q->pub_units, first, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   return true;
 }
-
-// What a block remembers between its claims (in LDS, written by lane 0 of
-// wavefront 0): the largest published unit count it has seen, and the
-// request of its last unit. Unit numbers are never reused, so a unit inside
-// the remembered request's range belongs to it, and that request cannot have
-// completed while one of its units is still to run.
-struct DqCache {
-  unsigned long long pub;
-  unsigned long long first, units;
-  unsigned long long w[7];  // the request's ring entry: in, out, n, dtypes, key, seq, slot
-  int slot;
-  int pad;
-};
 
 // Wavefront 0: take the next ticket, wait until its unit is published (or
 // the kernel ends), and find the unit's request. Fills *c (c->exit when the
@@ -1601,7 +1623,7 @@ __device__ __forceinline__ void dq_claim(const DqArgs& a, DqClaim* c, DqCache* m
       if (u == pub) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the previous poller's counts
         unsigned long long stop = 0;
-        if (dq_copy_new(a, &stop)) continue;
+        if (dq_copy_new(a, &stop, m)) continue;
         unsigned long long last = 0, ex = 0, born = 0;
         if (lane == 0) {
           last = ld_agent(&q->last_seen);
@@ -1914,9 +1936,11 @@ __device__ __forceinline__ void dq_finish(const DqArgs& a, const DqClaim& c, uns
   if (threadIdx.x == 0) {
     DqDev* q = a.dev;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-    const unsigned prev = __hip_atomic_fetch_add(&q->finished[c.slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // a one-unit request needs no count: its unit is the last
+    const unsigned prev =
+        target == 1 ? 0u : __hip_atomic_fetch_add(&q->finished[c.slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == target - 1) {
-      __hip_atomic_store(&q->finished[c.slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (target > 1) __hip_atomic_store(&q->finished[c.slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
       const unsigned long long tag = dq_tag(c.seq);
       DqHost* h = a.host;

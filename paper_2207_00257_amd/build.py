@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnrm.so")
 
-SOURCES = ["nrm_kernels.hip", "nrm_batched.hip", "nrm_forms.hip", "nrm_nll.hip", "nrm_layerforward.hip", "nrm_ceiling.hip", "nrm_api.cpp",
+SOURCES = ["nrm_kernels.hip", "nrm_batched.hip", "nrm_dq.hip", "nrm_forms.hip", "nrm_nll.hip", "nrm_layerforward.hip", "nrm_ceiling.hip", "nrm_api.cpp",
            "nrm_batched_api.cpp", "nrm_server.cpp", "nrm_noalloc.cpp", "nrm_tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -32,96 +32,14 @@
 // depends only on its length, its start alignment modulo 128 bytes, its
 // dtypes, the accumulation mode and the launch parameters: never on the
 // other rows or its position in the batch.
-#include <stddef.h>
-
 #include "nrm_batch.h"
 #include "nrm_device.h"
-#include "nrm_dq.h"
+#include "nrm_rows.h"
 
 namespace nrm {
 namespace {
 
 using namespace dev;
-
-// ---- geometry of one contiguous segment --------------------------------------
-
-// A segment's vector body starts on a 128-byte boundary (one cache line), so
-// every wavefront's 1 KiB access covers whole lines: a body that is only
-// 16-byte aligned straddles a line at each end of every access, and with
-// non-temporal stores those partial lines cost about a tenth of the map's
-// bandwidth. The head before the boundary (at most 31 binary32 or 63 2-byte
-// elements, fewer than the 64 threads of the smallest block) and the tail
-// after the last whole vector are handled one element per thread.
-constexpr int BODY_ALIGN = 128;
-
-struct Geom {
-  int64_t head;        // elements before the body's 128-byte boundary
-  int64_t nvec;        // whole 16-byte vectors in the body
-  int64_t tail_begin;  // first element after the vectors
-};
-
-template <int DT>
-__device__ __forceinline__ Geom geometry(const char* p, int64_t n) {
-  constexpr int SI = Elem<DT>::SIZE, VEC = Elem<DT>::VEC;
-  Geom g;
-  const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(p) & (BODY_ALIGN - 1));
-  g.head = mis ? (BODY_ALIGN - mis) / SI : 0;
-  if (g.head > n) g.head = n;
-  g.nvec = (n - g.head) / VEC;
-  g.tail_begin = g.head + g.nvec * VEC;
-  return g;
-}
-
-// Output vectors can be stored whole when the output segment has the same
-// alignment as the input's vector body.
-template <int DTI, int DTO>
-__device__ __forceinline__ bool out_vector_ok(const char* out_seg, int64_t head) {
-  constexpr int SO = Elem<DTO>::SIZE, VEC = Elem<DTI>::VEC;
-  constexpr int A = VEC * SO < 16 ? VEC * SO : 16;
-  return (reinterpret_cast<uintptr_t>(out_seg + head * SO) % A) == 0;
-}
-
-template <int DTI, int DTO>
-__device__ __forceinline__ void store_quotients(char* out_seg, int64_t head, int64_t v, bool vec_ok,
-                                                const float (&q)[Elem<DTI>::VEC]) {
-  constexpr int VEC = Elem<DTI>::VEC;
-  if (vec_ok) {
-    store_vec<DTO, VEC>(out_seg + head * Elem<DTO>::SIZE, v, q);
-  } else {
-#pragma unroll
-    for (int c = 0; c < VEC; ++c) store_one<DTO>(out_seg, head + v * VEC + c, q[c]);
-  }
-}
-
-// ---- the element-wise map of a row ---------------------------------------------------
-
-// normalize: x / S with the row's sum, a correctly rounded binary32 division.
-// softmax: exp2(x log2(e) - k) times 1/s (the correctly rounded reciprocal of
-// the row's scaled sum, formed once per block) with the row's exponent k; the
-// exponent argument is one fused multiply-add (one rounding), the same
-// expression as in the softmax chains' terms.
-template <int ACC>
-struct RowMap {
-  float S;
-  __device__ __forceinline__ static RowMap of(const Acc<ACC>& acc) { return RowMap{acc.value()}; }
-  __device__ __forceinline__ static RowMap of(const RowRes& r) { return RowMap{r.a}; }
-  __device__ __forceinline__ RowRes result() const { return RowRes{S, 0.0f}; }
-  __device__ __forceinline__ float operator()(float x) const { return x / S; }
-};
-
-template <>
-struct RowMap<ACC_SOFTMAX> {
-  float k, s, rs;
-  __device__ __forceinline__ static RowMap make(float k, float s) { return RowMap{k, s, 1.0f / s}; }
-  __device__ __forceinline__ static RowMap of(const Acc<ACC_SOFTMAX>& acc) { return make(acc.k, acc.s); }
-  __device__ __forceinline__ static RowMap of(const RowRes& r) { return make(r.a, r.b); }
-  __device__ __forceinline__ RowRes result() const { return RowRes{k, s}; }
-  __device__ __forceinline__ float operator()(float x) const {
-    return __builtin_amdgcn_exp2f(__builtin_fmaf(x, LOG2E_F, -k)) * rs;
-  }
-  // log of the row's sum of exponentials: (k + log2 s) ln 2
-  __device__ __forceinline__ float lse() const { return (k + __builtin_amdgcn_logf(s)) * LN2_F; }
-};
 
 // The lse output of a softmax call (device float[rows]), or NULL.
 __device__ __forceinline__ float* lse_out(const BatchArgs& a) { return reinterpret_cast<float*>(a.cnt[CNT_LSE]); }
@@ -518,55 +436,6 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   }
 }
 
-// Softmax chains of one thread that share one exponent k (every chain's k is
-// the same): raised once per loop iteration to cover the iteration's largest
-// element, the chains' sums rescaled exactly, so that each element then costs
-// one fused multiply-add, one exp2 and one addition instead of a compare and
-// a branch of its own.
-template <int NA>
-__device__ __forceinline__ void raise_shared(Acc<ACC_SOFTMAX> (&acc)[NA], float m) {
-  const float y = m * LOG2E_F;
-  if (y > acc[0].k) {
-    const float kn = __builtin_ceilf(y), d = acc[0].k - kn;
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      acc[j].s = scale_pow2(acc[j].s, d);
-      acc[j].k = kn;
-    }
-  }
-}
-
-// A thread's held vectors r[k] (those with first + k * stride < nvec) into
-// softmax chains that share one exponent: one maximum over all of them, one
-// raise (raise_shared), then per element a fused multiply-add, an exp2 and an
-// addition.
-template <int DTI, int NA, int KB>
-__device__ __forceinline__ void softmax_add_held(Acc<ACC_SOFTMAX> (&acc)[NA], const u4 (&r)[KB], int64_t first,
-                                                 int64_t stride, int64_t nvec) {
-  constexpr int VEC = Elem<DTI>::VEC;
-  float m = -3.0e38f;
-#pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    if (first + (int64_t)k * stride < nvec) {
-      float x[VEC];
-      widen<DTI>(r[k], x);
-#pragma unroll
-      for (int c = 0; c < VEC; ++c) m = fmaxf(m, x[c]);
-    }
-  }
-  raise_shared<NA>(acc, m);
-  const float nk = -acc[0].k;
-#pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    if (first + (int64_t)k * stride < nvec) {
-      float x[VEC];
-      widen<DTI>(r[k], x);
-#pragma unroll
-      for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].s += __builtin_amdgcn_exp2f(__builtin_fmaf(x[c], LOG2E_F, nk));
-    }
-  }
-}
-
 // ---- single-pass rows (held in registers) --------------------------------------------
 
 template <int DTI, int DTO, int ACC, int KB>
@@ -823,325 +692,6 @@ __device__ __forceinline__ void dispatch_tile_map(const RowDesc& d, int64_t b, i
       default: NRM_TM(NRM_F16, NRM_F16); break;
     }
 #undef NRM_TM
-  }
-}
-
-// ---- resident rows -------------------------------------------------------------------------
-// A row of at most RES_MAX_SEGMENTS segments of 2^RES_LOG2 elements crosses
-// HBM twice instead of three times: each segment is one work item, held in
-// one block's registers from its read to its write. The blocks of a row
-// publish their segment sums, each waits until it sees all of them, merges
-// them in a fixed order (the same in every block of the row, so that every
-// block divides by the same bits) and divides its segment from registers.
-//
-// Progress: blocks take items from a counter (CNT_DISPENSE) in item order, a
-// row's items are consecutive, a block takes an item only once it has
-// finished the previous one, and it publishes its sum before it waits. Every row
-// before the one holding the last item taken therefore has all its items in
-// running blocks, each of which publishes: their waits end. Only that last
-// row can wait on items not yet taken, and at most RES_MAX_SEGMENTS - 1 of
-// its blocks wait while the others take its remaining items. The wait is
-// still bounded: after RES_SPIN_LIMIT polls a block flags NRM_DEVERR_STALL
-// and goes on, and every wait of the call gives up once that flag is set,
-// so the kernel always ends.
-//
-// A partial travels as tagged 64-bit words (this call's number in the high
-// half, a binary32 in the low half; two words for the two-float kinds),
-// written and read with agent-scope atomics, which are coherent across the
-// XCDs' L2 caches. A word is valid when its tag is this call's number: no
-// slot is cleared between calls and no fence orders one word after another.
-constexpr uint32_t RES_SPIN_LIMIT = 1u << 18;
-
-template <int ACC>
-struct Tagged {
-  static constexpr int WORDS = ACC == NRM_ACC_F32 ? 1 : 2;
-  __device__ __forceinline__ static void split(const Acc<ACC>& v, float (&f)[2]) {
-    if constexpr (ACC == NRM_ACC_F32) {
-      f[0] = v.s;
-      f[1] = 0.0f;
-    } else if constexpr (ACC == NRM_ACC_KAHAN) {
-      f[0] = v.hi;
-      f[1] = v.lo;
-    } else {
-      f[0] = v.k;
-      f[1] = v.s;
-    }
-  }
-  __device__ __forceinline__ static Acc<ACC> join(const float (&f)[2]) {
-    Acc<ACC> v;
-    if constexpr (ACC == NRM_ACC_F32) {
-      v.s = f[0];
-    } else if constexpr (ACC == NRM_ACC_KAHAN) {
-      v.hi = f[0];
-      v.lo = f[1];
-    } else {
-      v.k = f[0];
-      v.s = f[1];
-    }
-    return v;
-  }
-};
-
-// Where one row's segments meet: segment s's tagged words at slots[2 s] and
-// slots[2 s + 1]; the count of segments that have published (0 between
-// calls); the row's merged total, two tagged words. The last segment to
-// arrive merges all partials and publishes the total; the others wait for
-// that one word, so a row's blocks poll one location each instead of every
-// block polling every partial.
-struct ResExchange {
-  unsigned long long* slots;
-  unsigned long long* total;
-  unsigned* arrivals;
-  uint32_t ep;                // this call's number
-  int* error;                 // device error word (NRM_DEVERR_STALL)
-  unsigned long long* stall;  // the number of the last call in which a wait gave up
-  unsigned long long* call;   // when set: the call counter the last arrival moves on
-};
-
-template <int ACC>
-__device__ __forceinline__ void publish_tagged(unsigned long long* words, uint32_t ep, const Acc<ACC>& v) {
-  float f[2];
-  Tagged<ACC>::split(v, f);
-#pragma unroll
-  for (int w = 0; w < Tagged<ACC>::WORDS; ++w)
-    __hip_atomic_store(words + w, ((unsigned long long)ep << 32) | bits_f32(f[w]), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// A bounded wait has run out: flag it for the host and for this call's other
-// waits.
-__device__ __forceinline__ void give_up(const ResExchange& x) {
-  atomicOr(x.error, NRM_DEVERR_STALL);
-  __hip_atomic_store(x.stall, (unsigned long long)x.ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ bool given_up(const ResExchange& x, uint32_t spin) {
-  return (spin & 255) == 255 && __hip_atomic_load(x.stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == x.ep;
-}
-
-// One thread: wait for the row's total (bounded), and return it.
-template <int ACC>
-__device__ __forceinline__ Acc<ACC> wait_total(const ResExchange& x) {
-  float f[2] = {0.0f, 0.0f};
-  for (uint32_t spin = 0;; ++spin) {
-    bool ok = true;
-#pragma unroll
-    for (int w = 0; w < Tagged<ACC>::WORDS; ++w) {
-      const unsigned long long v = __hip_atomic_load(x.total + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      f[w] = f32_bits((uint32_t)v);
-      ok = ok && (uint32_t)(v >> 32) == x.ep;
-    }
-    if (ok) break;
-    if (spin >= RES_SPIN_LIMIT) {
-      give_up(x);
-      break;
-    }
-    if (given_up(x, spin)) break;
-    __builtin_amdgcn_s_sleep(1);
-  }
-  return Tagged<ACC>::join(f);
-}
-
-// Wavefront 0 (all 64 lanes) of the last block to arrive: read the row's
-// nseg <= 64 * PER_LANE partials (each has been published; a word not yet
-// visible is read again), lane l taking segments l, l + 64, ..., then merge
-// them: each lane its own pairwise, then the wavefront tree. Every lane
-// returns the row's total; the order depends only on nseg.
-template <int ACC, int PER_LANE>
-__device__ __forceinline__ Acc<ACC> gather_row(const ResExchange& x, int nseg) {
-  const int lane = threadIdx.x & 63;
-  float f[PER_LANE][2];
-  bool have[PER_LANE];
-#pragma unroll
-  for (int j = 0; j < PER_LANE; ++j) {
-    f[j][0] = f[j][1] = 0.0f;
-    have[j] = lane + 64 * j >= nseg;
-  }
-  for (uint32_t spin = 0;; ++spin) {
-    bool all = true;
-#pragma unroll
-    for (int j = 0; j < PER_LANE; ++j) {
-      if (!have[j]) {
-        bool ok = true;
-#pragma unroll
-        for (int w = 0; w < Tagged<ACC>::WORDS; ++w) {
-          const unsigned long long v = __hip_atomic_load(x.slots + 2 * (lane + 64 * j) + w, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-          f[j][w] = f32_bits((uint32_t)v);
-          ok = ok && (uint32_t)(v >> 32) == x.ep;
-        }
-        have[j] = ok;
-      }
-      all = all && have[j];
-    }
-    if (__all(all)) break;
-    if (spin >= RES_SPIN_LIMIT) {
-      if (lane == 0) give_up(x);
-      break;
-    }
-    if (given_up(x, spin)) break;  // another wait of this call already gave up
-    __builtin_amdgcn_s_sleep(1);
-  }
-  Acc<ACC> v[PER_LANE];
-#pragma unroll
-  for (int j = 0; j < PER_LANE; ++j) {
-    if (lane + 64 * j < nseg && have[j]) v[j] = Tagged<ACC>::join(f[j]);
-    else v[j].zero();
-  }
-#pragma unroll
-  for (int st = 1; st < PER_LANE; st <<= 1)
-#pragma unroll
-    for (int j = 0; j + st < PER_LANE; j += 2 * st) v[j].merge(v[j + st]);
-  return wave_reduce<ACC>(v[0]);
-}
-
-// One resident segment of 2^LOG2 elements held by a BLOCK-thread block:
-// read into registers, block sum, exchange with the row's other segments,
-// divide from the registers, write. The row's result (RowMap) is left in
-// *s_bcast; lse, when given, receives the softmax row's log-sum-exp (from
-// segment 0).
-//
-// DIRECT: every block of the row reads all partials itself (one round trip:
-// the lowest latency for a single row of few segments) instead of waiting for
-// the last arrival's total (fewer polls: the better throughput for a batch);
-// the arrival count then only finds the last block, which moves the call
-// number on.
-template <int DTI, int DTO, int ACC, int BLOCK, int LOG2, int PER_LANE, bool DIRECT = false>
-__device__ __forceinline__ void resident_unit(const RowDesc& d, int seg, const ResExchange& x, Acc<ACC>* slots,
-                                              RowRes* s_bcast, float* lse_row) {
-  constexpr int VEC = Elem<DTI>::VEC;
-  constexpr int KB = (1 << LOG2) / (BLOCK * VEC);
-  static_assert(KB >= 1 && KB * BLOCK * VEC == (1 << LOG2), "a segment is whole vectors per thread");
-  // chains per thread: 8 binary32, 4 of the two-float kinds (registers)
-  constexpr int NA_MAX = ACC == NRM_ACC_F32 ? 8 : 4;
-  constexpr int NA = KB * VEC < NA_MAX ? KB * VEC : NA_MAX;
-  const int t = threadIdx.x;
-  const int64_t S = int64_t(1) << LOG2;
-  const int64_t b = (int64_t)seg << LOG2;
-  const int64_t n = d.n - b < S ? d.n - b : S;
-  const int nseg = (int)((d.n + S - 1) >> LOG2);
-  const char* in_seg = d.in + b * Elem<DTI>::SIZE;
-  char* out_seg = d.out + b * Elem<DTO>::SIZE;
-  const Geom g = geometry<DTI>(in_seg, n);
-  const u4* body = reinterpret_cast<const u4*>(in_seg + g.head * Elem<DTI>::SIZE);
-  const bool has_head = t < g.head;
-  const int64_t ti = g.tail_begin + t;
-  const bool has_tail = ti < n;
-  u4 r[KB];
-#pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    const int64_t v = t + (int64_t)k * BLOCK;
-    if (v < g.nvec) r[k] = load_vec<true>(body + v);
-  }
-  const float xh = has_head ? load_one<DTI>(in_seg, t) : 0.0f;
-  const float xt = has_tail ? load_one<DTI>(in_seg, ti) : 0.0f;
-  Acc<ACC> acc[NA];
-#pragma unroll
-  for (int k = 0; k < NA; ++k) acc[k].zero();
-  if constexpr (ACC == ACC_SOFTMAX) {
-    softmax_add_held<DTI, NA, KB>(acc, r, t, BLOCK, g.nvec);
-  } else {
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      if (t + (int64_t)k * BLOCK < g.nvec) {
-        float xv[VEC];
-        widen<DTI>(r[k], xv);
-#pragma unroll
-        for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(xv[c]);
-      }
-    }
-  }
-  if (has_head) acc[0].add(xh);
-  if (has_tail) acc[0].add(xt);
-  merge_chains<ACC, NA>(acc);
-  const Acc<ACC> tot = block_reduce<ACC>(acc[0], slots);
-  if (nseg == 1) {
-    if (t == 0) {
-      const RowMap<ACC> f0 = RowMap<ACC>::of(tot);
-      *s_bcast = f0.result();
-      if constexpr (ACC == ACC_SOFTMAX) {
-        if (lse_row) *lse_row = f0.lse();
-      }
-    }
-  } else if (DIRECT && t < 64) {
-    if (t == 0) publish_tagged<ACC>(x.slots + 2 * seg, x.ep, tot);
-    const Acc<ACC> total = gather_row<ACC, PER_LANE>(x, nseg);
-    if (t == 0) {
-      const RowMap<ACC> f0 = RowMap<ACC>::of(total);
-      *s_bcast = f0.result();
-      if constexpr (ACC == ACC_SOFTMAX) {
-        if (lse_row && seg == 0) *lse_row = f0.lse();
-      }
-      // after this block's reads of the tags: the last one moves the call on
-      if (__hip_atomic_fetch_add(x.arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)nseg - 1) {
-        __hip_atomic_store(x.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (x.call) __hip_atomic_fetch_add(x.call, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-  } else if (t < 64) {
-    unsigned prev = 0;
-    if (t == 0) {
-      publish_tagged<ACC>(x.slots + 2 * seg, x.ep, tot);
-      prev = __hip_atomic_fetch_add(x.arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    prev = (unsigned)__builtin_amdgcn_readfirstlane((int)prev);
-    Acc<ACC> total;
-    if (prev == (unsigned)nseg - 1) {
-      // the last to arrive: every segment has published; the count goes back
-      // to 0 for the next call, and the merged total is published once
-      if (t == 0) __hip_atomic_store(x.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      total = gather_row<ACC, PER_LANE>(x, nseg);
-      if (t == 0) {
-        publish_tagged<ACC>(x.total, x.ep, total);
-        if (x.call) __hip_atomic_fetch_add(x.call, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    } else if (t == 0) {
-      total = wait_total<ACC>(x);
-    }
-    if (t == 0) {
-      const RowMap<ACC> f0 = RowMap<ACC>::of(total);
-      *s_bcast = f0.result();
-      if constexpr (ACC == ACC_SOFTMAX) {
-        if (lse_row && seg == 0) *lse_row = f0.lse();
-      }
-    }
-  }
-  lds_barrier();
-  const RowMap<ACC> f = RowMap<ACC>::of(*s_bcast);
-  const bool vec_ok = out_vector_ok<DTI, DTO>(out_seg, g.head);
-#pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    const int64_t v = t + (int64_t)k * BLOCK;
-    if (v < g.nvec) {
-      float xv[VEC], q[VEC];
-      widen<DTI>(r[k], xv);
-#pragma unroll
-      for (int c = 0; c < VEC; ++c) q[c] = f(xv[c]);
-      store_quotients<DTI, DTO>(out_seg, g.head, v, vec_ok, q);
-    }
-  }
-  if (has_head) store_one<DTO>(out_seg, t, f(xh));
-  if (has_tail) store_one<DTO>(out_seg, ti, f(xt));
-}
-
-template <int ACC>
-__device__ __forceinline__ void dispatch_resident(const RowDesc& d, int seg, const ResExchange& x, Acc<ACC>* slots,
-                                                  RowRes* s_bcast, float* lse_row) {
-  if constexpr (ACC == ACC_SOFTMAX) {
-    resident_unit<NRM_F32, NRM_F32, ACC, RES_BLOCK, RES_LOG2, 1>(d, seg, x, slots, s_bcast, lse_row);
-  } else {
-#define NRM_RU(I, O) return resident_unit<I, O, ACC, RES_BLOCK, RES_LOG2, 1>(d, seg, x, slots, s_bcast, lse_row)
-    switch (d.in_dt * 3 + d.out_dt) {
-      case NRM_F32 * 3 + NRM_F32: NRM_RU(NRM_F32, NRM_F32);
-      case NRM_F32 * 3 + NRM_BF16: NRM_RU(NRM_F32, NRM_BF16);
-      case NRM_F32 * 3 + NRM_F16: NRM_RU(NRM_F32, NRM_F16);
-      case NRM_BF16 * 3 + NRM_F32: NRM_RU(NRM_BF16, NRM_F32);
-      case NRM_BF16 * 3 + NRM_BF16: NRM_RU(NRM_BF16, NRM_BF16);
-      case NRM_BF16 * 3 + NRM_F16: NRM_RU(NRM_BF16, NRM_F16);
-      case NRM_F16 * 3 + NRM_F32: NRM_RU(NRM_F16, NRM_F32);
-      case NRM_F16 * 3 + NRM_BF16: NRM_RU(NRM_F16, NRM_BF16);
-      default: NRM_RU(NRM_F16, NRM_F16);
-    }
-#undef NRM_RU
   }
 }
 
@@ -1449,571 +999,6 @@ hipError_t plain_resident_acc(const RowDesc& d, const PlainResidentWs& w, hipStr
 }
 
 
-// ---- device queue: the server's persistent kernel -----------------------------------------
-// The protocol is described in nrm_dq.h. Wavefront 0 of a block takes a
-// ticket (the next unit number) and waits until the unit is published; the
-// block holding the ticket equal to the published count is the one that
-// polls the host (at most one block reads host memory at a time) and copies
-// new requests into the device ring. Progress follows the resident rows'
-// argument: units are taken in order and a request's units are consecutive,
-// a block takes a ticket only after finishing its previous unit, and it
-// publishes before it waits; a long request's dividing units wait only on
-// its summing units, all of which were taken before them. Every wait is
-// bounded: the exchange waits by RES_SPIN_LIMIT polls, the poller by the idle
-// limit, the launch's slice or the host's stop word, and a waiting block by
-// the exit word the poller sets when it ends, or by four idle limits of its
-// own.
-
-// Blocks whose ticket is more than this many units past the published count
-// poll it at the slowest rate.
-constexpr unsigned long long DQ_NEAR = 16;
-
-struct DqClaim {
-  RowDesc d;
-  long long part;  // the unit's index within its request
-  unsigned long long seq;
-  int units;
-  int slot;
-  int exit;
-  int pad;
-};
-
-__device__ __forceinline__ unsigned long long dq_now() { return (unsigned long long)wall_clock64(); }
-
-__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_sys(const uint64_t* p) {
-  return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-// What a block remembers between its claims (in LDS, written by lane 0 of
-// wavefront 0): the largest published unit count it has seen, and the
-// request of its last unit. Unit numbers are never reused, so a unit inside
-// the remembered request's range belongs to it, and that request cannot have
-// completed while one of its units is still to run.
-struct DqCache {
-  unsigned long long pub;
-  unsigned long long first, units;
-  unsigned long long w[7];  // the request's ring entry: in, out, n, dtypes, key, seq, slot
-  int slot;
-  int pad;
-};
-
-// The poller (wavefront 0 of the block holding the ticket equal to the
-// published unit count): read the next DQ_BATCH lines of the publish ring and
-// the host's stop word in one round trip (lane 4 i + k: word k of request
-// pub_reqs + i; lane 4 DQ_BATCH: the stop word), take the leading requests
-// whose four words all carry their tag, copy them into the device ring with
-// their unit numbers, then publish the new unit count. The first of them
-// holds the poller's own unit: it goes into the block's cache, which spares
-// the lookup. Returns whether there were any; *stop receives the stop word.
-constexpr int DQ_BATCH = 15;
-static_assert(4 * DQ_BATCH < 64, "one wavefront reads the lines and the stop word");
-
-__device__ __forceinline__ bool dq_copy_new(const DqArgs& a, unsigned long long* stop, DqCache* m) {
-  DqDev* q = a.dev;
-  const DqHost* h = a.host;
-  const int lane = threadIdx.x;
-  const int i = lane >> 2, k = lane & 3;
-  unsigned long long done = lane == 0 ? ld_agent(&q->pub_reqs) : 0;
-  done = uniform_u64(done);
-  unsigned long long word = 0;
-  if (i < DQ_BATCH) word = ld_sys(&h->pub[(done + i) % DQ_PUB].w[k]);
-  else if (lane == 4 * DQ_BATCH) word = ld_sys(&h->stop);
-  *stop = uniform_u64((unsigned long long)__builtin_amdgcn_readlane((int)(uint32_t)word, 4 * DQ_BATCH));
-  const bool ok = i < DQ_BATCH && (word >> DQ_TAG_SHIFT) == dq_pub_tag(done + i);
-  // requests are taken in order: stop at the first with a word missing
-  const unsigned long long bad = __ballot(i < DQ_BATCH && !ok) | (~0ull << (4 * DQ_BATCH));
-  const int cnt = __builtin_ctzll(bad) / 4;
-  if (cnt == 0) return false;
-  const unsigned long long low = word & ((1ull << DQ_TAG_SHIFT) - 1);
-  // n is word 2 of each request: every lane of request i learns its n and
-  // the units of the requests before it
-  unsigned long long first = uniform_u64(ld_agent(&q->pub_units)), my_first = 0, my_units = 0;
-  for (int j = 0; j < cnt; ++j) {
-    const int64_t nj = (int64_t)uniform_u64(
-        ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(low >> 32), 4 * j + 2) << 32) |
-        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 4 * j + 2));
-    const unsigned long long uj = (unsigned long long)dq_units(nj);
-    if (i == j) {
-      my_first = first;
-      my_units = uj;
-    }
-    first += uj;
-  }
-  if (i < cnt) {
-    // word 3: in_dtype | out_dtype << 8 | slot << 16
-    const unsigned long long w3 = (unsigned long long)(uint32_t)__shfl((int)(uint32_t)low, 4 * i + 3);
-    const int slot = (int)((w3 >> 16) & (DQ_RING - 1));
-    unsigned long long* dst = reinterpret_cast<unsigned long long*>(&q->ring[slot]);
-    if (k < 3) {
-      st_agent(dst + k, low);  // in, out, n
-    } else {
-      st_agent(dst + 3, (w3 & 0xFF) | ((w3 >> 8) & 0xFF) << 32);  // in_dt, out_dt
-      const unsigned long long key = (my_first << DQ_KEY_UNIT_BITS) | my_units;
-      st_agent(dst + offsetof(DqReq, key) / 8, key);
-      st_agent(dst + offsetof(DqReq, seq) / 8, done + i);
-      st_agent(dst + offsetof(DqReq, slot) / 8, (unsigned long long)slot);
-      st_agent(&q->key[slot], key);
-      // the slot's previous request has completed: its counters start from 0
-      // (they are 0 already unless one of its waits gave up)
-      __hip_atomic_store(&q->arrivals[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&q->finished[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  // request 0's entry, as the lanes of request 0 wrote it to the ring
-  const unsigned long long w0 = uniform_u64(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(low >> 32), 0) << 32) |
-                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 0));
-  const unsigned long long w1 = uniform_u64(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(low >> 32), 1) << 32) |
-                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 1));
-  const unsigned long long w2 = uniform_u64(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(low >> 32), 2) << 32) |
-                                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 2));
-  const unsigned long long w3 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)low, 3);
-  const unsigned long long first0 = uniform_u64(ld_agent(&q->pub_units));
-  const unsigned long long units0 = (unsigned long long)dq_units((int64_t)w2);
-  // the copies before the counts: a block that sees the new unit count finds
-  // its request in the ring
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (lane == 0) {
-    m->w[0] = w0;
-    m->w[1] = w1;
-    m->w[2] = w2;
-    m->w[3] = (w3 & 0xFF) | ((w3 >> 8) & 0xFF) << 32;
-    m->w[offsetof(DqReq, key) / 8] = (first0 << DQ_KEY_UNIT_BITS) | units0;
-    m->w[offsetof(DqReq, seq) / 8] = done;
-    m->w[offsetof(DqReq, slot) / 8] = (w3 >> 16) & (DQ_RING - 1);
-    m->first = first0;
-    m->units = units0;
-    m->slot = (int)((w3 >> 16) & (DQ_RING - 1));
-    st_agent(&q->pub_reqs, done + cnt);
-    st_agent(&q->last_seen, dq_now());
-    __hip_atomic_store(&q->pub_units, first, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  return true;
-}
-
-// Wavefront 0: take the next ticket, wait until its unit is published (or
-// the kernel ends), and find the unit's request. Fills *c (c->exit when the
-// block is to end).
-__device__ __forceinline__ void dq_claim(const DqArgs& a, DqClaim* c, DqCache* m) {
-  DqDev* q = a.dev;
-  const int lane = threadIdx.x;
-  unsigned long long u = 0;
-  if (lane == 0) u = __hip_atomic_fetch_add(&q->next_unit, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  u = uniform_u64(u);
-  if (u >= uniform_u64(m->pub)) {
-    const unsigned long long t_start = dq_now();
-    for (uint32_t spin = 0;; ++spin) {
-      unsigned long long pub = lane == 0 ? ld_agent(&q->pub_units) : 0;
-      pub = uniform_u64(pub);
-      if (u < pub) {
-        if (lane == 0) m->pub = pub;
-        break;
-      }
-      bool end = false;
-      if (u == pub) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the previous poller's counts
-        unsigned long long stop = 0;
-        if (dq_copy_new(a, &stop, m)) continue;
-        unsigned long long last = 0, ex = 0, born = 0;
-        if (lane == 0) {
-          last = ld_agent(&q->last_seen);
-          ex = ld_agent(&q->exit_epoch);
-          born = ld_agent(&q->launched_at);
-        }
-        last = uniform_u64(last);
-        ex = uniform_u64(ex);
-        born = uniform_u64(born);
-        const unsigned long long now = dq_now();
-        // idle for idle_ticks, or this launch has run its slice (so that a
-        // kernel queued behind it on its hardware queue waits at most that
-        // long; the host starts the next launch)
-        end = stop != 0 || ex == a.epoch || (now > last && now - last > a.idle_ticks) ||
-              (a.slice_ticks != 0 && now > born && now - born > a.slice_ticks);
-        if (!end) __builtin_amdgcn_s_sleep(2);
-      } else if ((spin & 7) == 7) {
-        unsigned long long ex = lane == 0 ? ld_agent(&q->exit_epoch) : 0;
-        ex = uniform_u64(ex);
-        const unsigned long long now = dq_now();
-        end = ex == a.epoch || now - t_start > 4 * a.idle_ticks;
-      } else if (u - pub > DQ_NEAR) {
-        // far from the published count: poll rarely, so that hundreds of idle
-        // blocks do not load one word hundreds of millions of times a second
-        // (that channel then slows every transfer striped across it)
-        __builtin_amdgcn_s_sleep(127);
-      } else {
-        __builtin_amdgcn_s_sleep(16);
-      }
-      if (end) {
-        if (lane == 0) {
-          st_agent(&q->exit_epoch, a.epoch);
-          c->exit = 1;
-        }
-        return;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the ring entries copied before the unit count
-  }
-  const unsigned long long mfirst = uniform_u64(m->first), munits = uniform_u64(m->units);
-  if (!(munits > 0 && mfirst <= u && u < mfirst + munits)) {
-    // lane s looks at slot s: the published request whose units hold u (the
-    // ranges of different requests never overlap; a request's entry stays
-    // until the request has completed, and u is one of its units)
-    // (every lane reads its slot's whole entry in the same round trip; a slot
-    // being rewritten for a newer request cannot match u, whose request was
-    // copied before the unit count this block has seen)
-    bool found = false;
-    for (uint32_t spin = 0; spin < RES_SPIN_LIMIT; ++spin) {
-      const unsigned long long* e = reinterpret_cast<const unsigned long long*>(&q->ring[lane]);
-      unsigned long long w[7];
-#pragma unroll
-      for (int k = 0; k < 7; ++k) w[k] = ld_agent(e + k);
-      const unsigned long long key = w[offsetof(DqReq, key) / 8];
-      const unsigned long long first = key >> DQ_KEY_UNIT_BITS, units = key & ((1ull << DQ_KEY_UNIT_BITS) - 1);
-      const bool mine = units > 0 && first <= u && u < first + units;
-      const unsigned long long hit = __ballot(mine);
-      if (hit) {
-        const int src = __builtin_ctzll(hit);
-        if (lane == src) {
-#pragma unroll
-          for (int k = 0; k < 7; ++k) m->w[k] = w[k];
-          m->first = first;
-          m->units = units;
-          m->slot = src;
-        }
-        found = true;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    if (!found) {
-      // cannot happen while the host keeps its side of the protocol; skip the unit
-      if (lane == 0) {
-        atomicOr(&q->error, NRM_DEVERR_ROW);
-        c->d.n = 0;
-        c->units = 0;
-        c->exit = 0;
-      }
-      return;
-    }
-  }
-  if (lane == 0) {
-    // the entry's words: in, out, n, dtypes, key, seq, slot
-    c->d.in = reinterpret_cast<const char*>(m->w[0]);
-    c->d.out = reinterpret_cast<char*>(m->w[1]);
-    c->d.n = (int64_t)m->w[2];
-    c->d.in_dt = (int32_t)(uint32_t)m->w[3];
-    c->d.out_dt = (int32_t)(uint32_t)(m->w[3] >> 32);
-    c->part = (long long)(u - m->first);
-    c->seq = m->w[5];
-    c->units = (int)m->units;
-    c->slot = m->slot;
-    c->exit = 0;
-  }
-}
-
-// Sum of part `part` (2^DQ_LONG_LOG2 elements) of a long request: temporal
-// loads, so that the request's dividing units find it in the last-level cache.
-// The result is valid in thread 0.
-template <int DTI, int ACC>
-__device__ __forceinline__ Acc<ACC> dq_part_sum(const RowDesc& d, int64_t part, Acc<ACC>* slots) {
-  constexpr int VEC = Elem<DTI>::VEC;
-  constexpr int KB = (1 << RES_LOG2) / (RES_BLOCK * VEC);
-  constexpr int CH = 1 << (DQ_LONG_LOG2 - RES_LOG2);
-  constexpr int NA = ACC == NRM_ACC_F32 ? 8 : 4;
-  const int t = threadIdx.x;
-  const int64_t b = part << DQ_LONG_LOG2;
-  const int64_t n = d.n - b < (int64_t(1) << DQ_LONG_LOG2) ? d.n - b : (int64_t(1) << DQ_LONG_LOG2);
-  const char* in_seg = d.in + b * Elem<DTI>::SIZE;
-  const Geom g = geometry<DTI>(in_seg, n);
-  const u4* body = reinterpret_cast<const u4*>(in_seg + g.head * Elem<DTI>::SIZE);
-  Acc<ACC> acc[NA];
-#pragma unroll
-  for (int k = 0; k < NA; ++k) acc[k].zero();
-#pragma unroll 1
-  for (int ch = 0; ch < CH; ++ch) {
-    u4 r[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int64_t v = (int64_t)ch * KB * RES_BLOCK + t + (int64_t)k * RES_BLOCK;
-      if (v < g.nvec) r[k] = load_vec<false>(body + v);
-    }
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int64_t v = (int64_t)ch * KB * RES_BLOCK + t + (int64_t)k * RES_BLOCK;
-      if (v < g.nvec) {
-        float xv[VEC];
-        widen<DTI>(r[k], xv);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[(k * VEC + e) % NA].add(xv[e]);
-      }
-    }
-  }
-  if (t < g.head) acc[0].add(load_one<DTI>(in_seg, t));
-  if (g.tail_begin + t < n) acc[0].add(load_one<DTI>(in_seg, g.tail_begin + t));
-  merge_chains<ACC, NA>(acc);
-  return block_reduce<ACC>(acc[0], slots);
-}
-
-// Divide part `part` of a long request by the request's sum S.
-template <int DTI, int DTO, int ACC>
-__device__ __forceinline__ void dq_part_map(const RowDesc& d, int64_t part, const RowMap<ACC>& f) {
-  constexpr int VEC = Elem<DTI>::VEC;
-  constexpr int KB = (1 << RES_LOG2) / (RES_BLOCK * VEC);
-  constexpr int CH = 1 << (DQ_LONG_LOG2 - RES_LOG2);
-  const int t = threadIdx.x;
-  const int64_t b = part << DQ_LONG_LOG2;
-  const int64_t n = d.n - b < (int64_t(1) << DQ_LONG_LOG2) ? d.n - b : (int64_t(1) << DQ_LONG_LOG2);
-  const char* in_seg = d.in + b * Elem<DTI>::SIZE;
-  char* out_seg = d.out + b * Elem<DTO>::SIZE;
-  const Geom g = geometry<DTI>(in_seg, n);
-  const u4* body = reinterpret_cast<const u4*>(in_seg + g.head * Elem<DTI>::SIZE);
-  const bool vec_ok = out_vector_ok<DTI, DTO>(out_seg, g.head);
-#pragma unroll 1
-  for (int ch = 0; ch < CH; ++ch) {
-    u4 r[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int64_t v = (int64_t)ch * KB * RES_BLOCK + t + (int64_t)k * RES_BLOCK;
-      if (v < g.nvec) r[k] = load_vec<true>(body + v);
-    }
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int64_t v = (int64_t)ch * KB * RES_BLOCK + t + (int64_t)k * RES_BLOCK;
-      if (v < g.nvec) {
-        float xv[VEC], qv[VEC];
-        widen<DTI>(r[k], xv);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) qv[e] = f(xv[e]);
-        store_quotients<DTI, DTO>(out_seg, g.head, v, vec_ok, qv);
-      }
-    }
-  }
-  if (t < g.head) store_one<DTO>(out_seg, t, f(load_one<DTI>(in_seg, t)));
-  if (g.tail_begin + t < n) store_one<DTO>(out_seg, g.tail_begin + t, f(load_one<DTI>(in_seg, g.tail_begin + t)));
-}
-
-// One unit of a long request: a summing unit (part < m) publishes its part's
-// sum, and the last of the request's parts to arrive merges all m in a fixed
-// order and publishes the total; a dividing unit (part >= m) waits for the
-// total and divides its part. Returns whether the unit wrote outputs.
-// Wavefront 0 of the last part to arrive: the request's m <= DQ_MAX_PARTS
-// part sums, lane l taking parts l, l + 64, ..., requested four slices of 64
-// at a time; a slice with a word not yet visible is read again (bounded, as
-// every wait here). Then each lane's pairwise merge and the wavefront tree:
-// the same order as gather_row. Not inlined: it runs once per long request,
-// and inlined its registers would crowd the resident units' (the kernel
-// spilled).
-template <int ACC>
-__device__ __noinline__ Acc<ACC> gather_parts(ResExchange x, int m) {
-  constexpr int PER = DQ_MAX_PARTS / 64;
-  constexpr int G = 4;  // slices requested at once
-  constexpr int W = Tagged<ACC>::WORDS;
-  const int lane = threadIdx.x & 63;
-  Acc<ACC> v[PER];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) v[j].zero();
-#pragma unroll
-  for (int j0 = 0; j0 < PER; j0 += G) {
-    if (64 * j0 >= m) break;
-    unsigned long long w[G][W];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int s = lane + 64 * (j0 + g);
-#pragma unroll
-      for (int k = 0; k < W; ++k)
-        w[g][k] = s < m ? __hip_atomic_load(x.slots + 2 * s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int s = lane + 64 * (j0 + g);
-      bool ok = true;
-#pragma unroll
-      for (int k = 0; k < W; ++k) ok = ok && (s >= m || (uint32_t)(w[g][k] >> 32) == x.ep);
-      for (uint32_t spin = 0; !__all(ok); ++spin) {
-        if (spin >= RES_SPIN_LIMIT) {
-          if (lane == 0) give_up(x);
-          break;
-        }
-        if (given_up(x, spin)) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (!ok) {
-          ok = true;
-#pragma unroll
-          for (int k = 0; k < W; ++k) {
-            w[g][k] = __hip_atomic_load(x.slots + 2 * s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = ok && (uint32_t)(w[g][k] >> 32) == x.ep;
-          }
-        }
-      }
-      if (s < m && ok) {
-        float f[2] = {f32_bits((uint32_t)w[g][0]), W > 1 ? f32_bits((uint32_t)w[g][W - 1]) : 0.0f};
-        v[j0 + g] = Tagged<ACC>::join(f);
-      }
-    }
-  }
-#pragma unroll
-  for (int st = 1; st < PER; st <<= 1)
-#pragma unroll
-    for (int j = 0; j + st < PER; j += 2 * st) v[j].merge(v[j + st]);
-  return wave_reduce<ACC>(v[0]);
-}
-
-template <int ACC>
-__device__ __forceinline__ Acc<ACC> dispatch_part_sum(const RowDesc& d, int64_t part, Acc<ACC>* slots) {
-  if (d.in_dt == NRM_F32) return dq_part_sum<NRM_F32, ACC>(d, part, slots);
-  if (d.in_dt == NRM_BF16) return dq_part_sum<NRM_BF16, ACC>(d, part, slots);
-  return dq_part_sum<NRM_F16, ACC>(d, part, slots);
-}
-
-template <int ACC>
-__device__ __forceinline__ void dispatch_part_map(const RowDesc& d, int64_t part, const RowMap<ACC>& f) {
-#define NRM_DM(I, O) return dq_part_map<I, O, ACC>(d, part, f)
-  switch (d.in_dt * 3 + d.out_dt) {
-    case NRM_F32 * 3 + NRM_F32: NRM_DM(NRM_F32, NRM_F32);
-    case NRM_F32 * 3 + NRM_BF16: NRM_DM(NRM_F32, NRM_BF16);
-    case NRM_F32 * 3 + NRM_F16: NRM_DM(NRM_F32, NRM_F16);
-    case NRM_BF16 * 3 + NRM_F32: NRM_DM(NRM_BF16, NRM_F32);
-    case NRM_BF16 * 3 + NRM_BF16: NRM_DM(NRM_BF16, NRM_BF16);
-    case NRM_BF16 * 3 + NRM_F16: NRM_DM(NRM_BF16, NRM_F16);
-    case NRM_F16 * 3 + NRM_F32: NRM_DM(NRM_F16, NRM_F32);
-    case NRM_F16 * 3 + NRM_BF16: NRM_DM(NRM_F16, NRM_BF16);
-    default: NRM_DM(NRM_F16, NRM_F16);
-  }
-#undef NRM_DM
-}
-
-// One unit of a long request: a summing unit (part < m) publishes its part's
-// sum, and the last of the request's parts to arrive merges all m in a fixed
-// order and publishes the total; a dividing unit (part >= m) waits for the
-// total and divides its part. Only the loops depend on the dtypes; the
-// exchange is shared by all of them. Returns whether the unit wrote outputs.
-template <int ACC>
-__device__ __forceinline__ bool dq_long_unit(const RowDesc& d, int64_t part, int m, const ResExchange& x,
-                                             Acc<ACC>* slots, RowRes* s_bcast) {
-  const int t = threadIdx.x;
-  if (part < m) {
-    const Acc<ACC> tot = dispatch_part_sum<ACC>(d, part, slots);
-    if (t < 64) {
-      unsigned prev = 0;
-      if (t == 0) {
-        publish_tagged<ACC>(x.slots + 2 * part, x.ep, tot);
-        prev = __hip_atomic_fetch_add(x.arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      prev = (unsigned)__builtin_amdgcn_readfirstlane((int)prev);
-      if (prev == (unsigned)m - 1) {
-        if (t == 0) __hip_atomic_store(x.arrivals, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const Acc<ACC> total = gather_parts<ACC>(x, m);
-        if (t == 0) publish_tagged<ACC>(x.total, x.ep, total);
-      }
-    }
-    return false;
-  }
-  if (t == 0) *s_bcast = RowMap<ACC>::of(wait_total<ACC>(x)).result();
-  lds_barrier();
-  dispatch_part_map<ACC>(d, part - m, RowMap<ACC>::of(*s_bcast));
-  return true;
-}
-
-// After a unit that wrote outputs: make its stores visible beyond the XCD's
-// L2 (to the host, DMA engines and later kernels), count it, and let the
-// request's last such unit write the completion word into host memory.
-__device__ __forceinline__ void dq_finish(const DqArgs& a, const DqClaim& c, unsigned target) {
-  // every wavefront waits for its own stores to reach the L2 before the
-  // barrier (the barrier's workgroup-scope release does not wait for global
-  // stores), so that thread 0's write-back below covers the whole unit
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    DqDev* q = a.dev;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-    // a one-unit request needs no count: its unit is the last
-    const unsigned prev =
-        target == 1 ? 0u : __hip_atomic_fetch_add(&q->finished[c.slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == target - 1) {
-      if (target > 1) __hip_atomic_store(&q->finished[c.slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      const unsigned long long tag = dq_tag(c.seq);
-      DqHost* h = a.host;
-      if (ld_agent(&q->stall) == tag)
-        __hip_atomic_store(reinterpret_cast<unsigned long long*>(&h->stalled[c.slot]), tag, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
-      __hip_atomic_store(reinterpret_cast<unsigned long long*>(&h->done[c.slot]), tag, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-  }
-}
-
-template <int ACC>
-__global__ void __launch_bounds__(RES_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 4))) dq_kernel(DqArgs a) {
-  __shared__ Acc<ACC> slots[MAX_WAVES];
-  __shared__ RowRes s_bcast;
-  __shared__ DqClaim s_c;
-  __shared__ DqCache s_cache;
-  DqDev* q = a.dev;
-  if (threadIdx.x == 0) {
-    s_cache.pub = 0;
-    s_cache.units = 0;
-  }
-  for (;;) {
-    if (threadIdx.x < 64) dq_claim(a, &s_c, &s_cache);
-    lds_barrier();
-    // the same in every thread: scalar registers, so that the branches on the
-    // unit's kind are uniform and their bodies do not share registers
-    DqClaim c;
-    c.d.in = reinterpret_cast<const char*>(uniform_u64(reinterpret_cast<unsigned long long>(s_c.d.in)));
-    c.d.out = reinterpret_cast<char*>(uniform_u64(reinterpret_cast<unsigned long long>(s_c.d.out)));
-    c.d.n = (int64_t)uniform_u64((unsigned long long)s_c.d.n);
-    c.d.in_dt = __builtin_amdgcn_readfirstlane(s_c.d.in_dt);
-    c.d.out_dt = __builtin_amdgcn_readfirstlane(s_c.d.out_dt);
-    c.part = (long long)uniform_u64((unsigned long long)s_c.part);
-    c.seq = uniform_u64(s_c.seq);
-    c.units = __builtin_amdgcn_readfirstlane(s_c.units);
-    c.slot = __builtin_amdgcn_readfirstlane(s_c.slot);
-    c.exit = __builtin_amdgcn_readfirstlane(s_c.exit);
-    if (c.exit) return;
-    if (c.units == 0) {
-      lds_barrier();  // s_c is written again by the next claim
-      continue;
-    }
-    const uint32_t tag = dq_tag(c.seq);
-    const ResExchange x{q->tagged[c.slot], q->total[c.slot], &q->arrivals[c.slot], tag, &q->error, &q->stall,
-                        nullptr};
-    if (c.d.n <= DQ_RESIDENT_MAX) {
-      dispatch_resident<ACC>(c.d, (int)c.part, x, slots, &s_bcast, nullptr);
-      dq_finish(a, c, (unsigned)c.units);
-    } else {
-      const int m = c.units / 2;
-      if (dq_long_unit<ACC>(c.d, c.part, m, x, slots, &s_bcast)) dq_finish(a, c, (unsigned)m);
-      else lds_barrier();  // slots and s_c are reused by the next unit
-    }
-  }
-}
-
-__global__ void dq_hold_kernel(const DqHost* h, unsigned long long max_ticks) {
-  const unsigned long long t0 = dq_now();
-  while (ld_sys(&h->hold) == 0 && dq_now() - t0 < max_ticks) __builtin_amdgcn_s_sleep(20);
-}
-
-__global__ void dq_touch_kernel() {}
-
-__global__ void dq_reset_kernel(DqDev* q) {
-  st_agent(&q->next_unit, ld_agent(&q->pub_units));
-  st_agent(&q->exit_epoch, 0ull);
-  const unsigned long long now = dq_now();
-  st_agent(&q->last_seen, now);
-  st_agent(&q->launched_at, now);
-}
-
 }  // namespace
 
 int64_t small_capacity(int) { return SMALL_ELEMS; }
@@ -2057,27 +1042,6 @@ hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
     case ACC_SOFTMAX: return launch_phases<ACC_SOFTMAX>(p, a, s);
     default: return launch_phases<NRM_ACC_F32>(p, a, s);
   }
-}
-
-hipError_t launch_dq_hold(const DqHost* host, unsigned long long max_ticks, hipStream_t s) {
-  hipLaunchKernelGGL(dq_hold_kernel, dim3(1), dim3(1), 0, s, host, max_ticks);
-  return hipGetLastError();
-}
-
-hipError_t launch_dq_touch(hipStream_t s) {
-  hipLaunchKernelGGL(dq_touch_kernel, dim3(1), dim3(1), 0, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_dq(const DqArgs& a, int acc, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL(dq_reset_kernel, dim3(1), dim3(1), 0, s, a.dev);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (acc == NRM_ACC_KAHAN)
-    hipLaunchKernelGGL((dq_kernel<NRM_ACC_KAHAN>), dim3((unsigned)blocks), dim3(RES_BLOCK), 0, s, a);
-  else
-    hipLaunchKernelGGL((dq_kernel<NRM_ACC_F32>), dim3((unsigned)blocks), dim3(RES_BLOCK), 0, s, a);
-  return hipGetLastError();
 }
 
 }  // namespace nrm

@@ -1,5 +1,5 @@
 // Internal interface of the device queue: the server's persistent-kernel
-// executor (nrm_server.cpp) and the kernel that runs it (nrm_batched.hip).
+// executor (nrm_server.cpp) and the kernel that runs it (nrm_dq.hip).
 // Not part of the public ABI.
 //
 // The host publishes each admitted request into a ring in pinned, coherent

@@ -155,6 +155,13 @@ typedef struct {
   int32_t resident_grid;     /* persistent 512-thread blocks of the resident rows' kernel, 1..2^20 and
                                 at least resident_segments: a row's blocks wait for each other, so the
                                 device must be able to run that many of them at once (two per CU fit) */
+  int32_t wave_max;          /* 0..2048: a row of 0 < n <= wave_max elements is taken by one wavefront
+                                (64 lanes): read into registers, summed across the lanes by DPP moves
+                                with no LDS, barrier or work claim, divided from the registers and
+                                written (two HBM transfers). 0: off (such rows take the resident or
+                                single-pass path) */
+  int32_t wave_grid;         /* 256-thread blocks of the short rows' kernel, 1..2^20; its W wavefronts
+                                take the rows statically (wavefront w: rows w, w + W, ...) */
 } nrm_batch_params;
 
 /* One row of a batch given as a table: `in` and `out` are device arrays of
@@ -417,7 +424,7 @@ typedef struct {
                                 that time is picked up without a thread wake-up */
   int32_t min_batch_rows;    /* 1..2^20: with batching, a group of fewer requests runs as one plain
                                 call per request on its slot (a small call is one launch; the batched
-                                call costs its planner and four kernels whatever the group's size) */
+                                call costs its planner and five kernels whatever the group's size) */
   int64_t budget_bytes;      /* HBM admission budget: input + output bytes of admitted requests */
   int64_t arena_bytes;       /* device arena for outputs (0: two thirds of the budget) */
   int64_t max_batch_rows;    /* requests per batch */

@@ -57,6 +57,8 @@ class NrmBatchParams(ctypes.Structure):
         ("keep_mib", ctypes.c_int32),
         ("resident_segments", ctypes.c_int32),
         ("resident_grid", ctypes.c_int32),
+        ("wave_max", ctypes.c_int32),
+        ("wave_grid", ctypes.c_int32),
     ]
 
 

@@ -66,7 +66,8 @@ enum {
   CNT_DISPENSE = 7,    // resident units handed out so far (set to 0 by the planner)
   CNT_EPOCH = 8,       // this call's number: tags the resident rows' published partials
   CNT_STALL = 9,       // the number of the last call in which a resident wait gave up
-  CNT_COUNT = 10,
+  CNT_ROWS = 10,       // the batch's rows (0 when the planner rejected the batch)
+  CNT_COUNT = 11,
 };
 
 // One row's reduction result: the sum (a) for normalize, or the exponent and
@@ -104,13 +105,32 @@ struct BatchArgs {
   unsigned long long* tagged;  // [2 * cap_items]: each segment's partial, two tagged words
   unsigned long long* rowtot;  // [2 * cap_items]: a resident row's total at its first item, two tagged words
   unsigned* arrivals;          // [cap_items]: a resident row's published segments at its first item (0 between calls)
+  // short rows: a row of 0 < n <= wave_max elements is taken by one
+  // wavefront of the short rows' kernel (0: none; at most WAVE_MAX_ELEMS)
+  int64_t wave_max;
+  // split planner (split_plan): a counting kernel leaves each round's counter
+  // totals here, so that the planner's blocks scan only their own round
+  int split_plan;
+  int64_t* round_agg;          // [ceil(cap_rows / PLAN_ROUND_ROWS) * 4]
 };
+
+// The planner takes rows PLAN_ROUND_ROWS at a time (a "round", one block).
+// Up to PLAN_SPLIT_ROWS rows of capacity every planner block scans every
+// round itself (one launch); above, a counting launch first leaves each
+// round's totals, and each planner block scans its own round only.
+constexpr int64_t PLAN_ROUND_ROWS = 1024;
+constexpr int64_t PLAN_SPLIT_ROWS = 4096;
 
 // Elements of one resident segment: 512 threads x 8 vectors of 4 binary32
 // (4 vectors of 8 for 2-byte inputs); two blocks fit a CU's registers.
 constexpr int RES_LOG2 = 14;
 constexpr int RES_BLOCK = 512;
 constexpr int RES_MAX_SEGMENTS = 64;  // one wavefront lane per segment in the merge
+
+// The short rows' kernel: blocks of WAVE_BLOCK threads, rows of at most
+// WAVE_MAX_ELEMS elements (2048 binary32: eight 16-byte vectors per lane).
+constexpr int WAVE_BLOCK = 256;
+constexpr int64_t WAVE_MAX_ELEMS = 2048;
 
 struct BatchPlan {
   int acc;
@@ -122,6 +142,7 @@ struct BatchPlan {
   int map_block;    // phase 2
   int64_t map_grid;
   int64_t res_grid; // persistent blocks of the resident-row kernel (0: none launched)
+  int64_t wave_grid; // blocks of the short rows' kernel (0: none launched)
 };
 
 hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s);

@@ -3,6 +3,10 @@
 // of the element-wise divide exactly as in the plain path (arXiv 2207.00257,
 // Fig. 1 and Sec. IV-C), in one persistent launch sequence for the batch.
 //
+//   batch_count_kernel   (batches of more than 4096 rows of capacity) one
+//                        block per round of 1024 rows: the round's counts,
+//                        so that the planner's blocks need not scan every
+//                        round themselves.
 //   batch_plan_kernel    one block per round of 1024 rows: resolves the row
 //                        table (from CSR offsets or a descriptor table),
 //                        validates it, classifies rows, and by exclusive
@@ -12,6 +16,13 @@
 //                        one item per short row, n <= short_max), of the
 //                        long rows' descriptors and starts, and of phase 2's
 //                        chunk table.
+//   batch_wave_kernel    rows of 0 < n <= wave_max (at most 2048) elements,
+//                        one per wavefront, statically: read into registers,
+//                        summed across the lanes, divided and written, with
+//                        no barrier and no work claim.
+//   batch_resident_kernel  rows of up to 2^20 elements held on chip in
+//                        segments of 2^14 (one block each) between their read
+//                        and their write.
 //   batch_phase1_kernel  persistent blocks walk the items. A single-pass item
 //                        keeps its row in registers: one read, block sum,
 //                        divide, one write. A tile item writes its partial.
@@ -26,9 +37,9 @@
 // ... and fetch the next unit's descriptor while the current one streams.
 //
 // All per-call inputs are read through fixed pointers (a header and the row
-// table in pinned host memory, read once by the planner), so the four
-// launches can be captured once in a hipGraph and replayed for any batch
-// that fits the workspace. A row's summation order
+// table in pinned host memory, read once by the planner), so the launches
+// can be captured once in a hipGraph and replayed for any batch that fits
+// the workspace. A row's summation order
 // depends only on its length, its start alignment modulo 128 bytes, its
 // dtypes, the accumulation mode and the launch parameters: never on the
 // other rows or its position in the batch.
@@ -203,12 +214,35 @@ __device__ __forceinline__ void scan_counts(int64_t (&v)[NCNT], int64_t (&last)[
   last[NCNT - 1] = (int64_t)lane_value64(w, PLAN_WAVES - 1);
 }
 
+// Block totals of the NCNT per-thread 64-bit values v (any magnitude, unlike
+// scan_counts' 32-bit counters), the same in every thread. The caller must
+// pass a barrier before sc is written again.
+__device__ __forceinline__ void block_totals(const int64_t (&v)[NCNT], int64_t (&tot)[NCNT],
+                                             int64_t (*sc)[PLAN_WAVES]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k) {
+    const int64_t w = (int64_t)wave_scan64((uint64_t)v[k], lane);
+    if (lane == 63) sc[k][wave] = w;
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < NCNT; ++k) {
+    int64_t x = 0;
+#pragma unroll
+    for (int j = 0; j < PLAN_WAVES; ++j) x += sc[k][j];
+    tot[k] = uniform64(x);  // the same in every lane: scalar registers
+  }
+}
+
 // Items of a row that is not long: one single-pass item, or with resident
-// rows one per segment of 2^RES_LOG2 elements.
-__device__ __forceinline__ void row_counts(int64_t n, int64_t short_max, int tile_log2, int res_on,
-                                           int64_t (&v)[NCNT]) {
-  v[0] = long_tiles(n, short_max, tile_log2);
-  v[1] = (n > 0 && n <= short_max) ? (res_on ? (n + (int64_t(1) << RES_LOG2) - 1) >> RES_LOG2 : 1) : 0;
+// rows one per segment of 2^RES_LOG2 elements; a row of the short rows'
+// kernel (0 < n <= wave_max) has none.
+__device__ __forceinline__ void row_counts(int64_t n, const BatchArgs& a, int64_t (&v)[NCNT]) {
+  const bool wave = n > 0 && n <= a.wave_max;
+  v[0] = wave ? 0 : long_tiles(n, a.short_max, a.tile_log2);
+  v[1] = (!wave && n > 0 && n <= a.short_max) ? (a.res_on ? (n + (int64_t(1) << RES_LOG2) - 1) >> RES_LOG2 : 1) : 0;
   v[2] = v[0] > 0 ? 1 : 0;
   v[3] = v[0] > 0 ? n : 0;
 }
@@ -236,12 +270,15 @@ constexpr int PLAN_SEARCHES = 4;  // binary searches in flight per thread
 // the tables; blocks past the last round return at once (the grid is sized
 // for the workspace's row capacity, so that a captured graph fits any batch).
 //
-// Pass 1 (every block, every round): resolve and validate the round's rows
-// and count, by a block scan, their tile items, single-pass items, long rows
-// and long-row elements. A block needs the totals before its own round and
-// the grand totals, so each block scans all rounds itself (a few us per
-// round) and the blocks never wait on one another. Rows are fetched
-// PLAN_ROUNDS rounds at a time (one round trip).
+// Pass 1: resolve and validate the round's rows and count, by a block scan,
+// their tile items, single-pass items, long rows and long-row elements. A
+// block needs the totals before its own round and the grand totals. Up to
+// PLAN_SPLIT_ROWS rows of capacity each block scans all rounds itself (a few
+// us per round; rows fetched PLAN_ROUNDS rounds at a time, one round trip)
+// and the blocks never wait on one another. Above, the counting launch has
+// left every round's totals, and each block scans only its own round and
+// adds up the others' totals (every thread a share of the rounds, then the
+// block): the planner's time no longer grows with the rounds.
 //
 // Pass 2 (own round only): each short row's item and each long row's first
 // item, descriptor and start in the long rows' concatenation (one thread per
@@ -255,7 +292,50 @@ constexpr int PLAN_SEARCHES = 4;  // binary searches in flight per thread
 // that every block moves the same number of elements however the row lengths
 // fall.
 constexpr int PLAN_ROUNDS = 4;
+static_assert(PLAN_THREADS == PLAN_ROUND_ROWS, "a round is one planner block's rows");
 
+// A fetched row resolved and validated as the planner takes it: n = 0 if it
+// is invalid (error bits in e) or has more tiles than a row's combine merges.
+__device__ __forceinline__ RowDesc plan_row(const BatchArgs& a, const BatchHeader* h, const RawRow& x, int& e) {
+  RowDesc d = resolve_row(h, x, e);
+  if (long_tiles(d.n, a.short_max, a.tile_log2) > MAX_ROW_TILES) {
+    e |= NRM_DEVERR_ROW;
+    d.n = 0;
+  }
+  return d;
+}
+
+// The split planner's first launch: block b counts round b's tile items,
+// single-pass items, long rows and long-row elements and leaves the totals
+// in round_agg[4 b ..]. Errors are left to the planner, which resolves the
+// same rows again.
+__global__ void __launch_bounds__(PLAN_THREADS) batch_count_kernel(BatchArgs a) {
+  __shared__ int64_t sc[NCNT][PLAN_WAVES];
+  __shared__ BatchHeader hs;
+  const int t = threadIdx.x;
+  const int64_t own = blockIdx.x;
+  if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
+  lds_barrier();
+  const int64_t nrows = hs.nrows;
+  if (nrows < 0 || nrows > a.cap_rows) return;  // the planner reports it
+  if (own >= (nrows + PLAN_THREADS - 1) / PLAN_THREADS) return;
+  const int64_t r = own * PLAN_THREADS + t;
+  RowDesc d;
+  d.n = 0;
+  if (r < nrows) {
+    int e = 0;
+    d = plan_row(a, &hs, fetch_row(&hs, r), e);
+  }
+  int64_t v[NCNT], last[NCNT];
+  row_counts(d.n, a, v);
+  scan_counts(v, last, sc);
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < NCNT; ++k) a.round_agg[own * NCNT + k] = last[k];
+  }
+}
+
+template <bool SPLIT>
 __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   __shared__ int64_t sc[NCNT][PLAN_WAVES];
   __shared__ BatchHeader hs;
@@ -273,6 +353,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     if (own == 0 && t == 0) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
       for (int k = 0; k < CNT_DISPENSE; ++k) a.cnt[k] = 0;  // the call number stays
+      a.cnt[CNT_ROWS] = 0;
     }
     return;
   }
@@ -288,11 +369,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     d.n = 0;
     if (r >= nrows) return d;
     int e = 0;
-    d = resolve_row(h, x, e);
-    if (long_tiles(d.n, a.short_max, a.tile_log2) > MAX_ROW_TILES) {
-      e |= NRM_DEVERR_ROW;
-      d.n = 0;
-    }
+    d = plan_row(a, h, x, e);
     if (mine) {
       err |= e;
       a.rows[r] = d;
@@ -312,7 +389,29 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   int64_t c_own[NCNT] = {0, 0, 0, 0}, incl_own[NCNT] = {0, 0, 0, 0}, last_own[NCNT] = {0, 0, 0, 0};
   RowDesc d_own;
   d_own.n = 0;
-  for (int64_t q0 = 0; q0 < rounds; q0 += PLAN_ROUNDS) {
+  if constexpr (SPLIT) {
+    // the own round's rows and scan; the totals of the rounds before it and
+    // of all rounds from the counting launch (every thread sums every
+    // PLAN_THREADS-th round, then the block adds them up)
+    if (own < rounds) {
+      d_own = resolve(own, fetch(own), true);
+      row_counts(d_own.n, a, incl_own);
+      scan_counts(incl_own, last_own, sc);
+      lds_barrier();  // sc is rewritten below
+    }
+    int64_t before[NCNT] = {0, 0, 0, 0}, all[NCNT] = {0, 0, 0, 0};
+    for (int64_t q = t; q < rounds; q += PLAN_THREADS)
+#pragma unroll
+      for (int k = 0; k < NCNT; ++k) {
+        const int64_t x = a.round_agg[q * NCNT + k];
+        all[k] += x;
+        before[k] += q < own ? x : 0;
+      }
+    block_totals(before, c_own, sc);
+    lds_barrier();
+    block_totals(all, carry, sc);
+  }
+  for (int64_t q0 = 0; !SPLIT && q0 < rounds; q0 += PLAN_ROUNDS) {
     RawRow fetched[PLAN_ROUNDS];
 #pragma unroll
     for (int k = 0; k < PLAN_ROUNDS; ++k)
@@ -324,7 +423,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
         const bool mine = q == own;
         const RowDesc d = resolve(q, fetched[k], mine);
         int64_t incl[NCNT], last[NCNT];
-        row_counts(d.n, a.short_max, a.tile_log2, a.res_on, incl);
+        row_counts(d.n, a, incl);
         scan_counts(incl, last, sc);
         lds_barrier();  // sc is rewritten by the next scan
         if (mine) {
@@ -335,7 +434,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
             last_own[c] = last[c];
           }
         }
-        for (int c = 0; c < NCNT; ++c) carry[c] += last[c];
+        for (int c = 0; c < NCNT; ++c) carry[c] = uniform64(carry[c] + last[c]);  // scalar registers
       }
     }
   }
@@ -361,7 +460,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     const int64_t(&c)[NCNT] = c_own;
     const int64_t(&last)[NCNT] = last_own;
     int64_t v[NCNT];
-    row_counts(d_own.n, a.short_max, a.tile_log2, a.res_on, v);
+    row_counts(d_own.n, a, v);
     ex_tile[t] = (int32_t)(incl[0] - v[0]);  // at most PLAN_THREADS * MAX_ROW_TILES
     ex_lrow[t] = (int32_t)(incl[2] - v[2]);
     ex_elem[t] = incl[3] - v[3];
@@ -418,7 +517,9 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
     if (total > a.cap_items) {
       atomicOr(a.error, NRM_DEVERR_CAPACITY);
       for (int k = 0; k < CNT_DISPENSE; ++k) a.cnt[k] = 0;  // the call number stays
+      a.cnt[CNT_ROWS] = 0;
     } else {
+      a.cnt[CNT_ROWS] = nrows;
       a.cnt[CNT_ITEMS] = total;
       a.cnt[CNT_LONG_ITEMS] = total_long;
       a.cnt[CNT_LONG_ROWS] = n_lrows;
@@ -898,8 +999,118 @@ hipError_t phase2_acc(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- short rows, one wavefront each ----------------------------------------------------
+// A row of 0 < n <= wave_max elements (at most WAVE_MAX_ELEMS) is taken by one
+// wavefront: its head, 16-byte vectors and tail are read into registers, summed
+// in each lane's chains and across the lanes by DPP moves (no LDS, no barrier,
+// no work claim), divided from the registers and written: two HBM transfers,
+// and a wavefront never waits for another. The wavefronts walk the batch's
+// rows statically (wavefront w of W takes rows w, w + W, ...), skip the rows
+// the other kernels take, and fetch the next row's descriptor while the
+// current row streams. A row's summation order depends only on its length,
+// its start alignment and its dtypes.
+template <int DTI, int DTO, int ACC>
+__device__ __forceinline__ void wave_row(const RowDesc& d, float* lse) {
+  constexpr int VEC = Elem<DTI>::VEC;
+  constexpr int KW = (int)(WAVE_MAX_ELEMS / (64 * VEC));
+  constexpr int NA = ACC == NRM_ACC_F32 ? 8 : 4;  // chains per lane (few: registers go to the held row)
+  const int lane = threadIdx.x & 63;
+  const Geom g = geometry<DTI>(d.in, d.n);
+  const u4* body = reinterpret_cast<const u4*>(d.in + g.head * Elem<DTI>::SIZE);
+  u4 r[KW];
+#pragma unroll
+  for (int k = 0; k < KW; ++k)
+    if (lane + k * 64 < g.nvec) r[k] = load_vec<false>(body + lane + k * 64);
+  const bool has_head = lane < g.head;
+  const bool has_tail = lane < d.n - g.tail_begin;
+  const float xh = has_head ? load_one<DTI>(d.in, lane) : 0.0f;
+  const float xt = has_tail ? load_one<DTI>(d.in, g.tail_begin + lane) : 0.0f;
+  Acc<ACC> acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k].zero();
+  if constexpr (ACC == ACC_SOFTMAX) {
+    softmax_add_held<DTI, NA, KW>(acc, r, lane, 64, g.nvec);
+  } else {
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      if (lane + k * 64 < g.nvec) {
+        float x[VEC];
+        widen<DTI>(r[k], x);
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(x[c]);
+      }
+    }
+  }
+  if (has_head) acc[0].add(xh);
+  if (has_tail) acc[0].add(xt);
+  merge_chains<ACC, NA>(acc);
+  const RowMap<ACC> f = RowMap<ACC>::of(wave_reduce<ACC>(acc[0]));  // the same in every lane
+  if constexpr (ACC == ACC_SOFTMAX) {
+    if (lse && lane == 0) *lse = f.lse();
+  }
+  const bool vec_ok = out_vector_ok<DTI, DTO>(d.out, g.head);
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int64_t v = lane + k * 64;
+    if (v < g.nvec) {
+      float x[VEC], q[VEC];
+      widen<DTI>(r[k], x);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
+      store_quotients<DTI, DTO>(d.out, g.head, v, vec_ok, q);
+    }
+  }
+  if (has_head) store_one<DTO>(d.out, lane, f(xh));
+  if (has_tail) store_one<DTO>(d.out, g.tail_begin + lane, f(xt));
+}
+
+template <int ACC>
+__device__ __forceinline__ void dispatch_wave(const RowDesc& d, float* lse) {
+  if constexpr (ACC == ACC_SOFTMAX) {
+    wave_row<NRM_F32, NRM_F32, ACC>(d, lse);
+  } else {
+#define NRM_WR(I, O) wave_row<I, O, ACC>(d, lse)
+    switch (d.in_dt * 3 + d.out_dt) {
+      case NRM_F32 * 3 + NRM_F32: NRM_WR(NRM_F32, NRM_F32); break;
+      case NRM_F32 * 3 + NRM_BF16: NRM_WR(NRM_F32, NRM_BF16); break;
+      case NRM_F32 * 3 + NRM_F16: NRM_WR(NRM_F32, NRM_F16); break;
+      case NRM_BF16 * 3 + NRM_F32: NRM_WR(NRM_BF16, NRM_F32); break;
+      case NRM_BF16 * 3 + NRM_BF16: NRM_WR(NRM_BF16, NRM_BF16); break;
+      case NRM_BF16 * 3 + NRM_F16: NRM_WR(NRM_BF16, NRM_F16); break;
+      case NRM_F16 * 3 + NRM_F32: NRM_WR(NRM_F16, NRM_F32); break;
+      case NRM_F16 * 3 + NRM_BF16: NRM_WR(NRM_F16, NRM_BF16); break;
+      default: NRM_WR(NRM_F16, NRM_F16); break;
+    }
+#undef NRM_WR
+  }
+}
+
+template <int ACC>
+__global__ void __launch_bounds__(WAVE_BLOCK) batch_wave_kernel(BatchArgs a) {
+  const int64_t nrows = a.cnt[CNT_ROWS], wmax = a.wave_max;
+  float* lse = lse_out(a);
+  const int64_t W = (int64_t)gridDim.x * (WAVE_BLOCK / 64);
+  int64_t r = (int64_t)blockIdx.x * (WAVE_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (r >= nrows) return;
+  RowDesc d = a.rows[r];
+  while (true) {
+    const int64_t next = r + W;
+    RowDesc d_next = d;
+    if (next < nrows) d_next = a.rows[next];
+    if (d.n > 0 && d.n <= wmax) dispatch_wave<ACC>(d, lse ? lse + r : nullptr);
+    if (next >= nrows) break;
+    r = next;
+    d = d_next;
+  }
+}
+
 template <int ACC>
 hipError_t launch_phases(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
+  if (p.wave_grid > 0) {
+    hipLaunchKernelGGL((batch_wave_kernel<ACC>), dim3((unsigned)p.wave_grid), dim3(WAVE_BLOCK), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (p.res_grid > 0) {
     hipLaunchKernelGGL((batch_resident_kernel<ACC>), dim3((unsigned)p.res_grid), dim3(RES_BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
@@ -1033,8 +1244,16 @@ hipError_t launch_batch(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
   // one block per round of the workspace's row capacity (blocks past the
   // batch's last round return at once)
   const int64_t plan_blocks = (a.cap_rows + PLAN_THREADS - 1) / PLAN_THREADS;
-  hipLaunchKernelGGL(batch_plan_kernel, dim3((unsigned)(plan_blocks > 0 ? plan_blocks : 1)), dim3(PLAN_THREADS), 0, s,
-                     a);
+  const dim3 plan_grid((unsigned)(plan_blocks > 0 ? plan_blocks : 1));
+  if (a.split_plan) {
+    hipLaunchKernelGGL(batch_count_kernel, plan_grid, dim3(PLAN_THREADS), 0, s, a);
+    const hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+  }
+  if (a.split_plan)
+    hipLaunchKernelGGL(batch_plan_kernel<true>, plan_grid, dim3(PLAN_THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL(batch_plan_kernel<false>, plan_grid, dim3(PLAN_THREADS), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (p.acc) {

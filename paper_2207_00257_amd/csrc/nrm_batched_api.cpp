@@ -54,6 +54,9 @@ nrm_batch_params default_batch_params() {
   // their read and their write; two 512-thread blocks per CU
   p.resident_segments = 64;
   p.resident_grid = 512;
+  // rows of up to 2048 elements one per wavefront, 16 wavefronts per CU
+  p.wave_max = 2048;
+  p.wave_grid = 1024;
   return p;
 }
 
@@ -75,6 +78,8 @@ int check_batch_params(const nrm_batch_params& p) {
   // able to hold a whole row's segments in running blocks at once
   if (p.resident_grid < p.resident_segments)
     return fail(NRM_EINVAL, "resident_grid must be at least resident_segments");
+  if (p.wave_max < 0 || p.wave_max > nrm::WAVE_MAX_ELEMS) return fail(NRM_EINVAL, "wave_max must be 0..2048");
+  if (p.wave_grid < 1 || p.wave_grid > (1 << 20)) return fail(NRM_EINVAL, "wave_grid must be 1..2^20");
   // a tile's per-thread summation tree must stay within the plain path's
   // height bound (36) for every input dtype: 4-byte elements give the most
   // iterations, 2-byte elements the most additions per iteration
@@ -110,7 +115,8 @@ void destroy_graph(BatchWorkspace& w) {
 
 // Layout of the single device allocation.
 struct Layout {
-  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, small, partials, tagged, rowtot, arrivals, total;
+  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, round_agg, small, partials, tagged, rowtot, arrivals,
+      total;
 };
 
 // Phase-2 chunks a workspace holds beyond one per item: the planner sizes the
@@ -132,6 +138,7 @@ Layout layout_for(int64_t cap_rows, int64_t cap_items, int64_t cap_chunks) {
   L.lstart = take(sizeof(int64_t) * cap_rows);
   L.lsum = take(sizeof(nrm::RowRes) * cap_rows);
   L.chunk_lrow = take(sizeof(int32_t) * cap_chunks);
+  L.round_agg = take(sizeof(int64_t) * 4 * (size_t)ceil_div(cap_rows, nrm::PLAN_ROUND_ROWS));
   L.small = take(kSmallBytes);  // the planner's counters, then the error word
   L.partials = take(8 * cap_items);
   L.tagged = take(16 * cap_items);
@@ -200,6 +207,7 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   w.lstart = reinterpret_cast<int64_t*>(d + L.lstart);
   w.lsum = reinterpret_cast<nrm::RowRes*>(d + L.lsum);
   w.chunk_lrow = reinterpret_cast<int32_t*>(d + L.chunk_lrow);
+  w.round_agg = reinterpret_cast<int64_t*>(d + L.round_agg);
   w.cnt = reinterpret_cast<int64_t*>(d + L.small);
   w.error = reinterpret_cast<int*>(d + L.small + kErrorOffset);
   w.partials = d + L.partials;
@@ -259,6 +267,9 @@ BatchArgs args_of(const nrm_ctx* c, int buf) {
   a.tagged = w.tagged;
   a.rowtot = w.rowtot;
   a.arrivals = w.arrivals;
+  a.wave_max = c->bparams.wave_max;
+  a.split_plan = w.cap_rows > nrm::PLAN_SPLIT_ROWS;
+  a.round_agg = w.round_agg;
   return a;
 }
 
@@ -273,6 +284,7 @@ BatchPlan plan_of(const nrm_ctx* c, int acc) {
   p.map_block = c->bparams.map_block;
   p.map_grid = c->bparams.map_grid;
   p.res_grid = c->bparams.resident_segments > 0 ? c->bparams.resident_grid : 0;
+  p.wave_grid = c->bparams.wave_max > 0 ? c->bparams.wave_grid : 0;
   return p;
 }
 

@@ -64,6 +64,7 @@ struct BatchWorkspace {
   int64_t* lstart = nullptr;
   RowRes* lsum = nullptr;
   int32_t* chunk_lrow = nullptr;
+  int64_t* round_agg = nullptr;
   int64_t* cnt = nullptr;
   int* error = nullptr;
   void* partials = nullptr;

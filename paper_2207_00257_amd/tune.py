@@ -183,9 +183,11 @@ def sweep(n: int, in_dtype="f32", out_dtype="f32", accum="f32", reps=5, quick=Fa
 def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
     """Sweep the batched path's launch shape on the ragged workload (rows with
     log-uniform lengths in [32, 2^20], LogNormal(0,1) FP32), timing whole
-    calls (planner, resident rows, tile phases) with the library's events:
-    first the resident rows' limit and grid, then, when some row of the
-    workload is longer than that limit, the tile phases' shapes."""
+    calls (planner, short rows, resident rows, tile phases) with the
+    library's events: first the resident rows' limit and grid, then the
+    short rows' (one per wavefront) limit and grid, then, when some row of
+    the workload is longer than the resident limit, the tile phases'
+    shapes."""
     import torch
 
     from . import api, synth
@@ -221,6 +223,17 @@ def sweep_batched(rows=4096, seed=4, reps=3, quick=False, log=print):
     for segs in ((0, 64) if quick else (0, 16, 32, 64)):
         for gmul in ((2,) if quick else (1, 1.5, 2)):
             p = dict(base_p, resident_segments=segs, resident_grid=max(segs, int(cus * gmul)))
+            ms = measure(p)
+            if ms is None:
+                continue
+            table.append({"kernel": "batched", "params": p, "ms": ms})
+            if ms < best_t:
+                best, best_t = p, ms
+    # rows per wavefront: rows up to wave_max elements one per wavefront (0:
+    # none), and that kernel's grid
+    for wmax in ((0, 2048) if quick else (0, 256, 1024, 2048)):
+        for gmul in ((4,) if quick or wmax == 0 else (2, 4, 8)):
+            p = dict(best, wave_max=wmax, wave_grid=cus * gmul)
             ms = measure(p)
             if ms is None:
                 continue

@@ -74,10 +74,15 @@ BATCH_PARAMS = [
     dict(keep_mib=0),                   # every tile non-temporal
     dict(keep_mib=1, tile_log2=10),     # the last 256 tiles temporal, the rest not
     dict(keep_mib=4096, graph=1),       # every tile temporal
-    dict(resident_segments=0),          # single-pass rows and tiles only
-    dict(resident_segments=1, resident_grid=3),   # one-segment resident rows, the rest tiled
+    dict(resident_segments=0, wave_max=0),  # single-pass rows and tiles only
+    dict(resident_segments=0),          # short rows one per wavefront, single-pass rows and tiles
+    dict(resident_segments=1, resident_grid=3, wave_max=0),  # one-segment resident rows, the rest tiled
     dict(resident_segments=3, resident_grid=5, graph=1),
     dict(resident_segments=64, resident_grid=64, tile_log2=11),
+    dict(wave_max=0),                   # no short rows' kernel: resident rows down to n = 1
+    dict(wave_max=1, wave_grid=1),      # one block of four wavefronts, rows of one element only
+    dict(wave_max=100, wave_grid=3, graph=1),
+    dict(wave_max=2048, wave_grid=5000),  # more wavefronts than rows
 ]
 
 
@@ -101,7 +106,8 @@ def test_batch_parameter_validation():
     for bad in (dict(block=96), dict(map_block=2048), dict(unroll=3), dict(map_unroll=16), dict(short_regs=0),
                 dict(grid=0), dict(map_grid=0), dict(tile_log2=9), dict(tile_log2=23), dict(graph=2),
                 dict(keep_mib=-1), dict(keep_mib=4097), dict(resident_segments=-1), dict(resident_segments=65),
-                dict(resident_segments=4, resident_grid=0), dict(resident_segments=8, resident_grid=4)):
+                dict(resident_segments=4, resident_grid=0), dict(resident_segments=8, resident_grid=4),
+                dict(wave_max=-1), dict(wave_max=2049), dict(wave_grid=0), dict(wave_grid=(1 << 20) + 1)):
         with pytest.raises(L.NrmError):
             ctx.set_batch_params(**bad)
         assert ctx.get_batch_params() == good, bad
@@ -181,10 +187,12 @@ def test_bad_offsets_are_flagged_and_skipped():
     ctx.close()
 
 
-def test_bad_rows_in_later_planner_rounds():
+@pytest.mark.parametrize("reserve", [0, 20000], ids=["one_launch_planner", "split_planner"])
+def test_bad_rows_in_later_planner_rounds(reserve):
     """Each round of 1024 rows is planned by its own block: invalid rows in
     rounds 1 and 3 are flagged and skipped by their owners while every valid
-    row of every round is computed."""
+    row of every round is computed. With room for more than 4096 rows the
+    planner is split (a counting launch first); the result is the same."""
     lengths = synth.loguniform_lengths(3100, 95, 1, 3000)
     lengths[[7, 2049, 3098]] = [70_000, 50_000, 90_000]  # long rows in rounds 0, 2 and 3
     offs = synth.ragged_offsets(lengths)
@@ -193,6 +201,8 @@ def test_bad_rows_in_later_planner_rounds():
     bad[1500] = -5          # row 1499 ends before it starts, row 1500 starts below zero
     bad[3080] = x.size + 9  # row 3079 ends past the buffer, row 3080 starts past its end
     ctx = api.Context()
+    if reserve:
+        ctx.batch_reserve(reserve, x.size)
     got = run_csr(x, bad, ctx).cpu().numpy()
     assert ctx.device_error() == L.NRM_EDEVICE
     assert ctx.device_error() == L.NRM_OK  # cleared
@@ -464,4 +474,121 @@ def test_back_to_back_calls_do_not_block_the_host():
     for t in outs:
         assert_f32_close(t.cpu().numpy(), ref, what="back-to-back call")
     assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_split_planner_same_bits_as_one_launch_planner(graph):
+    """The same 3000-row batch planned in one launch (room for 4096 rows) and
+    by the split planner (room for 50000 rows): identical bits, and the
+    oracle's values within the bound."""
+    lengths = synth.loguniform_lengths(3000, 160, 1, 1 << 16)
+    lengths[::9] = 0
+    lengths[5::97] = 300_000  # long rows, tiled
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 161, 1.0)
+    outs = []
+    for cap in (4096, 50000):
+        ctx = api.Context()
+        ctx.set_batch_params(graph=graph)
+        ctx.batch_reserve(cap, x.size)
+        outs.append(run_csr(x, offs, ctx).cpu().numpy())
+        assert ctx.device_error() == L.NRM_OK
+        ctx.close()
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    check_rows(outs[1], x, offs, "split planner")
+
+
+def test_hundred_thousand_short_rows():
+    """A batch of 100000 rows, lengths log-uniform in [1, 3000] (most taken
+    one per wavefront, the rest resident), some empty and some long: every
+    row against the oracle, through a replayed graph."""
+    lengths = synth.loguniform_lengths(100_000, 162, 1, 3000)
+    lengths[::31] = 0
+    lengths[17::5003] = 200_000
+    offs = synth.ragged_offsets(lengths)
+    x = synth.lognormal_f32(int(offs[-1]), 163, 1.0)
+    ctx = api.Context()
+    ctx.set_batch_params(graph=1)
+    ctx.batch_reserve(lengths.size, x.size)
+    for _ in range(2):  # the second call replays the graph
+        got = run_csr(x, offs, ctx).cpu().numpy()
+        check_rows(got, x, offs, "100000 rows")
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+WAVE_LENGTHS = [1, 2, 3, 31, 32, 33, 63, 64, 65, 255, 256, 257, 1000, 2047, 2048, 2049, 0, 5]
+
+
+@pytest.mark.parametrize("shift", [0, 1, 3, 17])
+@pytest.mark.parametrize("accum", ["f32", "kahan"])
+def test_wave_rows_lengths_and_alignments(shift, accum):
+    """Rows around the wavefront path's limits (one vector per lane, the
+    2048-element cap and one past it), every start alignment within a line
+    through the shift; then the same with wave_max = 100 (rows above it take
+    the resident path): all within the bound of the oracle."""
+    lengths = np.array(WAVE_LENGTHS, np.int64)
+    offs = synth.ragged_offsets(lengths) + shift
+    x = synth.lognormal_f32(int(offs[-1]), 164 + shift, 1.0)
+    for wave_max in (2048, 100):
+        ctx = api.Context()
+        ctx.set_batch_params(wave_max=wave_max)
+        got = run_csr(x, offs, ctx, accum=accum).cpu().numpy()
+        check_rows(got, x, offs, "wave_max=%d shift=%d %s" % (wave_max, shift, accum))
+        assert ctx.device_error() == L.NRM_OK
+        ctx.close()
+
+
+def test_wave_rows_every_dtype_pair():
+    """Row-table rows of the wavefront path in every input/output dtype pair,
+    at lengths from 1 to 2048: FP32 outputs within the stated bound, BF16 and
+    FP16 outputs within one ulp of the oracle's rounded value."""
+    from parity_util import ulp_f16
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+    pairs, checks = [], []
+    seed = 170
+    for di in ("f32", "bf16", "f16"):
+        for do in ("f32", "bf16", "f16"):
+            for n in (1, 7, 64, 333, 2048):
+                seed += 1
+                v = synth.lognormal_f32(n, seed, 1.0)
+                if di == "f32":
+                    host = v
+                elif di == "bf16":
+                    host = synth.f32_to_bf16_bits(v)
+                else:
+                    host = synth.f32_to_f16_bits(v)
+                inp = gpu(host.view(np.int16) if di != "f32" else host)
+                if di != "f32":
+                    inp = inp.view(tdt[di])
+                out = torch.empty(n, dtype=tdt[do], device=DEV)
+                pairs.append((out, inp))
+                checks.append((out, oracle.normalize(host, di), "%s->%s n=%d" % (di, do, n), do))
+    ctx = api.Context()
+    ctx.normalize_rows(pairs)
+    torch.cuda.synchronize()
+    for out, ref, what, do in checks:
+        if do == "f32":
+            assert_f32_close(out.cpu().numpy(), ref, what=what)
+        elif do == "bf16":
+            got = bf16_bits_to_f64(out.view(torch.int16).cpu().numpy().view(np.uint16))
+            assert_within_ulp(got, ref, ulp_bf16, what=what)
+        else:
+            assert_within_ulp(out.cpu().numpy().astype(np.float64), ref, ulp_f16, what=what)
+    assert ctx.device_error() == L.NRM_OK
+    ctx.close()
+
+
+def test_wave_row_is_position_independent():
+    """A row of the wavefront path gives the same bits alone and at another
+    place (same 128-byte alignment) in a batch of other rows."""
+    ctx = api.Context()
+    row = synth.lognormal_f32(1500, 180, 1.0)
+    alone = run_csr(row, np.array([0, row.size], np.int64), ctx).cpu().numpy()
+    filler = synth.lognormal_f32(32 * 77, 181, 1.0)
+    x = np.concatenate([filler, row, filler])
+    offs = np.array([0, 5, filler.size, filler.size + row.size, x.size], np.int64)
+    got = run_csr(x, offs, ctx).cpu().numpy()
+    assert np.array_equal(got[filler.size:filler.size + row.size].view(np.uint32), alone.view(np.uint32))
     ctx.close()

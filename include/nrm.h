@@ -156,10 +156,11 @@ typedef struct {
                                 at least resident_segments: a row's blocks wait for each other, so the
                                 device must be able to run that many of them at once (two per CU fit) */
   int32_t wave_max;          /* 0..2048: a row of 0 < n <= wave_max elements is taken by one wavefront
-                                (64 lanes): read into registers, summed across the lanes by DPP moves
-                                with no LDS, barrier or work claim, divided from the registers and
-                                written (two HBM transfers). 0: off (such rows take the resident or
-                                single-pass path) */
+                                (64 lanes), or for n <= 256 by a quarter of one (16 lanes, four such
+                                rows per wavefront at once): read into registers, summed across the
+                                lanes by DPP moves with no LDS, barrier or work claim, divided from
+                                the registers and written (two HBM transfers). 0: off (such rows take
+                                the resident or single-pass path) */
   int32_t wave_grid;         /* 256-thread blocks of the short rows' kernel, 1..2^20; its W wavefronts
                                 take the rows statically (wavefront w: rows w, w + W, ...) */
 } nrm_batch_params;

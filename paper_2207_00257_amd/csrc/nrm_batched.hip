@@ -17,7 +17,8 @@
 //                        long rows' descriptors and starts, and of phase 2's
 //                        chunk table.
 //   batch_wave_kernel    rows of 0 < n <= wave_max (at most 2048) elements,
-//                        one per wavefront, statically: read into registers,
+//                        one per wavefront (four per wavefront, 16 lanes
+//                        each, up to 256), statically: read into registers,
 //                        summed across the lanes, divided and written, with
 //                        no barrier and no work claim.
 //   batch_resident_kernel  rows of up to 2^20 elements held on chip in
@@ -1085,19 +1086,133 @@ __device__ __forceinline__ void dispatch_wave(const RowDesc& d, float* lse) {
   }
 }
 
+// Rows of at most WAVE_QUARTER_MAX elements go four to a wavefront: each
+// row of 16 lanes (a DPP row) takes one, so four such rows are in flight
+// per wavefront instead of one. The head before the first 16-byte boundary
+// (fewer than one vector) and the tail are one element per lane; each lane
+// holds at most WAVE_QUARTER_MAX / (16 VEC) vectors; the sum is the 16
+// lanes' chains merged by row16_reduce, in every lane of the row.
+constexpr int64_t WAVE_QUARTER_MAX = 256;
+
+template <int DTI, int DTO, int ACC>
+__device__ __forceinline__ void quarter_row(const RowDesc& d, float* lse) {
+  constexpr int VEC = Elem<DTI>::VEC, SI = Elem<DTI>::SIZE;
+  constexpr int KQ = (int)(WAVE_QUARTER_MAX / (16 * VEC));
+  constexpr int NA = ACC == NRM_ACC_F32 ? 8 : 4;
+  const int j = threadIdx.x & 15;
+  const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(d.in) & 15);
+  int64_t head = mis ? (16 - mis) / SI : 0;
+  if (head > d.n) head = d.n;
+  const int64_t nvec = (d.n - head) / VEC, tail_begin = head + nvec * VEC;
+  const u4* body = reinterpret_cast<const u4*>(d.in + head * SI);
+  u4 r[KQ];
+#pragma unroll
+  for (int k = 0; k < KQ; ++k)
+    if (j + k * 16 < nvec) r[k] = load_vec<false>(body + j + k * 16);
+  const bool has_head = j < head;
+  const bool has_tail = j < d.n - tail_begin;
+  const float xh = has_head ? load_one<DTI>(d.in, j) : 0.0f;
+  const float xt = has_tail ? load_one<DTI>(d.in, tail_begin + j) : 0.0f;
+  Acc<ACC> acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k].zero();
+  if constexpr (ACC == ACC_SOFTMAX) {
+    softmax_add_held<DTI, NA, KQ>(acc, r, j, 16, nvec);
+  } else {
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      if (j + k * 16 < nvec) {
+        float x[VEC];
+        widen<DTI>(r[k], x);
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) acc[(k * VEC + c) % NA].add(x[c]);
+      }
+    }
+  }
+  if (has_head) acc[0].add(xh);
+  if (has_tail) acc[0].add(xt);
+  merge_chains<ACC, NA>(acc);
+  const RowMap<ACC> f = RowMap<ACC>::of(row16_reduce<ACC>(acc[0]));  // the same in the row's 16 lanes
+  if constexpr (ACC == ACC_SOFTMAX) {
+    if (lse && j == 0) *lse = f.lse();
+  }
+  const bool vec_ok = out_vector_ok<DTI, DTO>(d.out, head);
+#pragma unroll
+  for (int k = 0; k < KQ; ++k) {
+    const int64_t v = j + k * 16;
+    if (v < nvec) {
+      float x[VEC], q[VEC];
+      widen<DTI>(r[k], x);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
+      store_quotients<DTI, DTO>(d.out, head, v, vec_ok, q);
+    }
+  }
+  if (has_head) store_one<DTO>(d.out, j, f(xh));
+  if (has_tail) store_one<DTO>(d.out, tail_begin + j, f(xt));
+}
+
+// A row of each 16-lane group: the dtype switch may differ between the
+// groups (row tables), never within one.
+template <int ACC>
+__device__ __forceinline__ void dispatch_quarter(const RowDesc& d, float* lse) {
+  if constexpr (ACC == ACC_SOFTMAX) {
+    quarter_row<NRM_F32, NRM_F32, ACC>(d, lse);
+  } else {
+#define NRM_QR(I, O) quarter_row<I, O, ACC>(d, lse)
+    switch (d.in_dt * 3 + d.out_dt) {
+      case NRM_F32 * 3 + NRM_F32: NRM_QR(NRM_F32, NRM_F32); break;
+      case NRM_F32 * 3 + NRM_BF16: NRM_QR(NRM_F32, NRM_BF16); break;
+      case NRM_F32 * 3 + NRM_F16: NRM_QR(NRM_F32, NRM_F16); break;
+      case NRM_BF16 * 3 + NRM_F32: NRM_QR(NRM_BF16, NRM_F32); break;
+      case NRM_BF16 * 3 + NRM_BF16: NRM_QR(NRM_BF16, NRM_BF16); break;
+      case NRM_BF16 * 3 + NRM_F16: NRM_QR(NRM_BF16, NRM_F16); break;
+      case NRM_F16 * 3 + NRM_F32: NRM_QR(NRM_F16, NRM_F32); break;
+      case NRM_F16 * 3 + NRM_BF16: NRM_QR(NRM_F16, NRM_BF16); break;
+      default: NRM_QR(NRM_F16, NRM_F16); break;
+    }
+#undef NRM_QR
+  }
+}
+
+// Two static walks, one after the other (their registers are not live at
+// once): wavefront w of W first takes the groups of four consecutive rows
+// 4w, 4(w + W), ..., and runs the group's rows of at most WAVE_QUARTER_MAX
+// elements, each on its 16 lanes, all at once; then it takes rows w, w + W,
+// ... and runs those of WAVE_QUARTER_MAX < n <= wave_max elements on the
+// whole wavefront. Each walk fetches its next descriptors while the current
+// rows stream.
 template <int ACC>
 __global__ void __launch_bounds__(WAVE_BLOCK) batch_wave_kernel(BatchArgs a) {
   const int64_t nrows = a.cnt[CNT_ROWS], wmax = a.wave_max;
   float* lse = lse_out(a);
+  const int grp = (threadIdx.x & 63) >> 4;
   const int64_t W = (int64_t)gridDim.x * (WAVE_BLOCK / 64);
-  int64_t r = (int64_t)blockIdx.x * (WAVE_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (r >= nrows) return;
+  const int64_t w = (int64_t)blockIdx.x * (WAVE_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (4 * w < nrows) {
+    int64_t g = 4 * w;
+    RowDesc d;
+    d.n = 0;
+    if (g + grp < nrows) d = a.rows[g + grp];
+    while (true) {
+      const int64_t next = g + 4 * W;
+      RowDesc d_next;
+      d_next.n = 0;
+      if (next + grp < nrows) d_next = a.rows[next + grp];
+      if (d.n > 0 && d.n <= WAVE_QUARTER_MAX && d.n <= wmax) dispatch_quarter<ACC>(d, lse ? lse + g + grp : nullptr);
+      if (next >= nrows) break;
+      g = next;
+      d = d_next;
+    }
+  }
+  if (wmax <= WAVE_QUARTER_MAX || w >= nrows) return;
+  int64_t r = w;
   RowDesc d = a.rows[r];
   while (true) {
     const int64_t next = r + W;
     RowDesc d_next = d;
     if (next < nrows) d_next = a.rows[next];
-    if (d.n > 0 && d.n <= wmax) dispatch_wave<ACC>(d, lse ? lse + r : nullptr);
+    if (d.n > WAVE_QUARTER_MAX && d.n <= wmax) dispatch_wave<ACC>(d, lse ? lse + r : nullptr);
     if (next >= nrows) break;
     r = next;
     d = d_next;

@@ -235,22 +235,21 @@ constexpr int QP_SWAP2 = 0x4E;       // quad_perm [2,3,0,1]
 constexpr int ROW_HALF_MIRROR = 0x141;
 constexpr int ROW_MIRROR = 0x140;
 
-// Sum over the 64 lanes of a wavefront. Within each row of 16 lanes, four DPP
-// steps (pair, quad, half-row mirror, row mirror) leave the row sum in every
-// lane of the row (each step adds a lane's value to its partner's, and
-// addition is commutative, so partners hold identical bits). The four row
-// sums are then combined as (r0 + r1) + (r2 + r3). Every lane returns it.
+// Sum over each row of 16 lanes: four DPP steps (pair, quad, half-row
+// mirror, row mirror) leave the row's sum in every lane of the row, with
+// identical bits in all of them (each step adds a lane's value to its
+// partner's, and the merges are symmetric in their operands). Lanes read
+// only lanes of their own row, so a row whose 16 lanes are all active may
+// run it while other rows of the wavefront are inactive.
 template <int ACC>
-__device__ __forceinline__ Acc<ACC> wave_reduce(Acc<ACC> a) {
+__device__ __forceinline__ Acc<ACC> row16_reduce(Acc<ACC> a) {
   if constexpr (ACC == NRM_ACC_F32) {
     float v = a.s;
     v = v + dpp<QP_SWAP1>(v);
     v = v + dpp<QP_SWAP2>(v);
     v = v + dpp<ROW_HALF_MIRROR>(v);
     v = v + dpp<ROW_MIRROR>(v);
-    Acc<ACC> r;
-    r.s = (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
-    return r;
+    a.s = v;
   } else if constexpr (ACC == ACC_SOFTMAX) {
     // the merge is symmetric in its operands (a maximum and a sum of two
     // exactly rescaled terms), so partner lanes again hold identical bits
@@ -259,6 +258,30 @@ __device__ __forceinline__ Acc<ACC> wave_reduce(Acc<ACC> a) {
     o.k = dpp<QP_SWAP2>(a.k); o.s = dpp<QP_SWAP2>(a.s); a.merge(o);
     o.k = dpp<ROW_HALF_MIRROR>(a.k); o.s = dpp<ROW_HALF_MIRROR>(a.s); a.merge(o);
     o.k = dpp<ROW_MIRROR>(a.k); o.s = dpp<ROW_MIRROR>(a.s); a.merge(o);
+  } else {
+    // TwoSum-based merge is symmetric in its operands (both the sum and the
+    // exact error term are), so partner lanes again hold identical bits.
+    Acc<ACC> o;
+    o.hi = dpp<QP_SWAP1>(a.hi); o.lo = dpp<QP_SWAP1>(a.lo); a.merge(o);
+    o.hi = dpp<QP_SWAP2>(a.hi); o.lo = dpp<QP_SWAP2>(a.lo); a.merge(o);
+    o.hi = dpp<ROW_HALF_MIRROR>(a.hi); o.lo = dpp<ROW_HALF_MIRROR>(a.lo); a.merge(o);
+    o.hi = dpp<ROW_MIRROR>(a.hi); o.lo = dpp<ROW_MIRROR>(a.lo); a.merge(o);
+  }
+  return a;
+}
+
+// Sum over the 64 lanes of a wavefront: each row of 16 lanes by
+// row16_reduce, then the four row sums combined as (r0 + r1) + (r2 + r3).
+// Every lane returns it.
+template <int ACC>
+__device__ __forceinline__ Acc<ACC> wave_reduce(Acc<ACC> a) {
+  a = row16_reduce<ACC>(a);
+  if constexpr (ACC == NRM_ACC_F32) {
+    const float v = a.s;
+    Acc<ACC> r;
+    r.s = (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+    return r;
+  } else if constexpr (ACC == ACC_SOFTMAX) {
     Acc<ACC> r0, r1, r2, r3;
     r0.k = readlane(a.k, 0); r0.s = readlane(a.s, 0);
     r1.k = readlane(a.k, 16); r1.s = readlane(a.s, 16);
@@ -269,13 +292,6 @@ __device__ __forceinline__ Acc<ACC> wave_reduce(Acc<ACC> a) {
     r0.merge(r2);
     return r0;
   } else {
-    // TwoSum-based merge is symmetric in its operands (both the sum and the
-    // exact error term are), so partner lanes again hold identical bits.
-    Acc<ACC> o;
-    o.hi = dpp<QP_SWAP1>(a.hi); o.lo = dpp<QP_SWAP1>(a.lo); a.merge(o);
-    o.hi = dpp<QP_SWAP2>(a.hi); o.lo = dpp<QP_SWAP2>(a.lo); a.merge(o);
-    o.hi = dpp<ROW_HALF_MIRROR>(a.hi); o.lo = dpp<ROW_HALF_MIRROR>(a.lo); a.merge(o);
-    o.hi = dpp<ROW_MIRROR>(a.hi); o.lo = dpp<ROW_MIRROR>(a.lo); a.merge(o);
     Acc<ACC> r0, r1, r2, r3;
     r0.hi = readlane(a.hi, 0); r0.lo = readlane(a.lo, 0);
     r1.hi = readlane(a.hi, 16); r1.lo = readlane(a.lo, 16);

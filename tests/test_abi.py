@@ -292,3 +292,39 @@ def test_binding_signatures_match_the_header(lib):
         assert want == got, (name, protos[name], got)
         checked += 1
     assert checked >= 35, checked  # every function the binding declares
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """Every public struct the Python binding declares has the size and field
+    offsets that a C compiler gives it from include/nrm.h."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"nrm_params": L.NrmParams, "nrm_batch_params": L.NrmBatchParams, "nrm_row": L.NrmRow,
+               "nrm_request": L.NrmRequest, "nrm_completion": L.NrmCompletion,
+               "nrm_server_config": L.NrmServerConfig, "nrm_server_counters": L.NrmServerCounters}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "nrm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            cf = fname.rstrip("_")
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, cf))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", include, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

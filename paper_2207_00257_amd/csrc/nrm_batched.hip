@@ -1094,34 +1094,62 @@ __device__ __forceinline__ void dispatch_wave(const RowDesc& d, float* lse) {
 // lanes' chains merged by row16_reduce, in every lane of the row.
 constexpr int64_t WAVE_QUARTER_MAX = 256;
 
+// What a row of 16 lanes holds of its row between its loads and the rest,
+// so that a wavefront's next group of rows can be loaded while the current
+// one is summed and written: at most four 16-byte vectors per lane, and the
+// lane's head and tail elements.
+struct QuarterHeld {
+  u4 r[4];
+  float xh, xt;
+};
+static_assert(WAVE_QUARTER_MAX / (16 * 4) <= 4, "a lane holds at most four vectors");
+
+template <int DTI>
+struct QuarterGeom {
+  int64_t head, nvec, tail_begin;
+  __device__ __forceinline__ explicit QuarterGeom(const RowDesc& d) {
+    const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(d.in) & 15);
+    head = mis ? (16 - mis) / Elem<DTI>::SIZE : 0;
+    if (head > d.n) head = d.n;
+    nvec = (d.n - head) / Elem<DTI>::VEC;
+    tail_begin = head + nvec * Elem<DTI>::VEC;
+  }
+};
+
+template <int DTI>
+__device__ __forceinline__ void quarter_load(const RowDesc& d, QuarterHeld& q) {
+  constexpr int KQ = (int)(WAVE_QUARTER_MAX / (16 * Elem<DTI>::VEC));
+  const int j = threadIdx.x & 15;
+  const QuarterGeom<DTI> g(d);
+  const u4* body = reinterpret_cast<const u4*>(d.in + g.head * Elem<DTI>::SIZE);
+#pragma unroll
+  for (int k = 0; k < KQ; ++k)
+    if (j + k * 16 < g.nvec) q.r[k] = load_vec<false>(body + j + k * 16);
+  q.xh = j < g.head ? load_one<DTI>(d.in, j) : 0.0f;
+  q.xt = j < d.n - g.tail_begin ? load_one<DTI>(d.in, g.tail_begin + j) : 0.0f;
+}
+
 template <int DTI, int DTO, int ACC>
-__device__ __forceinline__ void quarter_row(const RowDesc& d, float* lse) {
-  constexpr int VEC = Elem<DTI>::VEC, SI = Elem<DTI>::SIZE;
+__device__ __forceinline__ void quarter_finish(const RowDesc& d, const QuarterHeld& q, float* lse) {
+  constexpr int VEC = Elem<DTI>::VEC;
   constexpr int KQ = (int)(WAVE_QUARTER_MAX / (16 * VEC));
   constexpr int NA = ACC == NRM_ACC_F32 ? 8 : 4;
   const int j = threadIdx.x & 15;
-  const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(d.in) & 15);
-  int64_t head = mis ? (16 - mis) / SI : 0;
-  if (head > d.n) head = d.n;
-  const int64_t nvec = (d.n - head) / VEC, tail_begin = head + nvec * VEC;
-  const u4* body = reinterpret_cast<const u4*>(d.in + head * SI);
+  const QuarterGeom<DTI> g(d);
+  const bool has_head = j < g.head;
+  const bool has_tail = j < d.n - g.tail_begin;
   u4 r[KQ];
 #pragma unroll
-  for (int k = 0; k < KQ; ++k)
-    if (j + k * 16 < nvec) r[k] = load_vec<false>(body + j + k * 16);
-  const bool has_head = j < head;
-  const bool has_tail = j < d.n - tail_begin;
-  const float xh = has_head ? load_one<DTI>(d.in, j) : 0.0f;
-  const float xt = has_tail ? load_one<DTI>(d.in, tail_begin + j) : 0.0f;
+  for (int k = 0; k < KQ; ++k) r[k] = q.r[k];
   Acc<ACC> acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k].zero();
   if constexpr (ACC == ACC_SOFTMAX) {
-    softmax_add_held<DTI, NA, KQ>(acc, r, j, 16, nvec);
+    softmax_add_held<DTI, NA, KQ>(acc, r, j, 16, g.nvec);
   } else {
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
-      if (j + k * 16 < nvec) {
+      if (j + k * 16 < g.nvec) {
         float x[VEC];
         widen<DTI>(r[k], x);
 #pragma unroll
@@ -1129,37 +1157,44 @@ __device__ __forceinline__ void quarter_row(const RowDesc& d, float* lse) {
       }
     }
   }
-  if (has_head) acc[0].add(xh);
-  if (has_tail) acc[0].add(xt);
+  if (has_head) acc[0].add(q.xh);
+  if (has_tail) acc[0].add(q.xt);
   merge_chains<ACC, NA>(acc);
   const RowMap<ACC> f = RowMap<ACC>::of(row16_reduce<ACC>(acc[0]));  // the same in the row's 16 lanes
   if constexpr (ACC == ACC_SOFTMAX) {
     if (lse && j == 0) *lse = f.lse();
   }
-  const bool vec_ok = out_vector_ok<DTI, DTO>(d.out, head);
+  const bool vec_ok = out_vector_ok<DTI, DTO>(d.out, g.head);
 #pragma unroll
   for (int k = 0; k < KQ; ++k) {
     const int64_t v = j + k * 16;
-    if (v < nvec) {
-      float x[VEC], q[VEC];
+    if (v < g.nvec) {
+      float x[VEC], qv[VEC];
       widen<DTI>(r[k], x);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) q[c] = f(x[c]);
-      store_quotients<DTI, DTO>(d.out, head, v, vec_ok, q);
+      for (int c = 0; c < VEC; ++c) qv[c] = f(x[c]);
+      store_quotients<DTI, DTO>(d.out, g.head, v, vec_ok, qv);
     }
   }
-  if (has_head) store_one<DTO>(d.out, j, f(xh));
-  if (has_tail) store_one<DTO>(d.out, tail_begin + j, f(xt));
+  if (has_head) store_one<DTO>(d.out, j, f(q.xh));
+  if (has_tail) store_one<DTO>(d.out, g.tail_begin + j, f(q.xt));
 }
 
-// A row of each 16-lane group: the dtype switch may differ between the
-// groups (row tables), never within one.
+// The dtype switches of a row of each 16-lane group: they may differ between
+// the groups (row tables), never within one.
 template <int ACC>
-__device__ __forceinline__ void dispatch_quarter(const RowDesc& d, float* lse) {
+__device__ __forceinline__ void dispatch_quarter_load(const RowDesc& d, QuarterHeld& q) {
+  if (ACC == ACC_SOFTMAX || d.in_dt == NRM_F32) quarter_load<NRM_F32>(d, q);
+  else if (d.in_dt == NRM_BF16) quarter_load<NRM_BF16>(d, q);
+  else quarter_load<NRM_F16>(d, q);
+}
+
+template <int ACC>
+__device__ __forceinline__ void dispatch_quarter_finish(const RowDesc& d, const QuarterHeld& q, float* lse) {
   if constexpr (ACC == ACC_SOFTMAX) {
-    quarter_row<NRM_F32, NRM_F32, ACC>(d, lse);
+    quarter_finish<NRM_F32, NRM_F32, ACC>(d, q, lse);
   } else {
-#define NRM_QR(I, O) quarter_row<I, O, ACC>(d, lse)
+#define NRM_QR(I, O) quarter_finish<I, O, ACC>(d, q, lse)
     switch (d.in_dt * 3 + d.out_dt) {
       case NRM_F32 * 3 + NRM_F32: NRM_QR(NRM_F32, NRM_F32); break;
       case NRM_F32 * 3 + NRM_BF16: NRM_QR(NRM_F32, NRM_BF16); break;
@@ -1178,10 +1213,10 @@ __device__ __forceinline__ void dispatch_quarter(const RowDesc& d, float* lse) {
 // Two static walks, one after the other (their registers are not live at
 // once): wavefront w of W first takes the groups of four consecutive rows
 // 4w, 4(w + W), ..., and runs the group's rows of at most WAVE_QUARTER_MAX
-// elements, each on its 16 lanes, all at once; then it takes rows w, w + W,
-// ... and runs those of WAVE_QUARTER_MAX < n <= wave_max elements on the
-// whole wavefront. Each walk fetches its next descriptors while the current
-// rows stream.
+// elements, each on its 16 lanes, all at once, with the next group's rows
+// loaded before the current group is summed and written; then it takes rows
+// w, w + W, ... and runs those of WAVE_QUARTER_MAX < n <= wave_max elements
+// on the whole wavefront, fetching the next descriptor while a row streams.
 template <int ACC>
 __global__ void __launch_bounds__(WAVE_BLOCK) batch_wave_kernel(BatchArgs a) {
   const int64_t nrows = a.cnt[CNT_ROWS], wmax = a.wave_max;
@@ -1190,19 +1225,31 @@ __global__ void __launch_bounds__(WAVE_BLOCK) batch_wave_kernel(BatchArgs a) {
   const int64_t W = (int64_t)gridDim.x * (WAVE_BLOCK / 64);
   const int64_t w = (int64_t)blockIdx.x * (WAVE_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (4 * w < nrows) {
+    // two groups in flight: the next group's rows are loaded (and the
+    // descriptors of the one after fetched) before the current group is
+    // summed and written
+    const auto quarter = [&](const RowDesc& x) { return x.n > 0 && x.n <= WAVE_QUARTER_MAX && x.n <= wmax; };
+    const auto desc = [&](int64_t r) {
+      RowDesc x;
+      x.n = 0;
+      if (r < nrows) x = a.rows[r];
+      return x;
+    };
     int64_t g = 4 * w;
-    RowDesc d;
-    d.n = 0;
-    if (g + grp < nrows) d = a.rows[g + grp];
+    RowDesc d = desc(g + grp), dn = desc(g + 4 * W + grp);
+    QuarterHeld q;
+    if (quarter(d)) dispatch_quarter_load<ACC>(d, q);
     while (true) {
       const int64_t next = g + 4 * W;
-      RowDesc d_next;
-      d_next.n = 0;
-      if (next + grp < nrows) d_next = a.rows[next + grp];
-      if (d.n > 0 && d.n <= WAVE_QUARTER_MAX && d.n <= wmax) dispatch_quarter<ACC>(d, lse ? lse + g + grp : nullptr);
+      QuarterHeld qn;
+      if (quarter(dn)) dispatch_quarter_load<ACC>(dn, qn);
+      const RowDesc dnn = desc(next + 4 * W + grp);
+      if (quarter(d)) dispatch_quarter_finish<ACC>(d, q, lse ? lse + g + grp : nullptr);
       if (next >= nrows) break;
       g = next;
-      d = d_next;
+      d = dn;
+      dn = dnn;
+      q = qn;
     }
   }
   if (wmax <= WAVE_QUARTER_MAX || w >= nrows) return;

@@ -1006,10 +1006,9 @@ hipError_t phase2_acc(const BatchPlan& p, const BatchArgs& a, hipStream_t s) {
 // in each lane's chains and across the lanes by DPP moves (no LDS, no barrier,
 // no work claim), divided from the registers and written: two HBM transfers,
 // and a wavefront never waits for another. The wavefronts walk the batch's
-// rows statically (wavefront w of W takes rows w, w + W, ...), skip the rows
-// the other kernels take, and fetch the next row's descriptor while the
-// current row streams. A row's summation order depends only on its length,
-// its start alignment and its dtypes.
+// rows statically (batch_wave_kernel below) and skip the rows the other
+// kernels take. A row's summation order depends only on its length, its
+// start alignment and its dtypes.
 template <int DTI, int DTO, int ACC>
 __device__ __forceinline__ void wave_row(const RowDesc& d, float* lse) {
   constexpr int VEC = Elem<DTI>::VEC;

@@ -483,7 +483,8 @@ def bench_short_rows(args):
     and 200,000 rows of lengths log-uniform in [1, 4096] (LogNormal(0,1),
     seed 8), each with the short rows' kernel (the library's default batch
     parameters) and with that path off (short rows as resident segments, one
-    block and one work claim each)."""
+    block and one work claim each). Also timed: the row softmax with
+    log-sum-exp over the same 1,048,576 rows of 256 (N(0, 4) logits)."""
     import numpy as np
     import torch
 
@@ -549,6 +550,29 @@ def bench_short_rows(args):
         others[name] = {"elements": int(xx.size), "median_ms": t_on, "median_ms_wave_path_off": t_off,
                         "GBps_12B": round(12.0 * xx.size / (t_on * 1e-3) / 1e9, 1)}
     t_off_main = run(x, offs, 3, 1, wave_max=0)[1]["median_ms"]
+    # row softmax + log-sum-exp over the same 1,048,576 rows of 256 (N(0, 4) logits)
+    xs = synth.normal_f32(rows * n, 9, 2.0)
+    inp = torch.from_numpy(xs).to(dev)
+    out = torch.empty_like(inp)
+    lse = torch.empty(rows, device=dev)
+    od = torch.from_numpy(offs).to(dev)
+    sctx = api.Context()
+    sctx.set_batch_params(**dict(base, graph=1))
+    sctx.batch_reserve(rows, xs.size)
+    for _ in range(3):
+        api.softmax_batched(out, inp, od, lse=lse, ctx=sctx)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+    ev[0].record(stream)
+    for k in range(10):
+        api.softmax_batched(out, inp, od, lse=lse, ctx=sctx)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    sm_ms = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(10)]))
+    r0 = xs[:n].astype(np.float64)
+    sm_err = float(np.max(np.abs(out[:n].cpu().numpy() - np.exp(r0 - r0.max()) / np.exp(r0 - r0.max()).sum())))
+    sctx.close()
+    del inp, out, lse
     line = {
         "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s",
         "pct_of_peak": round(100.0 * gbs / PEAK_HBM_GBS, 2),
@@ -561,6 +585,8 @@ def bench_short_rows(args):
                    "rows": rows, "elements": total, "batch_params": bp},
         "per_step": per_step,
         "wave_path_off_median_ms": t_off_main,
+        "softmax_1048576x256": {"median_ms": round(sm_ms, 5), "GBps_12B": round(12.0 * total / (sm_ms * 1e-3) / 1e9, 1),
+                                "row0_max_abs_err": sm_err},
         "others": others,
         "sample_max_rel_err": worst,
     }

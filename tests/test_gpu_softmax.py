@@ -211,3 +211,25 @@ def test_full_workload_sampled_rows():
     sums = np.add.reduceat(got.astype(np.float64), offs[:-1])
     assert np.all(np.abs(sums - 1.0) <= 1e-4)
     ctx.close()
+
+
+def test_many_short_rows_split_planner():
+    """20,000 rows of lengths log-uniform in [1, 3000] (room for more than
+    4096 rows: the split planner; rows of at most 256 elements four to a
+    wavefront, up to 2048 one per wavefront, the rest resident): every row
+    and its log-sum-exp against the oracle within the bound."""
+    x, offs = synth.ragged_logits(20000, 57, lo=1, hi=3000, sigma=2.0)
+    got, lse = run(x, offs)
+    check(x, offs, got, lse, "20000 rows")
+
+
+@pytest.mark.parametrize("shift", [0, 3])
+def test_short_rows_at_the_wavefront_limits(shift):
+    """Rows at the limits of the short rows' kernel (one vector per lane of a
+    16-lane row, 256 and 2048 elements, one past each) at two start
+    alignments, with the log-sum-exp."""
+    lengths = [1, 2, 15, 16, 17, 64, 255, 256, 257, 1000, 2047, 2048, 2049, 0, 5]
+    offs = csr(lengths) + shift
+    x = synth.normal_f32(int(offs[-1]), 58 + shift, 3.0)
+    got, lse = run(x, offs)
+    check(x, offs, got, lse, "shift %d" % shift)

@@ -112,6 +112,7 @@ struct BatchArgs {
   // totals here, so that the planner's blocks scan only their own round
   int split_plan;
   int64_t* round_agg;          // [ceil(cap_rows / PLAN_ROUND_ROWS) * 4]
+  BatchHeader* hdr_dev;        // the header, copied to device memory by the counting launch
 };
 
 // The planner takes rows PLAN_ROUND_ROWS at a time (a "round", one block).

@@ -308,14 +308,18 @@ __device__ __forceinline__ RowDesc plan_row(const BatchArgs& a, const BatchHeade
 
 // The split planner's first launch: block b counts round b's tile items,
 // single-pass items, long rows and long-row elements and leaves the totals
-// in round_agg[4 b ..]. Errors are left to the planner, which resolves the
+// in round_agg[4 b ..]; block 0 also copies the header to device memory for
+// the planner's blocks. Errors are left to the planner, which resolves the
 // same rows again.
 __global__ void __launch_bounds__(PLAN_THREADS) batch_count_kernel(BatchArgs a) {
   __shared__ int64_t sc[NCNT][PLAN_WAVES];
   __shared__ BatchHeader hs;
   const int t = threadIdx.x;
   const int64_t own = blockIdx.x;
-  if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
+  if (t == 0) {
+    hs = *a.hdr;  // one read of the header (pinned host memory)
+    if (own == 0) *a.hdr_dev = hs;  // read by the planner after the kernel boundary
+  }
   lds_barrier();
   const int64_t nrows = hs.nrows;
   if (nrows < 0 || nrows > a.cap_rows) return;  // the planner reports it
@@ -346,7 +350,9 @@ __global__ void __launch_bounds__(PLAN_THREADS) batch_plan_kernel(BatchArgs a) {
   __shared__ int32_t ex_short[PLAN_THREADS];
   const int t = threadIdx.x;
   const int64_t own = blockIdx.x;
-  if (t == 0) hs = *a.hdr;  // one read of the header (pinned host memory)
+  // one read of the header: from pinned host memory, or split, from the
+  // counting launch's copy in device memory
+  if (t == 0) hs = SPLIT ? *a.hdr_dev : *a.hdr;
   lds_barrier();
   const BatchHeader* h = &hs;
   const int64_t nrows = h->nrows;

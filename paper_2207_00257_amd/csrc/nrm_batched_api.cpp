@@ -115,8 +115,8 @@ void destroy_graph(BatchWorkspace& w) {
 
 // Layout of the single device allocation.
 struct Layout {
-  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, round_agg, small, partials, tagged, rowtot, arrivals,
-      total;
+  size_t rows, items, lrow_first, lrows, lstart, lsum, chunk_lrow, round_agg, hdr_dev, small, partials, tagged, rowtot,
+      arrivals, total;
 };
 
 // Phase-2 chunks a workspace holds beyond one per item: the planner sizes the
@@ -139,6 +139,7 @@ Layout layout_for(int64_t cap_rows, int64_t cap_items, int64_t cap_chunks) {
   L.lsum = take(sizeof(nrm::RowRes) * cap_rows);
   L.chunk_lrow = take(sizeof(int32_t) * cap_chunks);
   L.round_agg = take(sizeof(int64_t) * 4 * (size_t)ceil_div(cap_rows, nrm::PLAN_ROUND_ROWS));
+  L.hdr_dev = take(sizeof(BatchHeader));
   L.small = take(kSmallBytes);  // the planner's counters, then the error word
   L.partials = take(8 * cap_items);
   L.tagged = take(16 * cap_items);
@@ -208,6 +209,7 @@ int reserve(nrm_ctx* c, int64_t rows, int64_t items) {
   w.lsum = reinterpret_cast<nrm::RowRes*>(d + L.lsum);
   w.chunk_lrow = reinterpret_cast<int32_t*>(d + L.chunk_lrow);
   w.round_agg = reinterpret_cast<int64_t*>(d + L.round_agg);
+  w.hdr_dev = reinterpret_cast<BatchHeader*>(d + L.hdr_dev);
   w.cnt = reinterpret_cast<int64_t*>(d + L.small);
   w.error = reinterpret_cast<int*>(d + L.small + kErrorOffset);
   w.partials = d + L.partials;
@@ -270,6 +272,7 @@ BatchArgs args_of(const nrm_ctx* c, int buf) {
   a.wave_max = c->bparams.wave_max;
   a.split_plan = w.cap_rows > nrm::PLAN_SPLIT_ROWS;
   a.round_agg = w.round_agg;
+  a.hdr_dev = w.hdr_dev;
   return a;
 }
 

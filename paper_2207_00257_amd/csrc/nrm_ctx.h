@@ -65,6 +65,7 @@ struct BatchWorkspace {
   RowRes* lsum = nullptr;
   int32_t* chunk_lrow = nullptr;
   int64_t* round_agg = nullptr;
+  BatchHeader* hdr_dev = nullptr;
   int64_t* cnt = nullptr;
   int* error = nullptr;
   void* partials = nullptr;
